@@ -1,0 +1,379 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own formula: each compares it with a
+library routine (scipy's Sobel, numpy's interp/var/float16, torch's bfloat16,
+scipy's Gaussian density), a closed form, a brute-force enumeration of all
+segmentation labelings, or an invariant EM guarantees.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+RNG = np.random.default_rng(20260)
+
+
+def _params(K, H, W, b, D, beta, ref=None, d_min=0.0, d_step=1.0, **kw):
+    ref = ref if ref is not None else int(np.argmin(np.abs(np.asarray(b))))
+    return O.make_params(K, H, W, ref, b, d_min, d_step, D, beta, **kw)
+
+
+def _random_views(K, H, W, rng=RNG):
+    return rng.integers(0, 256, size=(K, H, W, 3), dtype=np.uint8)
+
+
+def _interp_row(row, u):
+    """Linear interpolation with end clamping (numpy's interp)."""
+    return np.interp(u, np.arange(row.shape[0], dtype=np.float64), row)
+
+
+def _gathered(f, b, y, x, d):
+    """[K][2] descriptors of reference pixel (x, y) at disparity d, via np.interp."""
+    K = f.shape[0]
+    return np.array([[_interp_row(f[k, y, :, c], x - b[k] * d) for c in range(2)] for k in range(K)])
+
+
+# ---------------------------------------------------------------- storage rounding
+
+def test_round_fp16_matches_numpy():
+    vals = np.concatenate([
+        RNG.uniform(-1, 1, 4000),
+        RNG.uniform(0, 1e-4, 500),                      # subnormal range of binary16
+        np.arange(-3060, 3061) / 4096.0,                # every possible descriptor value
+        (np.arange(2049, 4096, 2) + 0.5) / 4096.0,      # exact ties
+    ])
+    ours = np.array([O.round_storage(v, "f16") for v in vals])
+    ref = vals.astype(np.float16).astype(np.float64)
+    assert np.array_equal(ours, ref)
+
+
+def test_round_bf16_matches_torch():
+    torch = pytest.importorskip("torch")
+    vals = np.concatenate([
+        RNG.uniform(-1, 1, 4000).astype(np.float32),
+        (np.arange(-3060, 3061) / 4096.0).astype(np.float32),
+        np.float32(1.0) + np.arange(0, 64).astype(np.float32) * np.float32(2.0 ** -9),  # ties at 1.x
+        RNG.uniform(0, 1, 500).astype(np.float32),
+    ]).astype(np.float32)
+    ours = np.array([O.round_storage(float(v), "bf16") for v in vals])
+    ref = torch.from_numpy(vals).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(ours, ref)
+
+
+# ---------------------------------------------------------------- descriptors
+
+def test_descriptors_match_scipy_sobel():
+    from scipy.ndimage import sobel
+    K, H, W = 3, 17, 23
+    views = _random_views(K, H, W)
+    p = _params(K, H, W, [-1, 0, 1], 4, 100.0)
+    f = O.descriptors(p, views)
+    for k in range(K):
+        L = views[k].astype(np.float64).sum(axis=2)
+        gx = sobel(L, axis=1, mode="nearest") / 4096.0
+        gy = sobel(L, axis=0, mode="nearest") / 4096.0
+        assert np.array_equal(f[k, :, :, 0], gx)
+        assert np.array_equal(f[k, :, :, 1], gy)
+
+
+def test_descriptors_linear_ramp():
+    # L = a x + c y  =>  Gx = 8a, Gy = 8c away from the border (textbook Sobel)
+    H, W, a, c = 12, 20, 3, 5
+    y, x = np.mgrid[0:H, 0:W]
+    L = a * x + c * y
+    views = np.zeros((2, H, W, 3), np.uint8)
+    views[:, :, :, 0] = np.minimum(L, 255)
+    views[:, :, :, 1] = np.clip(L - 255, 0, 255)
+    assert L.max() <= 510
+    p = _params(2, H, W, [0, 1], 4, 100.0)
+    f = O.descriptors(p, views)
+    assert np.all(f[0, 1:-1, 1:-1, 0] * 4096 == 8 * a)
+    assert np.all(f[0, 1:-1, 1:-1, 1] * 4096 == 8 * c)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_descriptors_mirrored_rounding(storage):
+    torch = pytest.importorskip("torch")
+    K, H, W = 2, 9, 31
+    # high-contrast columns: many |G| above 2048, where binary16 must round
+    hi = RNG.integers(0, 2, size=(K, 1, W, 1)) * 235
+    views = (hi + RNG.integers(0, 21, size=(K, H, W, 3))).astype(np.uint8)
+    exact = O.descriptors(_params(K, H, W, [0, 1], 4, 100.0), views)
+    low = O.descriptors(_params(K, H, W, [0, 1], 4, 100.0, storage=storage), views)
+    if storage == "f16":
+        ref = exact.astype(np.float16).astype(np.float64)
+    else:
+        ref = torch.from_numpy(exact.astype(np.float32)).to(torch.bfloat16).double().numpy()
+    assert np.array_equal(low, ref)
+    assert not np.array_equal(low, exact)      # the rounding is really applied
+
+
+# ---------------------------------------------------------------- ray prior
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_ray_prior_is_interp_of_SP(storage):
+    K, H, W = 3, 6, 40
+    b = [-1.5, 0.0, 2.0]
+    S_P = RNG.uniform(0, 1, (K, H, W)).astype(np.float32)
+    mu = RNG.uniform(-3, 12, (H, W)).astype(np.float32)
+    p = _params(K, H, W, b, 8, 100.0, ref=1, storage=storage)
+    rho, q0 = O.ray_prior(p, S_P, mu)
+    sp = S_P.astype(np.float16).astype(np.float64) if storage == "f16" else S_P.astype(np.float64)
+    for k in range(K):
+        for y in range(H):
+            want = _interp_row(sp[k, y], np.arange(W) - b[k] * mu[y].astype(np.float64))
+            np.testing.assert_allclose(rho[k, y], want, rtol=0, atol=1e-15)
+    assert np.array_equal(q0, (rho >= 0.7).astype(np.float64))
+
+
+# ---------------------------------------------------------------- likelihood constant
+
+def test_lambda_is_gaussian_over_uniform_density():
+    from scipy.stats import multivariate_normal
+    for K, beta in [(5, 2133.0), (9, 75000.0), (3, 10.0)]:
+        p = _params(K, 4, 4, list(range(K)), 4, beta, ref=0)
+        bp = beta / K
+        gauss_peak = multivariate_normal(mean=[0, 0], cov=np.eye(2) / (2 * bp)).pdf([0, 0])
+        uniform = 1.0 / (2 * 3060 / 4096) ** 2
+        assert math.isclose(O.derive_lambda(p), math.log(gauss_peak / uniform), rel_tol=1e-12)
+
+
+# ---------------------------------------------------------------- M-step
+
+def _energies_from_variance(f, b, y, x, levels, beta, gamma, sigma, mu):
+    """All-static energies: beta * (population variance over views, summed over features)."""
+    E = []
+    for d in levels:
+        g = _gathered(f, b, y, x, d)
+        var = np.var(g, axis=0).sum()
+        E.append(beta * var + math.log1p(gamma) - math.log(gamma + math.exp(-(d - mu) ** 2 / (2 * sigma ** 2))))
+    return np.array(E)
+
+
+@pytest.mark.parametrize("d_step", [1.0, 0.5, 0.75])
+def test_mstep_all_static_is_beta_times_variance(d_step):
+    K, H, W, D = 4, 5, 30, 9
+    b = [0.0, 1.0, 2.0, -1.0]
+    views = _random_views(K, H, W)
+    mu = RNG.uniform(0, 6, (H, W)).astype(np.float32)
+    p = _params(K, H, W, b, D, 300.0, ref=0, d_min=-1.0, d_step=d_step)
+    f = O.descriptors(p, views)
+    rho = np.ones((K, H, W))
+    out = O.em_iteration(p, f, rho, mu, np.ones((K, H, W)))
+    levels = -1.0 + d_step * np.arange(D)
+    for y in range(H):
+        for x in range(W):
+            E = _energies_from_variance(f, b, y, x, levels, 300.0, 0.05, 2.0, float(mu[y, x]))
+            assert out["d_idx"][y, x] == int(np.argmin(E))
+            srt = np.sort(E)
+            assert math.isclose(out["E1"][y, x], srt[0], rel_tol=1e-11, abs_tol=1e-11)
+            assert math.isclose(out["E2"][y, x], srt[1], rel_tol=1e-11, abs_tol=1e-11)
+
+
+def test_mstep_weighted_matches_pairwise_form():
+    # sum_k q_k |f_k - m|^2 = (1/2Q) sum_k sum_l q_k q_l |f_k - f_l|^2
+    K, H, W, D = 5, 4, 26, 7
+    b = [-2.0, -1.0, 0.0, 1.0, 2.0]
+    views = _random_views(K, H, W)
+    mu = RNG.uniform(0, 6, (H, W)).astype(np.float32)
+    q = RNG.uniform(0, 1, (K, H, W))
+    q[:, 0, :3] = 0.0                       # no weight at all: the prior decides
+    beta, gamma, sigma = 800.0, 0.05, 2.0
+    p = _params(K, H, W, b, D, beta, ref=2)
+    f = O.descriptors(p, views)
+    out = O.em_iteration(p, f, np.full((K, H, W), 0.5), mu, q)
+    for y in range(H):
+        for x in range(W):
+            E = []
+            for j in range(D):
+                g = _gathered(f, b, y, x, float(j))
+                w = q[:, y, x]
+                Q = w.sum()
+                diff = ((g[:, None, :] - g[None, :, :]) ** 2).sum(-1)
+                C = (w[:, None] * w[None, :] * diff).sum() / (2 * Q) if Q > 0 else 0.0
+                E.append(beta / K * C + math.log1p(gamma)
+                         - math.log(gamma + math.exp(-(j - float(mu[y, x])) ** 2 / (2 * sigma ** 2))))
+            E = np.array(E)
+            assert out["d_idx"][y, x] == int(np.argmin(E))
+            assert math.isclose(out["E1"][y, x], E.min(), rel_tol=1e-10, abs_tol=1e-10)
+
+
+def test_mstep_beta_zero_picks_level_nearest_prior():
+    K, H, W, D = 3, 4, 20, 16
+    views = _random_views(K, H, W)
+    mu = RNG.uniform(-2, 10, (H, W)).astype(np.float32)
+    mu[0, 0] = 2.25    # exact tie between levels 2.0 and 2.5 -> the lower level
+    p = _params(K, H, W, [0, 1, 2], D, 0.0, ref=0, lam=0.0, d_min=-1.0, d_step=0.5)
+    f = O.descriptors(p, views)
+    out = O.em_iteration(p, f, np.full((K, H, W), 0.5), mu, RNG.uniform(0, 1, (K, H, W)))
+    levels = -1.0 + 0.5 * np.arange(D)
+    want = np.argmin(np.abs(levels[None, None, :] - mu[..., None].astype(np.float64)), axis=-1)
+    assert np.array_equal(out["d_idx"], want)
+    assert out["d_idx"][0, 0] == 6
+
+
+def test_mstep_recovers_fronto_parallel_plane():
+    # a textured plane at integer disparity d0, asymmetric baselines: the sign
+    # and scale of the shift are fixed by recovering d0 exactly
+    K, H, W, D, d0 = 3, 10, 80, 12, 5
+    b = [0.0, 1.0, 3.0]
+    rng = np.random.default_rng(7)
+    tex = rng.integers(0, 256, size=(H, W + 3 * D + 2, 3), dtype=np.uint8)
+    views = np.empty((K, H, W, 3), np.uint8)
+    xs = np.arange(W)
+    for k in range(K):
+        views[k] = tex[:, xs + int(b[k] * d0)]      # view k pixel x sees u = x + b_k d0
+    mu = np.full((H, W), 6.0, np.float32)           # prior off by one level
+    p = _params(K, H, W, b, D, 2133.0, ref=0, sigma=4.0)
+    f = O.descriptors(p, views)
+    out = O.em_iteration(p, f, np.ones((K, H, W)), mu, np.ones((K, H, W)))
+    # view k samples x - b_k d: columns below 3*d0 (+1 for the Sobel) fall outside view 3
+    assert np.all(out["d_idx"][:, 3 * d0 + 1:W - 1] == d0)
+
+
+# ---------------------------------------------------------------- E-step
+
+def _enumerate(rho, lam, bp, e):
+    """Joint over all 2^K labelings: marginals P(S_k=1), MAP labeling, log sum, log max."""
+    K = len(rho)
+    tot, best, best_S = 0.0, -1.0, None
+    marg = np.zeros(K)
+    for S in itertools.product([0, 1], repeat=K):
+        p = 1.0
+        for k in range(K):
+            p *= rho[k] * math.exp(lam - bp * e[k]) if S[k] else (1.0 - rho[k])
+        tot += p
+        marg += p * np.array(S)
+        if p > best:
+            best, best_S = p, S
+    return marg / tot, np.array(best_S, float), math.log(tot), math.log(best)
+
+
+@pytest.mark.parametrize("mode", ["soft", "hard"])
+def test_estep_and_objective_match_enumeration(mode):
+    K, H, W, D = 4, 3, 18, 6
+    b = [-1.0, 0.0, 1.0, 2.0]
+    views = _random_views(K, H, W)
+    mu = RNG.uniform(0, 5, (H, W)).astype(np.float32)
+    beta, lam, gamma, sigma = 60.0, 1.3, 0.05, 2.0
+    p = _params(K, H, W, b, D, beta, ref=1, lam=lam, mode=mode)
+    f = O.descriptors(p, views)
+    rho = RNG.uniform(0.02, 0.98, (K, H, W))
+    q_in = RNG.uniform(0, 1, (K, H, W))
+    out = O.em_iteration(p, f, rho, mu, q_in)
+    for y in range(H):
+        for x in range(W):
+            d = float(out["d_idx"][y, x])
+            g = _gathered(f, b, y, x, d)
+            m = np.average(g, axis=0, weights=q_in[:, y, x])
+            e = ((g - m) ** 2).sum(axis=1)
+            marg, S_map, log_sum, log_max = _enumerate(rho[:, y, x], lam, beta / K, e)
+            prior = math.log(gamma + math.exp(-(d - float(mu[y, x])) ** 2 / (2 * sigma ** 2)))
+            if mode == "soft":
+                np.testing.assert_allclose(out["q"][:, y, x], marg, rtol=1e-11, atol=1e-13)
+                assert math.isclose(out["L"][y, x], prior + log_sum, rel_tol=1e-11)
+            else:
+                assert np.array_equal(out["q"][:, y, x], S_map)
+                assert math.isclose(out["L"][y, x], prior + log_max, rel_tol=1e-11)
+
+
+def test_estep_certain_priors_are_kept():
+    K, H, W = 3, 2, 10
+    views = _random_views(K, H, W)
+    p = _params(K, H, W, [0, 1, 2], 5, 500.0, ref=0)
+    f = O.descriptors(p, views)
+    rho = RNG.integers(0, 2, (K, H, W)).astype(np.float64)
+    rho[:, 0, 0] = 0.0                       # no static view at all
+    out = O.em_iteration(p, f, rho, np.zeros((H, W), np.float32), np.ones((K, H, W)))
+    assert np.array_equal(out["q"], rho)
+    assert np.all(np.isfinite(out["L"]))
+
+
+def test_estep_beta_zero_is_logistic_prior():
+    from scipy.special import expit, logit
+    K, H, W = 3, 3, 12
+    views = _random_views(K, H, W)
+    lam = 0.7
+    p = _params(K, H, W, [0, 1, 2], 5, 0.0, ref=0, lam=lam)
+    f = O.descriptors(p, views)
+    rho = RNG.uniform(0.01, 0.99, (K, H, W))
+    out = O.em_iteration(p, f, rho, np.zeros((H, W), np.float32), np.ones((K, H, W)))
+    np.testing.assert_allclose(out["q"], expit(logit(rho) + lam), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- EM loop
+
+@pytest.mark.parametrize("mode", ["soft", "hard"])
+def test_em_objective_never_decreases(mode):
+    K, H, W, D = 5, 12, 48, 16
+    rng = np.random.default_rng(3)
+    views = rng.integers(0, 256, size=(K, H, W, 3), dtype=np.uint8)
+    S_P = rng.uniform(0, 1, (K, H, W)).astype(np.float32)
+    mu = rng.uniform(0, 15, (H, W)).astype(np.float32)
+    p = _params(K, H, W, [-2, -1, 0, 1, 2], D, 500.0, ref=2, mode=mode)
+    f = O.descriptors(p, views)
+    rho, q = O.ray_prior(p, S_P, mu)
+    prev = None
+    for t in range(6):
+        out = O.em_iteration(p, f, rho, mu, q)
+        if prev is not None:
+            assert np.all(out["L"] >= prev - 1e-9 * np.maximum(1.0, np.abs(prev)))
+        prev, q = out["L"], out["q"]
+        assert np.all((q >= 0) & (q <= 1))
+
+
+# ---------------------------------------------------------------- refocus
+
+def test_refocus_all_static_is_plain_mean():
+    K, H, W = 4, 5, 25
+    b = [0.0, 1.0, -1.0, 2.5]
+    views = _random_views(K, H, W)
+    p = _params(K, H, W, b, 10, 100.0, ref=0, d_step=0.5)
+    d_idx = RNG.integers(0, 10, (H, W)).astype(np.int32)
+    rgb, hole = O.refocus(p, views, d_idx, np.ones((K, H, W)))
+    assert not hole.any()
+    for y in range(H):
+        for x in range(W):
+            d = 0.5 * d_idx[y, x]
+            want = np.mean([[_interp_row(views[k, y, :, c].astype(float), x - b[k] * d) for c in range(3)]
+                            for k in range(K)], axis=0) / 255.0
+            np.testing.assert_allclose(rgb[y, x], want, rtol=0, atol=1e-14)
+
+
+def test_refocus_one_none_and_half():
+    K, H, W = 3, 2, 9
+    views = _random_views(K, H, W)
+    p = _params(K, H, W, [0.0, 1.0, 2.0], 4, 100.0, ref=0)
+    d_idx = np.full((H, W), 1, np.int32)
+    q = np.zeros((K, H, W))
+    q[2, 0, :] = 0.5                          # exactly 0.5 counts as static
+    rgb, hole = O.refocus(p, views, d_idx, q)
+    for x in range(W):
+        assert np.array_equal(rgb[0, x], views[2, 0, max(x - 2, 0)] / 255.0)
+        assert hole[0, x] == 0
+        assert np.array_equal(rgb[1, x], views[0, 1, x] / 255.0)   # none static: reference pixel
+        assert hole[1, x] == 1
+
+
+def test_threshold_start_counts_tau_as_static():
+    # S_P exactly at tau at integer footprints: the ray starts static (S_P >= tau)
+    K, H, W = 3, 2, 12
+    S_P = np.full((K, H, W), 0.5, np.float32)
+    S_P[:, 1, :] = np.nextafter(np.float32(0.5), np.float32(0))
+    p = _params(K, H, W, [0, 1, 2], 4, 100.0, ref=0, tau=0.5)
+    rho, q0 = O.ray_prior(p, S_P, np.full((H, W), 2.0, np.float32))
+    assert np.all(q0[:, 0] == 1.0) and np.all(q0[:, 1] == 0.0)
+
+
+def test_hard_assignment_tie_is_static():
+    # identical flat views: e_k = 0; rho = 1/2 and lambda = 0 make a1 == a0
+    K, H, W = 3, 2, 8
+    views = np.full((K, H, W, 3), 100, np.uint8)
+    p = _params(K, H, W, [0, 1, 2], 4, 100.0, ref=0, lam=0.0, mode="hard")
+    f = O.descriptors(p, views)
+    out = O.em_iteration(p, f, np.full((K, H, W), 0.5), np.zeros((H, W), np.float32), np.ones((K, H, W)))
+    assert np.all(out["q"] == 1.0)
+    np.testing.assert_allclose(out["L"], math.log(1.05) + K * math.log(0.5), rtol=1e-14)
