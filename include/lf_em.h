@@ -1,0 +1,183 @@
+/*
+ * lf_em.h -- C ABI of the MI355X (gfx950) implementation of the EM static-
+ * background reconstruction with a rectified linear camera array
+ * (Kaveti, Katt and Singh, "Removing Dynamic Objects for Static Scene
+ * Reconstruction using Light Fields", 2020).
+ *
+ * Problem (Sec. III-A, III-B): K rectified views I_k of a horizontal camera
+ * array, the per-view semantic segmentation prior S_P (probability that a
+ * pixel is static; S_P = 0 means dynamic) and a dense prior disparity map mu_T
+ * interpolated from a triangulation T.  For every pixel of the reference view
+ * the library estimates the static-background disparity d (M-step, Sec. III-C,
+ * Eq. 6), the posterior q_k that the ray into view k is static (E-step,
+ * Sec. III-D, Eq. 7) and the refocused image of the static scene (Eq. 2).
+ *
+ * Conventions shared by every entry point:
+ *   - View k is sampled at x - baselines[k] * d on the same row (Eq. 1 for a
+ *     rectified linear array), with linear interpolation along x for
+ *     non-integral positions and indices clamped to the image.
+ *   - Disparity levels are d_j = d_min + j * d_step, j = 0..D-1.
+ *   - Layouts are C order: views uint8 [K][H][W][3] (RGB), S_P float
+ *     [K][H][W], mu_T float [H][W], q float [K][H][W], d_idx int32 [H][W]
+ *     (level index j), rgb float [H][W][3] in [0,1], hole uint8 [H][W].
+ *   - Pointers are host memory unless the flags say device memory
+ *     (LF_INPUTS_ON_DEVICE for inputs, LF_OUTPUTS_ON_DEVICE for outputs).
+ *   - Every call returns a status code; no exception crosses the ABI.  On an
+ *     error lf_last_error() describes it (thread-local, valid until the next
+ *     call on the same thread).
+ *   - All descriptor, likelihood and posterior arithmetic is FP32 on the GPU;
+ *     `storage` only sets the precision in which descriptors and S_P are held
+ *     (values are rounded once, to nearest even).
+ */
+#ifndef LF_EM_H
+#define LF_EM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lf_status;
+#define LF_OK       0
+#define LF_EINVAL   1   /* invalid argument; nothing was launched                    */
+#define LF_ENOMEM   2   /* device memory (or the server's HBM budget) exhausted      */
+#define LF_EDEVICE  3   /* HIP runtime error or device-side failure                  */
+#define LF_EAGAIN   4   /* server queue full; retry later                            */
+#define LF_ESTATE   5   /* call out of order (e.g. refocus before any iteration)     */
+
+#define LF_MAX_VIEWS 16
+
+/* Storage precision of descriptors and S_P (arithmetic is always FP32). */
+#define LF_F32   0
+#define LF_F16   1
+#define LF_BF16  2
+
+/* E-step form: SOFT = posterior P(S_k = 1); HARD = the arg max labeling
+ * (the paper's delta / hard assignment, Sec. III-C and III-D). */
+#define LF_SOFT  0
+#define LF_HARD  1
+
+/* flags */
+#define LF_INPUTS_ON_DEVICE   0x1u  /* views, S_P, mu_T, q_warm are device pointers   */
+#define LF_OUTPUTS_ON_DEVICE  0x2u  /* rgb, d_idx, q, hole, L_pix are device pointers  */
+
+typedef struct {
+    int32_t K, H, W;            /* views, rows, columns; 2 <= K <= 16                 */
+    int32_t ref;                /* reference view, baselines[ref] must be 0 (Sec. III-F) */
+    float baselines[LF_MAX_VIEWS]; /* view k samples x - baselines[k] * d              */
+    float d_min, d_step;        /* disparity levels d_j = d_min + j * d_step, d_step > 0 */
+    int32_t D;                  /* number of levels, D >= 1                           */
+    float beta;                 /* likelihood sharpness beta >= 0 (Sec. III-C)         */
+    float lambda;               /* log ratio static/dynamic likelihood normalisers;   */
+                                /* NaN: derived as ln(beta'/pi) + 2 ln(2R),            */
+                                /* beta' = beta/K, R = 3060/4096 (needs beta > 0)      */
+    float gamma, sigma;         /* disparity prior ln(gamma + exp(-(d-mu)^2/(2 sigma^2))) */
+    float tau_init;             /* first-iteration threshold: static iff rho >= tau (0.7) */
+    int32_t storage;            /* LF_F32, LF_F16, LF_BF16                            */
+    int32_t mode;               /* LF_SOFT, LF_HARD                                   */
+    uint32_t flags;             /* LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE         */
+} lf_params;
+
+typedef struct lf_ctx lf_ctx;   /* opaque; owns all device buffers of one frame shape */
+
+/*
+ * lf_em_init -- create a context for frames of shape (K, H, W) and load the
+ * first frame: descriptors (3x3 Sobel responses of R+G+B, Sec. III-C), the ray
+ * prior rho_k = S_P of view k at the footprint x - b_k mu_T, and the first
+ * weights q0_k = [rho_k >= tau_init] (Sec. III-F) or q_warm when given.
+ *   out     : receives the context (NULL on failure).
+ *   p       : parameters, copied.
+ *   views   : uint8 [K][H][W][3]; S_P float [K][H][W] in [0,1];
+ *             mu_T float [H][W] finite; q_warm float [K][H][W] in [0,1] or NULL.
+ *   hip_stream : hipStream_t all work of this context is queued on (NULL is
+ *             the device's null stream); the caller keeps it alive until
+ *             lf_em_destroy.
+ * Host inputs are copied before return (the caller may free them).  Device
+ * inputs must stay valid until the next lf_em_load or lf_em_destroy.
+ * Errors: LF_EINVAL (checked before any device work: K outside [2,16], H or W
+ * < 1, ref out of range, baselines[ref] != 0, non-finite baselines, D < 1,
+ * d_step <= 0, beta < 0, lambda NaN with beta == 0, gamma <= 0, sigma <= 0,
+ * tau_init outside [0,1], bad storage/mode/flags, max |baseline * level|
+ * above 1e6, S_P outside [0,1] or NaN, mu_T not finite or |mu_T| above 1e6,
+ * q_warm outside [0,1]; a disparity halo too wide for one workgroup's LDS);
+ * LF_ENOMEM; LF_EDEVICE.  Value checks of device-resident inputs run on the
+ * device before the frame counts as loaded (one stream synchronisation).
+ */
+lf_status lf_em_init(lf_ctx **out, const lf_params *p, const uint8_t *views, const float *S_P,
+                     const float *mu_T, const float *q_warm, void *hip_stream);
+
+/*
+ * lf_em_load -- load a new frame of the same shape and parameters into an
+ * existing context (no allocation): recomputes descriptors, ray prior and the
+ * first weights exactly as lf_em_init does, and resets the iteration count.
+ * Arguments and errors as lf_em_init.
+ */
+lf_status lf_em_load(lf_ctx *c, const uint8_t *views, const float *S_P, const float *mu_T,
+                     const float *q_warm);
+
+/*
+ * lf_em_iterate -- run n_iters EM iterations (each an M-step followed by an
+ * E-step, the M-step first, Sec. III-B) on the current state.
+ *   objective : NULL, or host double [n_iters] receiving the frame objective
+ *               sum_p L_t(p) after each iteration, L_t(p) = ln(gamma +
+ *               exp(-(d_t-mu)^2/(2 sigma^2))) + sum_k logaddexp(a1_k, a0_k)
+ *               (SOFT) or sum_k max(a1_k, a0_k) (HARD); summed in FP64.
+ *               With NULL the call only queues work and returns.
+ * iterate(a) followed by iterate(b) gives bit-identical state to iterate(a+b).
+ * Errors: LF_EINVAL (n_iters < 0), LF_ESTATE (no frame loaded), LF_EDEVICE.
+ */
+lf_status lf_em_iterate(lf_ctx *c, int32_t n_iters, double *objective);
+
+/*
+ * lf_refocus -- refocused image of the static scene at the current disparity
+ * (Eq. 2): the mean of the views whose posterior is q_k >= 0.5, each sampled
+ * at x - b_k d.  Where no view is static the reference pixel is kept and
+ * hole = 1 (Sec. IV-B).  Also returns the state.
+ *   rgb    : float [H][W][3] in [0,1] (required).
+ *   d_idx  : int32 [H][W] level indices, or NULL.
+ *   q      : float [K][H][W] posteriors, or NULL.
+ *   hole   : uint8 [H][W], or NULL.
+ *   median : 0, or 3 for a 3x3 per-channel median of rgb (Sec. III-E); the
+ *            median is applied to every pixel, holes included.
+ * Host outputs are complete on return; device outputs are complete when the
+ * context's stream reaches this point.
+ * Errors: LF_EINVAL (rgb NULL, median not 0 or 3), LF_ESTATE (no iteration
+ * since the last load), LF_EDEVICE.
+ */
+lf_status lf_refocus(lf_ctx *c, float *rgb, int32_t *d_idx, float *q, uint8_t *hole, int32_t median);
+
+/*
+ * lf_em_state -- copy out the current state without refocusing.
+ *   q      : float [K][H][W] current weights (q0 before the first iteration), or NULL.
+ *   d_idx  : int32 [H][W] disparity levels of the last iteration, or NULL.
+ *   L_pix  : float [H][W] per-pixel objective L_t(p) of the last iteration, or NULL.
+ * Errors: LF_ESTATE (d_idx or L_pix requested before any iteration), LF_EDEVICE.
+ */
+lf_status lf_em_state(lf_ctx *c, float *q, int32_t *d_idx, float *L_pix);
+
+/*
+ * lf_em_intermediates -- copy out the current frame's per-view inputs to the
+ * EM iterations.
+ *   feat : [K][H][W][2] descriptors (Gx, Gy) * 2^-12 of the 3x3 Sobel
+ *          responses of R+G+B (Sec. III-C), in the storage precision: float
+ *          for LF_F32, IEEE binary16 for LF_F16, bfloat16 for LF_BF16
+ *          (8 or 4 bytes per pixel), or NULL.
+ *   rho  : float [K][H][W] ray prior, S_P of view k (rounded to the storage
+ *          precision) interpolated at x - b_k mu_T (Sec. III-B), or NULL.
+ * Errors: LF_ESTATE (no frame loaded), LF_EDEVICE.
+ */
+lf_status lf_em_intermediates(lf_ctx *c, void *feat, float *rho);
+
+/* lf_em_destroy -- wait for the context's work, free it.  NULL is a no-op. */
+void lf_em_destroy(lf_ctx *c);
+
+/* lf_last_error -- message of the last failing call on this thread ("" if none). */
+const char *lf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LF_EM_H */

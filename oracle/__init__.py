@@ -11,6 +11,7 @@ Every function follows the paper (Kaveti, Katt and Singh, 2020):
   em_iteration -> Sec. III-B (EM schedule, M-step first), Sec. III-C (E(d), Eq. 6),
                   Sec. III-D (segmentation posterior, Eq. 7)
   refocus      -> Eq. 2 (static rays only) and Sec. IV-B (no static ray: keep the pixel)
+  median3      -> Sec. III-E (median filter against the refocus' specular noise)
 """
 from __future__ import annotations
 
@@ -86,6 +87,7 @@ def lib():
         L.lfo_reconstruct.argtypes = [P, u8, fp, fp, dp, i32, i32, i32, dp, dp, dp, dp, i32p, dp, dp, dp, u8]
         L.lfo_reconstruct.restype = i32
         L.lfo_threads.restype = i32
+        L.lfo_median3.argtypes = [P, dp, dp, i32, i32]
         _lib = L
     return _lib
 
@@ -162,6 +164,15 @@ def refocus(p: Params, views, d_idx, q, rows=None):
     lib().lfo_refocus(ctypes.byref(p), _ptr(v, ctypes.c_uint8), _ptr(d, ctypes.c_int32),
                       _ptr(q, ctypes.c_double), _ptr(rgb, ctypes.c_double), _ptr(hole, ctypes.c_uint8), y0, y1)
     return rgb, hole
+
+
+def median3(p: Params, rgb, rows=None):
+    """3x3 per-channel median with replicated border, [H][W][3] float64."""
+    src = _c(rgb, np.float64)
+    out = np.zeros((p.H, p.W, 3))
+    y0, y1 = _rows(p, rows)
+    lib().lfo_median3(ctypes.byref(p), _ptr(src, ctypes.c_double), _ptr(out, ctypes.c_double), y0, y1)
+    return out
 
 
 def reconstruct(p: Params, views, S_P, mu_T, n_iters, q_warm=None, rows=None) -> dict:

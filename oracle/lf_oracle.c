@@ -132,6 +132,11 @@ void lfo_descriptors(const lfo_params *p, const uint8_t *views, double *f, int32
         }
 }
 
+/* Linear interpolation between a (t = 0) and b (t = 1), in the form that is
+ * exact when a == b: a certain prior (S_P exactly 0 or 1 on both sides)
+ * stays certain. */
+static double lerp(double a, double b, double t) { return a + t * (b - a); }
+
 /* Sample a row at real position u: linear interpolation, indices clamped.   */
 static double sample_row(const double *row, int W, int stride, double u)
 {
@@ -139,7 +144,7 @@ static double sample_row(const double *row, int W, int stride, double u)
     double t = u - fl;
     int i0 = clampi((int)fl, 0, W - 1);
     int i1 = clampi((int)fl + 1, 0, W - 1);
-    return (1.0 - t) * row[(size_t)i0 * stride] + t * row[(size_t)i1 * stride];
+    return lerp(row[(size_t)i0 * stride], row[(size_t)i1 * stride], t);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -300,7 +305,7 @@ void lfo_refocus(const lfo_params *p, const uint8_t *views, const int32_t *d_idx
                 for (int c = 0; c < 3; ++c) {
                     double fl = floor(u), t = u - fl;
                     int i0 = clampi((int)fl, 0, W - 1), i1 = clampi((int)fl + 1, 0, W - 1);
-                    acc[c] += (1.0 - t) * (double)vr[(size_t)i0 * 3 + c] + t * (double)vr[(size_t)i1 * 3 + c];
+                    acc[c] += lerp((double)vr[(size_t)i0 * 3 + c], (double)vr[(size_t)i1 * 3 + c], t);
                 }
                 ++n;
             }
@@ -368,4 +373,31 @@ int32_t lfo_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3x3 per-channel median of the refocused image, replicated border: the     */
+/* filter that removes the specular noise of the pixel-wise refocus          */
+/* (Sec. III-E).  rgb and out are [H][W][3].                                 */
+/* ------------------------------------------------------------------------ */
+
+void lfo_median3(const lfo_params *p, const double *rgb, double *out, int32_t y0, int32_t y1)
+{
+    const int H = p->H, W = p->W;
+#pragma omp parallel for schedule(static)
+    for (int y = y0; y < y1; ++y)
+        for (int x = 0; x < W; ++x)
+            for (int c = 0; c < 3; ++c) {
+                double v[9];
+                int n = 0;
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int yy = clampi(y + dy, 0, H - 1), xx = clampi(x + dx, 0, W - 1);
+                        double a = rgb[((size_t)yy * W + xx) * 3 + c];
+                        int i = n++;
+                        while (i > 0 && v[i - 1] > a) { v[i] = v[i - 1]; --i; }
+                        v[i] = a;
+                    }
+                out[((size_t)y * W + x) * 3 + c] = v[4];
+            }
 }

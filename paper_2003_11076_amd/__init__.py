@@ -1,0 +1,163 @@
+"""MI355X (gfx950) EM static-background reconstruction for a linear camera array.
+
+Thin ctypes binding of the C ABI in ``include/lf_em.h`` (``liblfem.so``, built
+in-tree by ``python -m paper_2003_11076_amd.build``).  The functions keep the C
+names and only marshal arguments: every step of the method runs in the HIP
+kernels of the library.  Array arguments may be numpy arrays (host memory),
+torch tensors (their device or host memory, by ``data_ptr``), raw integer
+addresses, or None where the C function accepts NULL.  A status other than
+LF_OK raises :class:`LFError` carrying the code and ``lf_last_error()``.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblfem.so")
+
+LF_OK, LF_EINVAL, LF_ENOMEM, LF_EDEVICE, LF_EAGAIN, LF_ESTATE = 0, 1, 2, 3, 4, 5
+STATUS_NAMES = {0: "LF_OK", 1: "LF_EINVAL", 2: "LF_ENOMEM", 3: "LF_EDEVICE", 4: "LF_EAGAIN", 5: "LF_ESTATE"}
+LF_MAX_VIEWS = 16
+LF_F32, LF_F16, LF_BF16 = 0, 1, 2
+LF_SOFT, LF_HARD = 0, 1
+LF_INPUTS_ON_DEVICE, LF_OUTPUTS_ON_DEVICE = 0x1, 0x2
+STORAGE = {"f32": LF_F32, "f16": LF_F16, "bf16": LF_BF16}
+
+
+class LFError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class lf_params(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32), ("ref", ctypes.c_int32),
+        ("baselines", ctypes.c_float * LF_MAX_VIEWS),
+        ("d_min", ctypes.c_float), ("d_step", ctypes.c_float), ("D", ctypes.c_int32),
+        ("beta", ctypes.c_float), ("lambda_", ctypes.c_float), ("gamma", ctypes.c_float),
+        ("sigma", ctypes.c_float), ("tau_init", ctypes.c_float),
+        ("storage", ctypes.c_int32), ("mode", ctypes.c_int32), ("flags", ctypes.c_uint32),
+    ]
+
+
+def make_params(K, H, W, ref, baselines, d_min, d_step, D, beta, lam=float("nan"), gamma=0.05, sigma=2.0,
+                tau_init=0.7, storage="f32", mode="soft", flags=0) -> lf_params:
+    p = lf_params()
+    p.K, p.H, p.W, p.ref = int(K), int(H), int(W), int(ref)
+    for k, b in enumerate(baselines):
+        p.baselines[k] = float(b)
+    p.d_min, p.d_step, p.D = float(d_min), float(d_step), int(D)
+    p.beta, p.lambda_, p.gamma, p.sigma, p.tau_init = float(beta), float(lam), float(gamma), float(sigma), float(tau_init)
+    p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p.mode = {"soft": LF_SOFT, "hard": LF_HARD}[mode] if isinstance(mode, str) else int(mode)
+    p.flags = int(flags)
+    return p
+
+
+_lib = None
+
+
+def lib():
+    """The loaded liblfem.so.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2003_11076_amd.build` "
+                              "(the HIP library is required; there is no fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, P = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(lf_params)
+        L.lf_em_init.argtypes = [ctypes.POINTER(vp), P, vp, vp, vp, vp, vp]
+        L.lf_em_load.argtypes = [vp, vp, vp, vp, vp]
+        L.lf_em_iterate.argtypes = [vp, i32, vp]
+        L.lf_refocus.argtypes = [vp, vp, vp, vp, vp, i32]
+        L.lf_em_state.argtypes = [vp, vp, vp, vp]
+        L.lf_em_intermediates.argtypes = [vp, vp, vp]
+        L.lf_em_destroy.argtypes = [vp]
+        L.lf_em_destroy.restype = None
+        L.lf_last_error.restype = ctypes.c_char_p
+        for f in ("lf_em_init", "lf_em_load", "lf_em_iterate", "lf_refocus", "lf_em_state", "lf_em_intermediates"):
+            getattr(L, f).restype = i32
+        _bind_server(L)
+        _lib = L
+    return _lib
+
+
+def _bind_server(L):
+    if not hasattr(L, "lf_server_create"):
+        return
+    vp, i32, P = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(lf_params)
+    L.lf_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, i32, i32, vp]
+    L.lf_submit_frame.argtypes = [vp, i32, P, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]
+    L.lf_server_poll.argtypes = [vp, ctypes.POINTER(i32)]
+    L.lf_server_drain.argtypes = [vp]
+    L.lf_server_stats.argtypes = [vp, vp]
+    L.lf_server_destroy.argtypes = [vp]
+    L.lf_server_destroy.restype = None
+    for f in ("lf_server_create", "lf_submit_frame", "lf_server_poll", "lf_server_drain", "lf_server_stats"):
+        getattr(L, f).restype = i32
+
+
+def last_error() -> str:
+    return lib().lf_last_error().decode()
+
+
+lf_last_error = last_error
+
+
+def _check(status):
+    if status != LF_OK:
+        raise LFError(status, last_error())
+    return status
+
+
+def addr(x):
+    """Address of an array argument (numpy, torch, int) or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):          # torch tensor
+        if not x.is_contiguous():
+            raise ValueError("tensor arguments must be contiguous")
+        return x.data_ptr()
+    if hasattr(x, "ctypes"):            # numpy array
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array arguments must be C-contiguous")
+        return x.ctypes.data
+    raise TypeError(f"cannot pass {type(x)!r} as an array")
+
+
+def lf_em_init(p: lf_params, views, S_P, mu_T, q_warm=None, hip_stream=None) -> int:
+    """Returns the context handle (an int)."""
+    out = ctypes.c_void_p()
+    _check(lib().lf_em_init(ctypes.byref(out), ctypes.byref(p), addr(views), addr(S_P), addr(mu_T), addr(q_warm),
+                            hip_stream))
+    return out.value
+
+
+def lf_em_load(ctx, views, S_P, mu_T, q_warm=None):
+    return _check(lib().lf_em_load(ctx, addr(views), addr(S_P), addr(mu_T), addr(q_warm)))
+
+
+def lf_em_iterate(ctx, n_iters, objective=None):
+    return _check(lib().lf_em_iterate(ctx, int(n_iters), addr(objective)))
+
+
+def lf_refocus(ctx, rgb, d_idx=None, q=None, hole=None, median=0):
+    return _check(lib().lf_refocus(ctx, addr(rgb), addr(d_idx), addr(q), addr(hole), int(median)))
+
+
+def lf_em_state(ctx, q=None, d_idx=None, L_pix=None):
+    return _check(lib().lf_em_state(ctx, addr(q), addr(d_idx), addr(L_pix)))
+
+
+def lf_em_intermediates(ctx, feat=None, rho=None):
+    return _check(lib().lf_em_intermediates(ctx, addr(feat), addr(rho)))
+
+
+def lf_em_destroy(ctx):
+    if ctx:
+        lib().lf_em_destroy(ctx)

@@ -1,0 +1,577 @@
+// Host side of the C ABI declared in include/lf_em.h: parameter validation,
+// device buffer plan, precision and view-count dispatch, launches and copies.
+#include "lf_em.h"
+#include "lf_em_kernels.h"
+#include "lf_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace lfem {
+
+thread_local std::string g_last_error;
+
+lf_status set_error(lf_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+lf_status hip_error(hipError_t e, const char *what) {
+    return set_error(LF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define LF_HIP(call, what)                                 \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_error(e_, what);  \
+    } while (0)
+
+static bool is_int(float v) { return std::isfinite(v) && std::fabs(v) < (1 << 20) && std::floor(v) == v; }
+
+lf_status validate_params(const lf_params *p) {
+    if (!p) return set_error(LF_EINVAL, "params is NULL");
+    if (p->K < 2 || p->K > LF_MAX_VIEWS) return set_error(LF_EINVAL, "K=%d outside [2,%d]", p->K, LF_MAX_VIEWS);
+    if (p->H < 1 || p->W < 1) return set_error(LF_EINVAL, "H=%d W=%d must be >= 1", p->H, p->W);
+    if ((int64_t)p->H * p->W > (int64_t)1 << 28) return set_error(LF_EINVAL, "frame too large");
+    if (p->ref < 0 || p->ref >= p->K) return set_error(LF_EINVAL, "ref=%d outside [0,K)", p->ref);
+    for (int k = 0; k < p->K; ++k)
+        if (!std::isfinite(p->baselines[k]) || std::fabs(p->baselines[k]) > 1e4f)
+            return set_error(LF_EINVAL, "baselines[%d] not finite or too large", k);
+    if (p->baselines[p->ref] != 0.0f) return set_error(LF_EINVAL, "baselines[ref] must be 0");
+    if (p->D < 1) return set_error(LF_EINVAL, "D=%d must be >= 1", p->D);
+    if (!(p->d_step > 0.0f) || !std::isfinite(p->d_step)) return set_error(LF_EINVAL, "d_step must be > 0");
+    if (!std::isfinite(p->d_min)) return set_error(LF_EINVAL, "d_min not finite");
+    if (!std::isfinite(p->d_min + (p->D - 1) * p->d_step) || std::fabs(p->d_min + (p->D - 1) * p->d_step) > 1e5f)
+        return set_error(LF_EINVAL, "disparity range too large");
+    {
+        // footprints x - b_k d are formed in float: keep |b_k d| where a float
+        // resolves well below one pixel
+        float bmax = 0.0f;
+        for (int k = 0; k < p->K; ++k) bmax = std::max(bmax, std::fabs(p->baselines[k]));
+        const float dabs = std::max(std::fabs(p->d_min), std::fabs(p->d_min + (p->D - 1) * p->d_step));
+        if ((double)bmax * dabs > 1e6) return set_error(LF_EINVAL, "shift |baseline * disparity| above 1e6 pixels");
+    }
+    if (!(p->beta >= 0.0f) || !std::isfinite(p->beta)) return set_error(LF_EINVAL, "beta must be finite and >= 0");
+    if (std::isnan(p->lambda) && !(p->beta > 0.0f))
+        return set_error(LF_EINVAL, "lambda cannot be derived for beta == 0; pass it explicitly");
+    if (!std::isnan(p->lambda) && !std::isfinite(p->lambda)) return set_error(LF_EINVAL, "lambda must be finite or NaN");
+    if (!(p->gamma > 0.0f) || !std::isfinite(p->gamma)) return set_error(LF_EINVAL, "gamma must be > 0");
+    if (!(p->sigma > 0.0f) || !std::isfinite(p->sigma)) return set_error(LF_EINVAL, "sigma must be > 0");
+    if (!(p->tau_init >= 0.0f && p->tau_init <= 1.0f)) return set_error(LF_EINVAL, "tau_init outside [0,1]");
+    if (p->storage < LF_F32 || p->storage > LF_BF16) return set_error(LF_EINVAL, "storage=%d unknown", p->storage);
+    if (p->mode != LF_SOFT && p->mode != LF_HARD) return set_error(LF_EINVAL, "mode=%d unknown", p->mode);
+    if (p->flags & ~(LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE)) return set_error(LF_EINVAL, "unknown flags");
+    return LF_OK;
+}
+
+lf_status validate_host_values(const lf_params *p, const float *S_P, const float *mu_T, const float *q_warm) {
+    const size_t HW = (size_t)p->H * p->W, KHW = HW * p->K;
+    for (size_t i = 0; i < KHW; ++i)
+        if (!(S_P[i] >= 0.0f && S_P[i] <= 1.0f)) return set_error(LF_EINVAL, "S_P[%zu] outside [0,1] or NaN", i);
+    for (size_t i = 0; i < HW; ++i)
+        if (!(std::fabs(mu_T[i]) <= 1e6f)) return set_error(LF_EINVAL, "mu_T[%zu] not finite or above 1e6", i);
+    if (q_warm)
+        for (size_t i = 0; i < KHW; ++i)
+            if (!(q_warm[i] >= 0.0f && q_warm[i] <= 1.0f)) return set_error(LF_EINVAL, "q_warm[%zu] outside [0,1]", i);
+    return LF_OK;
+}
+
+float derived_lambda(const lf_params *p) {
+    if (!std::isnan(p->lambda)) return p->lambda;
+    const double F = 2.0, bp = (double)p->beta / p->K, R = 3060.0 / 4096.0, pi = 3.14159265358979323846;
+    return (float)(0.5 * F * std::log(bp / pi) + F * std::log(2.0 * R));
+}
+
+Geometry make_geometry(const lf_params *p) {
+    Geometry g{};
+    g.frac = !(is_int(p->d_min) && is_int(p->d_step));
+    for (int k = 0; k < p->K; ++k) {
+        if (!is_int(p->baselines[k])) g.frac = true;
+        g.bi[k] = g.frac ? 0 : (int)p->baselines[k];
+    }
+    g.dmin_i = g.frac ? 0 : (int)p->d_min;
+    g.dstep_i = g.frac ? 0 : (int)p->d_step;
+    if (!g.frac) {
+        // integer levels must also keep integer shifts inside int range
+        for (int k = 0; k < p->K; ++k) {
+            const long long s = (long long)std::abs(g.bi[k]) *
+                                (std::llabs((long long)g.dmin_i) + (long long)(p->D - 1) * g.dstep_i);
+            if (s > (1 << 24)) g.frac = true;
+        }
+    }
+    return g;
+}
+
+// Upper bound of the LDS pairs one EM block stages for a tile of `tile` pixels.
+size_t em_window_pairs(const lf_params *p, const Geometry &g, int tile) {
+    size_t tot = 0;
+    const double d_max = (double)p->d_min + (double)(p->D - 1) * p->d_step;
+    for (int k = 0; k < p->K; ++k) {
+        if (g.frac) {
+            const double s0 = (double)p->baselines[k] * p->d_min, s1 = (double)p->baselines[k] * d_max;
+            tot += (size_t)tile + (size_t)std::ceil(std::fabs(s1 - s0)) + 8;
+        } else {
+            const long long dmax_i = g.dmin_i + (long long)(p->D - 1) * g.dstep_i;
+            const long long s0 = (long long)g.bi[k] * g.dmin_i, s1 = (long long)g.bi[k] * dmax_i;
+            tot += (size_t)tile + (size_t)std::llabs(s1 - s0);
+        }
+    }
+    return tot;
+}
+
+size_t pair_bytes(int storage) { return storage == LF_F32 ? 8 : 4; }
+
+// ---------------------------------------------------------------------------
+// Kernel dispatch over (K, storage, integer/fractional shifts).
+// ---------------------------------------------------------------------------
+using EmKernel = void (*)(EmArgs);
+
+template <int K, int ST>
+static EmKernel pick_em2(bool frac) {
+    return frac ? (EmKernel)lf_em_kernel<K, ST, true> : (EmKernel)lf_em_kernel<K, ST, false>;
+}
+
+template <int K>
+static EmKernel pick_em1(int st, bool frac) {
+    switch (st) {
+        case LF_F32: return pick_em2<K, 0>(frac);
+        case LF_F16: return pick_em2<K, 1>(frac);
+        default: return pick_em2<K, 2>(frac);
+    }
+}
+
+EmKernel pick_em(int K, int st, bool frac) {
+    switch (K) {
+#define LF_CASE(n) \
+    case n: return pick_em1<n>(st, frac);
+        LF_CASE(2) LF_CASE(3) LF_CASE(4) LF_CASE(5) LF_CASE(6) LF_CASE(7) LF_CASE(8) LF_CASE(9)
+        LF_CASE(10) LF_CASE(11) LF_CASE(12) LF_CASE(13) LF_CASE(14) LF_CASE(15) LF_CASE(16)
+#undef LF_CASE
+        default: return nullptr;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers shared by the plain context and the server.
+// ---------------------------------------------------------------------------
+hipError_t launch_descriptors(const lf_params *p, const uint8_t *views, void *feat, hipStream_t s) {
+    dim3 block(256), grid((p->W + 255) / 256, p->H, p->K);
+    switch (p->storage) {
+        case LF_F32:
+            hipLaunchKernelGGL(lf_descriptors_kernel<0>, grid, block, 0, s, views, (float2 *)feat, p->H, p->W);
+            break;
+        case LF_F16:
+            hipLaunchKernelGGL(lf_descriptors_kernel<1>, grid, block, 0, s, views, (__half2 *)feat, p->H, p->W);
+            break;
+        default:
+            hipLaunchKernelGGL(lf_descriptors_kernel<2>, grid, block, 0, s, views, (uint32_t *)feat, p->H, p->W);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *mu_T, const float *q_warm,
+                            float *rho, float *q, uint32_t *bad, int check, hipStream_t s) {
+    PriorArgs a{};
+    a.S_P = S_P;
+    a.mu_T = mu_T;
+    a.q_warm = q_warm;
+    a.rho = rho;
+    a.q = q;
+    a.bad = bad;
+    a.K = p->K;
+    a.H = p->H;
+    a.W = p->W;
+    a.storage = p->storage;
+    a.check = check;
+    a.tau = p->tau_init;
+    for (int k = 0; k < p->K; ++k) a.b[k] = p->baselines[k];
+    dim3 block(256), grid((p->W + 255) / 256, p->H, p->K);
+    hipLaunchKernelGGL(lf_ray_prior_kernel, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
+    EmArgs a{};
+    a.H = p->H;
+    a.W = p->W;
+    a.D = p->D;
+    a.mode = p->mode;
+    a.dmin_i = g.dmin_i;
+    a.dstep_i = g.dstep_i;
+    a.d_min = p->d_min;
+    a.d_step = p->d_step;
+    a.beta_p = (float)((double)p->beta / p->K);
+    a.lambda = lambda;
+    a.gamma = p->gamma;
+    const double s2 = 2.0 * (double)p->sigma * p->sigma;
+    a.c_exp2 = (float)(1.4426950408889634 / s2);
+    a.c_exp = (float)(1.0 / s2);
+    for (int k = 0; k < p->K; ++k) {
+        a.bi[k] = g.bi[k];
+        a.b[k] = p->baselines[k];
+    }
+    return a;
+}
+
+hipError_t launch_em(const lf_params *p, const Geometry &g, EmArgs a, int tile, size_t lds, hipStream_t s) {
+    EmKernel kern = pick_em(p->K, p->storage, g.frac);
+    a.tile = tile;
+    dim3 block(tile), grid((p->W + tile - 1) / tile, p->H);
+    a.n_blocks = grid.x * grid.y;
+    hipLaunchKernelGGL(kern, grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
+RefocusArgs make_refocus_args(const lf_params *p, const Geometry &g) {
+    RefocusArgs r{};
+    r.K = p->K;
+    r.H = p->H;
+    r.W = p->W;
+    r.ref = p->ref;
+    r.frac = g.frac;
+    r.dmin_i = g.dmin_i;
+    r.dstep_i = g.dstep_i;
+    r.d_min = p->d_min;
+    r.d_step = p->d_step;
+    for (int k = 0; k < p->K; ++k) {
+        r.bi[k] = g.bi[k];
+        r.b[k] = p->baselines[k];
+    }
+    return r;
+}
+
+hipError_t launch_refocus(const lf_params *p, RefocusArgs r, hipStream_t s) {
+    dim3 block(256), grid((p->W + 255) / 256, p->H);
+    hipLaunchKernelGGL(lf_refocus_kernel, grid, block, 0, s, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_median3(const lf_params *p, const float *in, float *out, hipStream_t s) {
+    dim3 block(256), grid((p->W + 255) / 256, p->H);
+    hipLaunchKernelGGL(lf_median3_kernel, grid, block, 0, s, in, out, p->H, p->W);
+    return hipGetLastError();
+}
+
+int choose_tile(const lf_params *p, const Geometry &g, size_t lds_limit, size_t *lds_out) {
+    int tile = p->W >= 128 ? 128 : 64;
+    for (;;) {
+        const size_t lds = em_window_pairs(p, g, tile) * pair_bytes(p->storage);
+        if (lds <= lds_limit || tile == 64) {
+            *lds_out = lds;
+            return lds <= lds_limit ? tile : 0;
+        }
+        tile /= 2;
+    }
+}
+
+}  // namespace lfem
+
+using namespace lfem;
+
+// ---------------------------------------------------------------------------
+// Plain context.
+// ---------------------------------------------------------------------------
+struct lf_ctx {
+    lf_params p;
+    Geometry g;
+    float lambda;
+    int device;
+    hipStream_t stream;
+    bool own_stream;
+    DeviceArena arena;
+    uint8_t *views_own;
+    float *sp_own, *mu_own, *qw_own;
+    const uint8_t *views;   // the frame's views on the device (own copy or caller's)
+    const float *mu_dev;    // the frame's mu_T on the device (own copy or caller's)
+    void *feat;
+    float *rho, *q, *lpix, *rgb, *rgb_med;
+    int32_t *d_idx;
+    uint8_t *hole;
+    double *obj;
+    uint32_t *bad;
+    double *h_obj;          // pinned
+    uint32_t *h_bad;        // pinned
+    int tile, n_blocks;
+    size_t lds;
+    bool loaded;
+    int64_t iters;
+};
+
+static constexpr int kMaxItersPerLaunch = 64;
+
+static lf_status ctx_alloc(lf_ctx *c) {
+    const lf_params &p = c->p;
+    const size_t HW = (size_t)p.H * p.W, KHW = HW * p.K;
+    const bool dev_in = p.flags & LF_INPUTS_ON_DEVICE;
+    const bool dev_out = p.flags & LF_OUTPUTS_ON_DEVICE;
+    size_t lds_limit = 0;
+    {
+        int v = 0;
+        LF_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device), "device attribute");
+        lds_limit = (size_t)v;
+    }
+    c->tile = choose_tile(&p, c->g, lds_limit, &c->lds);
+    if (!c->tile)
+        return set_error(LF_EINVAL, "disparity halo needs %zu bytes of LDS per block, more than %zu", c->lds, lds_limit);
+    c->n_blocks = ((p.W + c->tile - 1) / c->tile) * p.H;
+    ArenaPlan plan;
+    if (!dev_in) {
+        plan.add(&c->views_own, KHW * 3);
+        plan.add(&c->sp_own, KHW * 4);
+        plan.add(&c->mu_own, HW * 4);
+        plan.add(&c->qw_own, KHW * 4);
+    }
+    plan.add(&c->feat, KHW * pair_bytes(p.storage));
+    plan.add(&c->rho, KHW * 4);
+    plan.add(&c->q, KHW * 4);
+    plan.add(&c->d_idx, HW * 4);
+    plan.add(&c->lpix, HW * 4);
+    plan.add(&c->obj, (size_t)kMaxItersPerLaunch * c->n_blocks * 8);
+    plan.add(&c->bad, 256);
+    if (!dev_out) {
+        plan.add(&c->rgb, HW * 12);
+        plan.add(&c->hole, HW);
+    }
+    plan.add(&c->rgb_med, HW * 12);
+    lf_status st = c->arena.allocate(plan);
+    if (st != LF_OK) return st;
+    LF_HIP(hipHostMalloc((void **)&c->h_obj, (size_t)kMaxItersPerLaunch * c->n_blocks * 8, hipHostMallocDefault),
+           "pinned allocation");
+    LF_HIP(hipHostMalloc((void **)&c->h_bad, 256, hipHostMallocDefault), "pinned allocation");
+    return LF_OK;
+}
+
+static lf_status ctx_load(lf_ctx *c, const uint8_t *views, const float *S_P, const float *mu_T, const float *q_warm) {
+    const lf_params &p = c->p;
+    const size_t HW = (size_t)p.H * p.W, KHW = HW * p.K;
+    if (!views || !S_P || !mu_T) return set_error(LF_EINVAL, "views, S_P and mu_T are required");
+    const bool dev_in = p.flags & LF_INPUTS_ON_DEVICE;
+    c->loaded = false;
+    c->iters = 0;
+    const float *sp = S_P, *mu = mu_T, *qw = q_warm;
+    if (!dev_in) {
+        lf_status st = validate_host_values(&p, S_P, mu_T, q_warm);
+        if (st != LF_OK) return st;
+        LF_HIP(hipMemcpyAsync(c->views_own, views, KHW * 3, hipMemcpyHostToDevice, c->stream), "copy views");
+        LF_HIP(hipMemcpyAsync(c->sp_own, S_P, KHW * 4, hipMemcpyHostToDevice, c->stream), "copy S_P");
+        LF_HIP(hipMemcpyAsync(c->mu_own, mu_T, HW * 4, hipMemcpyHostToDevice, c->stream), "copy mu_T");
+        if (q_warm) LF_HIP(hipMemcpyAsync(c->qw_own, q_warm, KHW * 4, hipMemcpyHostToDevice, c->stream), "copy q_warm");
+        c->views = c->views_own;
+        sp = c->sp_own;
+        mu = c->mu_own;
+        qw = q_warm ? c->qw_own : nullptr;
+    } else {
+        c->views = views;
+        LF_HIP(hipMemsetAsync(c->bad, 0, 4, c->stream), "clear counter");
+    }
+    LF_HIP(launch_descriptors(&p, c->views, c->feat, c->stream), "descriptor launch");
+    LF_HIP(launch_ray_prior(&p, sp, mu, qw, c->rho, c->q, c->bad, dev_in ? 1 : 0, c->stream), "ray prior launch");
+    if (dev_in) {
+        LF_HIP(hipMemcpyAsync(c->h_bad, c->bad, 4, hipMemcpyDeviceToHost, c->stream), "copy counter");
+        LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+        if (*c->h_bad) return set_error(LF_EINVAL, "%u input values invalid (S_P outside [0,1], mu_T not finite "
+                                                  "or q_warm outside [0,1])", *c->h_bad);
+    } else {
+        // host inputs were copied asynchronously from caller memory: finish the
+        // copies before returning so the caller may free its buffers
+        LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    }
+    c->mu_dev = mu;
+    c->loaded = true;
+    return LF_OK;
+}
+
+namespace lfem {
+
+lf_status DeviceArena::allocate(const ArenaPlan &plan) {
+    release();
+    bytes = plan.total();
+    if (bytes == 0) return LF_OK;
+    hipError_t e = hipMalloc(&base, bytes);
+    if (e != hipSuccess) {
+        base = nullptr;
+        (void)hipGetLastError();
+        return set_error(LF_ENOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    size_t off = 0;
+    for (const ArenaPlan::Item &i : plan.items) {
+        *i.slot = static_cast<char *>(base) + off;
+        off += (i.bytes + 255) & ~(size_t)255;
+    }
+    return LF_OK;
+}
+
+void DeviceArena::release() {
+    if (base) (void)hipFree(base);
+    base = nullptr;
+    bytes = 0;
+}
+
+}  // namespace lfem
+
+static void ctx_free(lf_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    c->arena.release();
+    if (c->h_obj) (void)hipHostFree(c->h_obj);
+    if (c->h_bad) (void)hipHostFree(c->h_bad);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+extern "C" {
+
+const char *lf_last_error(void) { return g_last_error.c_str(); }
+
+lf_status lf_em_init(lf_ctx **out, const lf_params *p, const uint8_t *views, const float *S_P, const float *mu_T,
+                     const float *q_warm, void *hip_stream) {
+    g_last_error.clear();
+    if (!out) return set_error(LF_EINVAL, "out is NULL");
+    *out = nullptr;
+    lf_status st = validate_params(p);
+    if (st != LF_OK) return st;
+    if (!views || !S_P || !mu_T) return set_error(LF_EINVAL, "views, S_P and mu_T are required");
+    if (!(p->flags & LF_INPUTS_ON_DEVICE)) {
+        st = validate_host_values(p, S_P, mu_T, q_warm);
+        if (st != LF_OK) return st;
+    }
+    lf_ctx *c = new lf_ctx();
+    c->p = *p;
+    c->g = make_geometry(p);
+    c->lambda = derived_lambda(p);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        ctx_free(c);
+        return set_error(LF_EDEVICE, "no HIP device");
+    }
+    c->stream = (hipStream_t)hip_stream;   // NULL: the device's null stream
+    c->own_stream = false;
+    st = ctx_alloc(c);
+    if (st == LF_OK) st = ctx_load(c, views, S_P, mu_T, q_warm);
+    if (st != LF_OK) {
+        std::string msg = g_last_error;
+        ctx_free(c);
+        g_last_error = msg;
+        return st;
+    }
+    *out = c;
+    return LF_OK;
+}
+
+lf_status lf_em_load(lf_ctx *c, const uint8_t *views, const float *S_P, const float *mu_T, const float *q_warm) {
+    g_last_error.clear();
+    if (!c) return set_error(LF_EINVAL, "context is NULL");
+    return ctx_load(c, views, S_P, mu_T, q_warm);
+}
+
+lf_status lf_em_iterate(lf_ctx *c, int32_t n_iters, double *objective) {
+    g_last_error.clear();
+    if (!c) return set_error(LF_EINVAL, "context is NULL");
+    if (n_iters < 0) return set_error(LF_EINVAL, "n_iters=%d < 0", n_iters);
+    if (!c->loaded) return set_error(LF_ESTATE, "no frame loaded");
+    EmArgs a = make_em_args(&c->p, c->g, c->lambda);
+    a.feat = c->feat;
+    a.rho = c->rho;
+    a.mu_T = c->mu_dev;
+    a.q = c->q;
+    a.d_idx = c->d_idx;
+    a.lpix = c->lpix;
+    a.obj = c->obj;
+    int done = 0;
+    while (done < n_iters) {
+        const int n = std::min(kMaxItersPerLaunch, n_iters - done);
+        a.n_iters = n;
+        LF_HIP(launch_em(&c->p, c->g, a, c->tile, c->lds, c->stream), "EM launch");
+        if (objective) {
+            LF_HIP(hipMemcpyAsync(c->h_obj, c->obj, (size_t)n * c->n_blocks * 8, hipMemcpyDeviceToHost, c->stream),
+                   "copy objective");
+            LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+            for (int t = 0; t < n; ++t) {
+                double s = 0.0;
+                const double *row = c->h_obj + (size_t)t * c->n_blocks;
+                for (int b = 0; b < c->n_blocks; ++b) s += row[b];
+                objective[done + t] = s;
+            }
+        }
+        done += n;
+    }
+    c->iters += n_iters;
+    return LF_OK;
+}
+
+static lf_status copy_out(lf_ctx *c, void *dst, const void *src, size_t bytes) {
+    const hipMemcpyKind kind = (c->p.flags & LF_OUTPUTS_ON_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    LF_HIP(hipMemcpyAsync(dst, src, bytes, kind, c->stream), "copy output");
+    return LF_OK;
+}
+
+lf_status lf_refocus(lf_ctx *c, float *rgb, int32_t *d_idx, float *q, uint8_t *hole, int32_t median) {
+    g_last_error.clear();
+    if (!c) return set_error(LF_EINVAL, "context is NULL");
+    if (!rgb) return set_error(LF_EINVAL, "rgb is required");
+    if (median != 0 && median != 3) return set_error(LF_EINVAL, "median=%d must be 0 or 3", median);
+    if (!c->loaded || c->iters == 0) return set_error(LF_ESTATE, "refocus needs at least one EM iteration");
+    const lf_params &p = c->p;
+    const size_t HW = (size_t)p.H * p.W;
+    const bool dev_out = p.flags & LF_OUTPUTS_ON_DEVICE;
+    RefocusArgs r = make_refocus_args(&p, c->g);
+    r.views = c->views;
+    r.d_idx = c->d_idx;
+    r.q = c->q;
+    float *rgb_k = median ? c->rgb_med : (dev_out ? rgb : c->rgb);
+    r.rgb = rgb_k;
+    r.hole = dev_out ? hole : c->hole;
+    LF_HIP(launch_refocus(&p, r, c->stream), "refocus launch");
+    if (median) LF_HIP(launch_median3(&p, c->rgb_med, dev_out ? rgb : c->rgb, c->stream), "median launch");
+    lf_status st = LF_OK;
+    if (!dev_out) {
+        if (st == LF_OK) st = copy_out(c, rgb, c->rgb, HW * 12);
+        if (st == LF_OK && hole) st = copy_out(c, hole, c->hole, HW);
+    }
+    if (st == LF_OK && d_idx) st = copy_out(c, d_idx, c->d_idx, HW * 4);
+    if (st == LF_OK && q) st = copy_out(c, q, c->q, HW * p.K * 4);
+    if (st != LF_OK) return st;
+    if (!dev_out) LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    return LF_OK;
+}
+
+lf_status lf_em_state(lf_ctx *c, float *q, int32_t *d_idx, float *L_pix) {
+    g_last_error.clear();
+    if (!c) return set_error(LF_EINVAL, "context is NULL");
+    if (!c->loaded) return set_error(LF_ESTATE, "no frame loaded");
+    if ((d_idx || L_pix) && c->iters == 0) return set_error(LF_ESTATE, "no EM iteration since the last load");
+    const size_t HW = (size_t)c->p.H * c->p.W;
+    lf_status st = LF_OK;
+    if (q) st = copy_out(c, q, c->q, HW * c->p.K * 4);
+    if (st == LF_OK && d_idx) st = copy_out(c, d_idx, c->d_idx, HW * 4);
+    if (st == LF_OK && L_pix) st = copy_out(c, L_pix, c->lpix, HW * 4);
+    if (st != LF_OK) return st;
+    if (!(c->p.flags & LF_OUTPUTS_ON_DEVICE)) LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    return LF_OK;
+}
+
+lf_status lf_em_intermediates(lf_ctx *c, void *feat, float *rho) {
+    g_last_error.clear();
+    if (!c) return set_error(LF_EINVAL, "context is NULL");
+    if (!c->loaded) return set_error(LF_ESTATE, "no frame loaded");
+    const size_t KHW = (size_t)c->p.H * c->p.W * c->p.K;
+    lf_status st = LF_OK;
+    if (feat) st = copy_out(c, feat, c->feat, KHW * pair_bytes(c->p.storage));
+    if (st == LF_OK && rho) st = copy_out(c, rho, c->rho, KHW * 4);
+    if (st != LF_OK) return st;
+    if (!(c->p.flags & LF_OUTPUTS_ON_DEVICE)) LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    return LF_OK;
+}
+
+void lf_em_destroy(lf_ctx *c) { ctx_free(c); }
+
+}  // extern "C"

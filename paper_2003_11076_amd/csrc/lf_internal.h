@@ -1,0 +1,67 @@
+// Internal declarations shared by the plain context (lf_em.hip) and the
+// frame server (lf_server.hip).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "lf_em.h"
+
+namespace lfem {
+
+struct EmArgs;
+struct RefocusArgs;
+
+// Integer-shift geometry: when every baseline and both level parameters are
+// integers, footprints x - b_k d_j are exact integers and the kernels index
+// directly; otherwise they interpolate (frac = true).
+struct Geometry {
+    bool frac;
+    int dmin_i, dstep_i;
+    int bi[LF_MAX_VIEWS];
+};
+
+// One device allocation carved into 256-byte aligned buffers.
+struct ArenaPlan {
+    struct Item {
+        void **slot;
+        size_t bytes;
+    };
+    std::vector<Item> items;
+    template <class T>
+    void add(T **slot, size_t bytes) {
+        items.push_back({reinterpret_cast<void **>(slot), bytes});
+    }
+    size_t total() const {
+        size_t t = 0;
+        for (const Item &i : items) t += (i.bytes + 255) & ~(size_t)255;
+        return t;
+    }
+};
+
+struct DeviceArena {
+    void *base = nullptr;
+    size_t bytes = 0;
+    lf_status allocate(const ArenaPlan &plan);
+    void release();
+};
+
+lf_status set_error(lf_status s, const char *fmt, ...);
+lf_status hip_error(hipError_t e, const char *what);
+lf_status validate_params(const lf_params *p);
+lf_status validate_host_values(const lf_params *p, const float *S_P, const float *mu_T, const float *q_warm);
+float derived_lambda(const lf_params *p);
+Geometry make_geometry(const lf_params *p);
+size_t em_window_pairs(const lf_params *p, const Geometry &g, int tile);
+size_t pair_bytes(int storage);
+int choose_tile(const lf_params *p, const Geometry &g, size_t lds_limit, size_t *lds_out);
+
+hipError_t launch_descriptors(const lf_params *p, const uint8_t *views, void *feat, hipStream_t s);
+hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *mu_T, const float *q_warm,
+                            float *rho, float *q, uint32_t *bad, int check, hipStream_t s);
+hipError_t launch_median3(const lf_params *p, const float *in, float *out, hipStream_t s);
+
+}  // namespace lfem

@@ -1,0 +1,258 @@
+"""Test plumbing shared by the parity tests.
+
+A `Case` holds one seeded frame and its parameters, rounded to float32
+exactly as the C ABI receives them, so the oracle and the GPU library see the
+same numbers.  `teacher_forced` runs the GPU library one EM iteration at a
+time and, at every iteration, runs the FP64 oracle from the GPU's own state,
+comparing element by element:
+
+  * descriptors: bit-exact (integer Sobel, one rounding to the storage format);
+  * rho: max-abs 1e-6;  first weights q0: exact except |rho - tau| < 1e-6;
+  * d_idx: exact except near-ties, E_(2) - E_(1) <= 1e-4 * max(|E_(2)|, 1)
+    with the oracle's two smallest energies of that iteration;
+  * q: max-abs 1e-5 on pixels with matching d (hard mode: exact except
+    |a1 - a0| < 1e-3, the decision taken in different precisions);
+  * per-pixel objective: |diff| <= 1e-5 * max(|L|, 1) on pixels with matching d.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+import oracle as O
+
+TOL_RHO = 1e-6
+TOL_Q = 1e-5
+TOL_L = 1e-5
+TOL_RGB = 1e-6
+NEAR_TIE = 1e-4
+
+
+def f32(v) -> float:
+    return float(np.float32(v))
+
+
+@dataclass
+class Case:
+    K: int
+    H: int
+    W: int
+    ref: int
+    baselines: tuple
+    d_min: float
+    d_step: float
+    D: int
+    beta: float
+    lam: float
+    gamma: float
+    sigma: float
+    tau: float
+    storage: str
+    mode: str
+    views: np.ndarray
+    S_P: np.ndarray
+    mu_T: np.ndarray
+    n_iters: int = 1
+
+    @classmethod
+    def from_frame(cls, fr, storage=None, mode="soft", **over):
+        sp = fr.spec
+        c = cls(sp.K, sp.H, sp.W, sp.ref, tuple(f32(b) for b in sp.baselines), f32(sp.d_min), f32(sp.d_step),
+                sp.D, f32(fr.beta), float("nan"), f32(sp.gamma), f32(sp.sigma), f32(sp.tau),
+                storage or sp.storage, mode, fr.views, fr.S_P.astype(np.float32), fr.mu_T.astype(np.float32),
+                sp.n_iters)
+        for k, v in over.items():
+            setattr(c, k, v)
+        return c
+
+    def api_params(self, flags=0):
+        import paper_2003_11076_amd as LF
+        return LF.make_params(self.K, self.H, self.W, self.ref, self.baselines, self.d_min, self.d_step, self.D,
+                              self.beta, self.lam, self.gamma, self.sigma, self.tau, self.storage, self.mode, flags)
+
+    def oracle_params(self, mode=None):
+        return O.make_params(self.K, self.H, self.W, self.ref, self.baselines, self.d_min, self.d_step, self.D,
+                             self.beta, self.lam, self.gamma, self.sigma, self.tau, self.storage, mode or self.mode)
+
+
+def random_case(K, H, W, D, *, baselines=None, d_min=0.0, d_step=1.0, storage="f32", mode="soft", beta=2133.0,
+                seed=0, mu_range=None, ref=None):
+    """Small random-texture case (iid views, noisy S_P, smooth random mu_T)."""
+    rng = np.random.default_rng(seed)
+    if baselines is None:
+        baselines = [float(k - (K - 1) // 2) for k in range(K)]
+    if ref is None:
+        ref = int(np.argmin(np.abs(np.asarray(baselines))))
+    views = rng.integers(0, 256, size=(K, H, W, 3), dtype=np.uint8)
+    S_P = np.clip(rng.integers(0, 2, size=(K, H, W)) + rng.normal(0, 0.15, size=(K, H, W)), 0, 1).astype(np.float32)
+    lo, hi = mu_range or (d_min, d_min + d_step * (D - 1))
+    mu = (rng.uniform(lo, hi) + rng.normal(0, 0.5, size=(H, W)).cumsum(axis=1) * 0.1).astype(np.float32)
+    return Case(K, H, W, ref, tuple(f32(b) for b in baselines), f32(d_min), f32(d_step), D, f32(beta),
+                float("nan"), f32(0.05), f32(2.0), f32(0.7), storage, mode, views, S_P, mu)
+
+
+# ---------------------------------------------------------------------------
+# Storage decoding
+# ---------------------------------------------------------------------------
+
+def decode_feat(raw: np.ndarray, storage: str, K, H, W) -> np.ndarray:
+    """GPU descriptor bytes -> float64 [K][H][W][2]."""
+    if storage == "f32":
+        return raw.view(np.float32).reshape(K, H, W, 2).astype(np.float64)
+    if storage == "f16":
+        return raw.view(np.float16).reshape(K, H, W, 2).astype(np.float64)
+    u = raw.view(np.uint16).reshape(K, H, W, 2).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+def feat_bytes(storage, K, H, W):
+    return K * H * W * (8 if storage == "f32" else 4)
+
+
+# ---------------------------------------------------------------------------
+# GPU runs through the C ABI (inputs as device tensors on torch's stream)
+# ---------------------------------------------------------------------------
+
+class GpuRun:
+    def __init__(self, case: Case, device_inputs=True, q_warm=None):
+        import torch
+        import paper_2003_11076_amd as LF
+        self.LF, self.case = LF, case
+        flags = LF.LF_INPUTS_ON_DEVICE if device_inputs else 0
+        stream = torch.cuda.current_stream().cuda_stream
+        if device_inputs:
+            dev = torch.device("cuda")
+            self.t_views = torch.from_numpy(np.ascontiguousarray(case.views)).to(dev)
+            self.t_sp = torch.from_numpy(np.ascontiguousarray(case.S_P)).to(dev)
+            self.t_mu = torch.from_numpy(np.ascontiguousarray(case.mu_T)).to(dev)
+            self.t_qw = None if q_warm is None else torch.from_numpy(np.ascontiguousarray(q_warm, np.float32)).to(dev)
+            args = (self.t_views, self.t_sp, self.t_mu, self.t_qw)
+        else:
+            qw = None if q_warm is None else np.ascontiguousarray(q_warm, np.float32)
+            args = (np.ascontiguousarray(case.views), np.ascontiguousarray(case.S_P),
+                    np.ascontiguousarray(case.mu_T), qw)
+        self.ctx = LF.lf_em_init(case.api_params(flags), *args, hip_stream=stream)
+
+    def close(self):
+        if self.ctx:
+            self.LF.lf_em_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def iterate(self, n, objective=False):
+        obj = np.zeros(max(n, 1), np.float64) if objective else None
+        self.LF.lf_em_iterate(self.ctx, n, obj)
+        return obj
+
+    def state(self, with_d=True):
+        c = self.case
+        q = np.zeros((c.K, c.H, c.W), np.float32)
+        d = np.zeros((c.H, c.W), np.int32) if with_d else None
+        L = np.zeros((c.H, c.W), np.float32) if with_d else None
+        self.LF.lf_em_state(self.ctx, q, d, L)
+        return q, d, L
+
+    def intermediates(self):
+        c = self.case
+        raw = np.zeros(feat_bytes(c.storage, c.K, c.H, c.W), np.uint8)
+        rho = np.zeros((c.K, c.H, c.W), np.float32)
+        self.LF.lf_em_intermediates(self.ctx, raw, rho)
+        return decode_feat(raw, c.storage, c.K, c.H, c.W), rho
+
+    def refocus(self, median=0):
+        c = self.case
+        rgb = np.zeros((c.H, c.W, 3), np.float32)
+        d = np.zeros((c.H, c.W), np.int32)
+        q = np.zeros((c.K, c.H, c.W), np.float32)
+        hole = np.zeros((c.H, c.W), np.uint8)
+        self.LF.lf_refocus(self.ctx, rgb, d, q, hole, median)
+        return rgb, d, q, hole
+
+
+# ---------------------------------------------------------------------------
+# Comparisons
+# ---------------------------------------------------------------------------
+
+def near_tie(E1, E2):
+    return (E2 - E1) <= NEAR_TIE * np.maximum(np.abs(E2), 1.0)
+
+
+def rows_mask(H, W, rows):
+    m = np.zeros((H, W), bool)
+    y0, y1 = rows if rows is not None else (0, H)
+    m[y0:y1] = True
+    return m
+
+
+def compare_iteration(case, ref, ref_soft, q_gpu, d_gpu, L_gpu, rows=None, label=""):
+    """Compare one GPU iteration with the oracle's iteration from the same state.
+    Returns a dict of statistics; raises AssertionError on a parity failure."""
+    sel = rows_mask(case.H, case.W, rows)
+    tie = near_tie(ref["E1"], ref["E2"]) & sel
+    d_ok = (d_gpu == ref["d_idx"])
+    bad_d = sel & ~d_ok & ~tie
+    assert not bad_d.any(), f"{label}: d_idx differs off near-ties at {np.argwhere(bad_d)[:5].tolist()} " \
+                            f"gpu={d_gpu[bad_d][:5]} oracle={ref['d_idx'][bad_d][:5]}"
+    same = sel & d_ok
+    qd = np.abs(q_gpu.astype(np.float64) - ref["q"])
+    if case.mode == "hard":
+        z = np.log(np.clip(ref_soft["q"], 1e-300, 1.0)) - np.log(np.clip(1.0 - ref_soft["q"], 1e-300, 1.0))
+        decided = np.abs(z) >= 1e-3
+        bad_q = (qd > 0) & decided & same[None]
+        assert not bad_q.any(), f"{label}: hard q differs at {np.argwhere(bad_q)[:5].tolist()}"
+    else:
+        qmax = float(qd[:, same].max()) if same.any() else 0.0
+        assert qmax <= TOL_Q, f"{label}: q max-abs {qmax:.3g} > {TOL_Q}"
+    Ld = np.abs(L_gpu.astype(np.float64) - ref["L"]) / np.maximum(np.abs(ref["L"]), 1.0)
+    Lmax = float(Ld[same].max()) if same.any() else 0.0
+    assert Lmax <= TOL_L, f"{label}: objective rel diff {Lmax:.3g} > {TOL_L}"
+    n = int(sel.sum())
+    return {"pixels": n, "near_ties": int(tie.sum()), "d_mismatch_at_ties": int((sel & ~d_ok).sum()),
+            "q_maxabs": float(qd[:, same].max()) if same.any() else 0.0, "L_maxrel": Lmax}
+
+
+def teacher_forced(case: Case, n_iters: int, rows=None, device_inputs=True, check_refocus=True):
+    """Per-iteration parity of the GPU library against the oracle (see module doc)."""
+    op = case.oracle_params()
+    y0, y1 = rows if rows is not None else (0, case.H)
+    orows = (max(0, y0 - 1), min(case.H, y1 + 1))
+    f_o = O.descriptors(op, case.views, rows=orows)
+    rho_o, q0_o = O.ray_prior(op, case.S_P, case.mu_T, rows=(y0, y1))
+    run = GpuRun(case, device_inputs=device_inputs)
+    try:
+        f_g, rho_g = run.intermediates()
+        assert np.array_equal(f_g[:, y0:y1], f_o[:, y0:y1]), "descriptors differ"
+        rdiff = np.abs(rho_g[:, y0:y1].astype(np.float64) - rho_o[:, y0:y1]).max()
+        assert rdiff <= TOL_RHO, f"rho max-abs {rdiff:.3g}"
+        q_prev, _, _ = run.state(with_d=False)
+        near_tau = np.abs(rho_o - case.tau) < 1e-6
+        bad = (q_prev[:, y0:y1] != q0_o[:, y0:y1]) & ~near_tau[:, y0:y1]
+        assert not bad.any(), "first weights differ off the threshold"
+        stats = []
+        for t in range(n_iters):
+            run.iterate(1)
+            q_g, d_g, L_g = run.state()
+            ref = O.em_iteration(op, f_o, rho_o, case.mu_T, q_prev.astype(np.float64), rows=(y0, y1))
+            ref_soft = ref
+            if case.mode == "hard":
+                ref_soft = O.em_iteration(case.oracle_params(mode="soft"), f_o, rho_o, case.mu_T,
+                                          q_prev.astype(np.float64), rows=(y0, y1))
+            stats.append(compare_iteration(case, ref, ref_soft, q_g, d_g, L_g, rows=(y0, y1), label=f"iter {t + 1}"))
+            q_prev = q_g
+        if check_refocus and n_iters > 0:
+            rgb_g, d_g, q_g, hole_g = run.refocus()
+            rgb_o, hole_o = O.refocus(op, case.views, d_g, q_g.astype(np.float64), rows=(y0, y1))
+            assert np.array_equal(hole_g[y0:y1], hole_o[y0:y1]), "hole mask differs"
+            near_half = (np.abs(q_g.astype(np.float64) - 0.5) < 1e-4).any(axis=0)
+            cmp = ~near_half[y0:y1]
+            rd = np.abs(rgb_g[y0:y1].astype(np.float64) - rgb_o[y0:y1]).max(axis=-1)
+            rmax = float(rd[cmp].max()) if cmp.any() else 0.0
+            assert rmax <= TOL_RGB, f"refocus max-abs {rmax:.3g}"
+            stats.append({"refocus_maxabs": rmax})
+        return stats
+    finally:
+        run.close()

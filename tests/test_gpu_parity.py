@@ -1,0 +1,194 @@
+"""Parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Each test prints the case it runs (and flushes) before touching the GPU.
+Tolerances and exemptions are those of tests/lfcase.py.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import lf_scenes as S
+import oracle as O
+from lfcase import Case, GpuRun, random_case, teacher_forced, near_tie
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def config1():
+    return S.make_frame(S.config_spec(1))
+
+
+@pytest.mark.parametrize("mode", ["soft", "hard"])
+def test_config1_teacher_forced(config1, mode):
+    case = Case.from_frame(config1, storage="f32", mode=mode)
+    _say(f"config1 160x120 K=5 D=32 fp32 {mode} teacher-forced x5")
+    stats = teacher_forced(case, 5)
+    assert sum(s.get("near_ties", 0) for s in stats[:-1]) < 0.01 * case.H * case.W * 5
+
+
+SMALL = [
+    # K, H, W, D, baselines, d_min, d_step, storage
+    (2, 7, 37, 9, [0, 1], 0, 1, "f32"),                   # W below one tile
+    (3, 5, 300, 16, [-1, 0, 2], -2, 1, "f16"),            # ragged last tile, negative levels
+    (5, 4, 129, 24, None, 0, 1, "bf16"),                  # one pixel past a tile
+    (4, 3, 70, 12, [-1.5, 0, 0.5, 2.25], 0, 0.5, "f32"),  # fractional shifts
+    (4, 3, 70, 12, [-1.5, 0, 0.5, 2.25], 1.25, 0.75, "f16"),
+    (9, 3, 200, 40, None, 0, 1, "f32"),
+    (16, 2, 64, 8, list(range(-7, 9)), 0, 1, "f32"),      # largest K
+    (3, 1, 1, 1, [0, 1, 2], 0, 1, "f32"),                 # one pixel, one level
+    (7, 2, 257, 33, None, 3, 2, "bf16"),                  # level step 2
+]
+
+
+@pytest.mark.parametrize("K,H,W,D,b,dmin,dstep,st", SMALL)
+@pytest.mark.parametrize("mode", ["soft", "hard"])
+def test_small_cases_teacher_forced(K, H, W, D, b, dmin, dstep, st, mode):
+    case = random_case(K, H, W, D, baselines=b, d_min=dmin, d_step=dstep, storage=st, mode=mode,
+                       seed=K * 1000 + W)
+    _say(f"small K={K} H={H} W={W} D={D} b={b} d=({dmin},{dstep}) {st} {mode}")
+    teacher_forced(case, 3)
+
+
+def test_config2_full_size_fp32():
+    fr = S.make_frame(S.config_spec(2))
+    case = Case.from_frame(fr, storage="f32")
+    _say("config2 640x480 K=5 D=64 fp32 soft teacher-forced x10 (full frame)")
+    teacher_forced(case, 10)
+
+
+def test_config3_fp16_sampled_rows():
+    fr = S.make_frame(S.config_spec(3))
+    case = Case.from_frame(fr, storage="f16")
+    _say("config3 1280x960 K=5 D=128 fp16 teacher-forced x10, rows 472..488")
+    teacher_forced(case, 10, rows=(472, 488))
+
+
+def test_config5_bf16_sampled_rows():
+    fr = S.make_frame(S.config_spec(5))
+    case = Case.from_frame(fr, storage="bf16")
+    _say("config5 1920x1080 K=9 D=192 bf16 teacher-forced x12, rows 530..542")
+    teacher_forced(case, 12, rows=(530, 542))
+
+
+def test_resume_is_bitwise(config1):
+    case = Case.from_frame(config1, storage="f32")
+    _say("config1 resume: iterate(3)+iterate(2) vs iterate(5)")
+    a = GpuRun(case)
+    a.iterate(3)
+    a.iterate(2)
+    qa, da, La = a.state()
+    a.close()
+    b = GpuRun(case)
+    b.iterate(5)
+    qb, db, Lb = b.state()
+    b.close()
+    assert np.array_equal(qa, qb) and np.array_equal(da, db) and np.array_equal(La, Lb)
+
+
+def test_host_and_device_inputs_agree(config1):
+    case = Case.from_frame(config1, storage="f16")
+    _say("config1 host vs device inputs, fp16")
+    a = GpuRun(case, device_inputs=True)
+    a.iterate(4)
+    ra = a.refocus()
+    a.close()
+    b = GpuRun(case, device_inputs=False)
+    b.iterate(4)
+    rb = b.refocus()
+    b.close()
+    for x, y in zip(ra, rb):
+        assert np.array_equal(x, y)
+
+
+def test_warm_start_uses_given_weights(config1):
+    case = Case.from_frame(config1, storage="f32")
+    _say("config1 warm start")
+    qw = np.random.default_rng(5).uniform(0, 1, (case.K, case.H, case.W)).astype(np.float32)
+    run = GpuRun(case, q_warm=qw)
+    q0, _, _ = run.state(with_d=False)
+    assert np.array_equal(q0, qw)
+    run.iterate(1)
+    q1, d1, L1 = run.state()
+    run.close()
+    op = case.oracle_params()
+    f = O.descriptors(op, case.views)
+    rho, _ = O.ray_prior(op, case.S_P, case.mu_T)
+    ref = O.em_iteration(op, f, rho, case.mu_T, qw.astype(np.float64))
+    tie = near_tie(ref["E1"], ref["E2"])
+    assert np.all((d1 == ref["d_idx"]) | tie)
+
+
+def test_frame_objective_is_sum_of_pixels(config1):
+    case = Case.from_frame(config1, storage="f32")
+    _say("config1 frame objective")
+    run = GpuRun(case)
+    obj = run.iterate(3, objective=True)
+    q, d, L = run.state()
+    run.close()
+    assert abs(obj[-1] - L.astype(np.float64).sum()) <= 1e-9 * abs(obj[-1])
+    assert np.all(np.diff(obj) >= -1e-6 * np.abs(obj[1:]))
+
+
+def test_median_refocus(config1):
+    case = Case.from_frame(config1, storage="f32")
+    _say("config1 refocus with 3x3 median")
+    run = GpuRun(case)
+    run.iterate(2)
+    rgb0, d, q, hole = run.refocus(median=0)
+    rgb3, _, _, _ = run.refocus(median=3)
+    run.close()
+    op = case.oracle_params()
+    want = O.median3(op, rgb0.astype(np.float64))
+    assert np.array_equal(rgb3.astype(np.float64), want.astype(np.float32).astype(np.float64))
+
+
+def test_device_value_validation(config1):
+    import torch
+    import paper_2003_11076_amd as LF
+    case = Case.from_frame(config1, storage="f32")
+    _say("device-side S_P validation")
+    sp = case.S_P.copy()
+    sp[1, 5, 7] = np.nan
+    dev = torch.device("cuda")
+    tv = torch.from_numpy(case.views).to(dev)
+    ts = torch.from_numpy(sp).to(dev)
+    tm = torch.from_numpy(case.mu_T).to(dev)
+    with pytest.raises(LF.LFError) as e:
+        LF.lf_em_init(case.api_params(LF.LF_INPUTS_ON_DEVICE), tv, ts, tm,
+                      hip_stream=torch.cuda.current_stream().cuda_stream)
+    assert e.value.status == LF.LF_EINVAL
+
+
+def test_state_calls_out_of_order(config1):
+    import paper_2003_11076_amd as LF
+    case = Case.from_frame(config1, storage="f32")
+    _say("ESTATE paths")
+    run = GpuRun(case)
+    rgb = np.zeros((case.H, case.W, 3), np.float32)
+    with pytest.raises(LF.LFError) as e:
+        LF.lf_refocus(run.ctx, rgb)
+    assert e.value.status == LF.LF_ESTATE
+    with pytest.raises(LF.LFError) as e:
+        LF.lf_em_state(run.ctx, d_idx=np.zeros((case.H, case.W), np.int32))
+    assert e.value.status == LF.LF_ESTATE
+    run.close()
+
+
+def test_free_running_agreement(config1):
+    case = Case.from_frame(config1, storage="f32")
+    _say("config1 free-running agreement")
+    run = GpuRun(case)
+    run.iterate(case.n_iters)
+    rgb, d, q, hole = run.refocus()
+    run.close()
+    r = O.reconstruct(case.oracle_params(), case.views, case.S_P, case.mu_T, case.n_iters)
+    agree = (d == r["d_idx"]).mean()
+    print(f"free-running d agreement {agree:.6f}, q max-abs {np.abs(q - r['q']).max():.3g}")
+    assert agree >= 0.999

@@ -377,3 +377,14 @@ def test_hard_assignment_tie_is_static():
     out = O.em_iteration(p, f, np.full((K, H, W), 0.5), np.zeros((H, W), np.float32), np.ones((K, H, W)))
     assert np.all(out["q"] == 1.0)
     np.testing.assert_allclose(out["L"], math.log(1.05) + K * math.log(0.5), rtol=1e-14)
+
+
+def test_median3_matches_scipy():
+    from scipy.ndimage import median_filter
+    H, W = 9, 14
+    p = _params(2, H, W, [0, 1], 4, 100.0, ref=0)
+    rgb = RNG.uniform(0, 1, (H, W, 3))
+    rgb[2, 3] = rgb[2, 4]                      # repeated values
+    out = O.median3(p, rgb)
+    for c in range(3):
+        assert np.array_equal(out[:, :, c], median_filter(rgb[:, :, c], size=3, mode="nearest"))
