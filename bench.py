@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM traffic counters)")
     return ap.parse_args()
 
 
@@ -116,6 +118,15 @@ def main():
             ev[1].record(stream)
         LF.lf_refocus(ctx, rgb, d_idx, q, hole, 0)
 
+    if args.calib_copy:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the
+        # counters read for the EM kernel
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log(args, f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
         step()

@@ -62,6 +62,8 @@ typedef int32_t lf_status;
 /* flags */
 #define LF_INPUTS_ON_DEVICE   0x1u  /* views, S_P, mu_T, q_warm are device pointers   */
 #define LF_OUTPUTS_ON_DEVICE  0x2u  /* rgb, d_idx, q, hole, L_pix are device pointers  */
+#define LF_EXHAUSTIVE_SWEEP   0x4u  /* evaluate every level with the two-pass spread:   */
+                                    /* same results, slower; for verification          */
 
 typedef struct {
     int32_t K, H, W;            /* views, rows, columns; 2 <= K <= 16                 */
@@ -77,7 +79,8 @@ typedef struct {
     float tau_init;             /* first-iteration threshold: static iff rho >= tau (0.7) */
     int32_t storage;            /* LF_F32, LF_F16, LF_BF16                            */
     int32_t mode;               /* LF_SOFT, LF_HARD                                   */
-    uint32_t flags;             /* LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE         */
+    uint32_t flags;             /* LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE |       */
+                                /* LF_EXHAUSTIVE_SWEEP                                */
 } lf_params;
 
 typedef struct lf_ctx lf_ctx;   /* opaque; owns all device buffers of one frame shape */
@@ -175,6 +178,76 @@ void lf_em_destroy(lf_ctx *c);
 
 /* lf_last_error -- message of the last failing call on this thread ("" if none). */
 const char *lf_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Frame server: continuous batching of frames from many camera streams.     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct lf_server lf_server;   /* opaque */
+
+/* Called once per submitted frame from the server's service thread, after
+ * the frame's outputs are in the caller's buffers (status LF_OK) or when the
+ * frame failed (LF_EDEVICE).  Must not block for long; may call
+ * lf_submit_frame but not lf_server_drain or lf_server_destroy. */
+typedef void (*lf_done_fn)(int64_t frame_id, lf_status status, void *user);
+
+typedef struct {
+    int64_t submitted, completed, failed, rejected;  /* rejected: LF_EAGAIN at submission   */
+    int64_t batches;                                  /* device launches of admitted frames   */
+    double mean_batch_frames;                         /* frames per launch                    */
+    double p50_ms, p99_ms, mean_ms, max_ms;           /* submission -> outputs delivered      */
+    double wall_s;                                    /* first submission -> last completion  */
+    double frames_per_s;                              /* completed / wall_s                   */
+    int64_t hbm_in_use, hbm_peak;                     /* bytes of the HBM arena               */
+} lf_server_stats_t;
+
+/*
+ * lf_server_create -- start a server.  The whole method of Sec. III runs per
+ * frame (descriptors, ray prior, n_iters EM iterations, refocus, Eq. 2) for
+ * frames of any size, view count (K <= 9), level count and storage, with the
+ * previous frame's weights of the same stream (same K, H, W) as its first
+ * weights instead of the 0.7 threshold (warm start).
+ *   hbm_budget_bytes : device arena (>= 64 KiB) every admitted frame's buffers and every
+ *                      stream's warm-start weights come from; frames wait for
+ *                      admission until theirs fit.
+ *   max_streams      : stream ids are 0..max_streams-1.
+ *   n_iters          : EM iterations per frame.
+ *   staging_bytes    : pinned host staging for submitted frames (0: the smaller
+ *                      of the budget and 1 GiB); when full, submission returns
+ *                      LF_EAGAIN.
+ * Errors: LF_EINVAL, LF_ENOMEM (arena allocation), LF_EDEVICE.
+ */
+lf_status lf_server_create(lf_server **out, size_t hbm_budget_bytes, int32_t max_streams, int32_t n_iters,
+                           size_t staging_bytes);
+
+/*
+ * lf_submit_frame -- queue one frame of stream `stream_id`.  Host inputs
+ * (views, S_P, mu_T as in lf_em_init) are copied before return.  Outputs are
+ * written to the caller's host buffers before `done` runs: rgb_out float
+ * [H][W][3] (required), d_out int32 [H][W] (nullable), q_out float [K][H][W]
+ * (nullable).  Frames of one stream complete in submission order; frames of
+ * different streams run concurrently, batched into shared launches as they
+ * are admitted.  Results do not depend on what else is running.  The
+ * output buffers must stay valid until `done` has run for the frame (or
+ * lf_server_drain / lf_server_destroy has returned): the server writes them
+ * from its service thread.
+ * Errors: LF_EINVAL (as lf_em_init, plus K > 9, stream_id out of range, any
+ * flag set, a frame larger than the arenas), LF_EAGAIN (staging full), or
+ * the error a previous device failure left.
+ */
+lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, const uint8_t *views,
+                          const float *S_P, const float *mu_T, float *rgb_out, int32_t *d_out, float *q_out,
+                          lf_done_fn done, void *user, int64_t *frame_id);
+
+/* lf_server_drain -- block until every submitted frame has completed. */
+lf_status lf_server_drain(lf_server *s);
+
+/* lf_server_stats / lf_server_reset_stats -- counters and latency percentiles. */
+lf_status lf_server_stats(lf_server *s, lf_server_stats_t *out);
+lf_status lf_server_reset_stats(lf_server *s);
+
+/* lf_server_destroy -- drain, stop the service thread, free everything. */
+void lf_server_destroy(lf_server *s);
 
 #ifdef __cplusplus
 }

@@ -81,10 +81,10 @@ def lib():
         L.lfo_derive_lambda.argtypes = [P]
         L.lfo_derive_lambda.restype = ctypes.c_double
         L.lfo_descriptors.argtypes = [P, u8, dp, i32, i32]
-        L.lfo_ray_prior.argtypes = [P, fp, fp, dp, dp, i32, i32]
-        L.lfo_em_iteration.argtypes = [P, ctypes.c_double, dp, dp, fp, dp, dp, i32p, dp, dp, dp, i32, i32]
+        L.lfo_ray_prior.argtypes = [P, fp, fp, dp, dp, dp, i32, i32]
+        L.lfo_em_iteration.argtypes = [P, ctypes.c_double, dp, dp, dp, fp, dp, dp, i32p, dp, dp, dp, i32, i32]
         L.lfo_refocus.argtypes = [P, u8, i32p, dp, dp, u8, i32, i32]
-        L.lfo_reconstruct.argtypes = [P, u8, fp, fp, dp, i32, i32, i32, dp, dp, dp, dp, i32p, dp, dp, dp, u8]
+        L.lfo_reconstruct.argtypes = [P, u8, fp, fp, dp, i32, i32, i32, dp, dp, dp, dp, dp, i32p, dp, dp, dp, u8]
         L.lfo_reconstruct.restype = i32
         L.lfo_threads.restype = i32
         L.lfo_median3.argtypes = [P, dp, dp, i32, i32]
@@ -125,31 +125,42 @@ def descriptors(p: Params, views, rows=None) -> np.ndarray:
     return f
 
 
+class RayPrior(tuple):
+    """(rho, q0) with the dynamic prior omr = 1 - rho as an attribute."""
+    omr: np.ndarray
+
+
 def ray_prior(p: Params, S_P, mu_T, rows=None):
-    """(rho, q0): [K][H][W] float64 each."""
+    """(rho, q0): [K][H][W] float64 each; `.omr` holds 1 - rho interpolated
+    from 1 - S_P (accurate where rho is close to 1)."""
     sp, mu = _c(S_P, np.float32), _c(mu_T, np.float32)
     rho = np.zeros((p.K, p.H, p.W))
+    omr = np.ones((p.K, p.H, p.W))
     q0 = np.zeros((p.K, p.H, p.W))
     y0, y1 = _rows(p, rows)
     lib().lfo_ray_prior(ctypes.byref(p), _ptr(sp, ctypes.c_float), _ptr(mu, ctypes.c_float),
-                        _ptr(rho, ctypes.c_double), _ptr(q0, ctypes.c_double), y0, y1)
-    return rho, q0
+                        _ptr(rho, ctypes.c_double), _ptr(omr, ctypes.c_double), _ptr(q0, ctypes.c_double), y0, y1)
+    out = RayPrior((rho, q0))
+    out.omr = omr
+    return out
 
 
-def em_iteration(p: Params, f, rho, mu_T, q_in, lam=None, rows=None) -> dict:
-    """One EM iteration (M-step, then E-step) from weights q_in.
+def em_iteration(p: Params, f, rho, mu_T, q_in, lam=None, rows=None, omr=None) -> dict:
+    """One EM iteration (M-step, then E-step) from weights q_in.  omr is the
+    dynamic prior 1 - rho (taken as 1 - rho when None).
 
     Returns q [K][H][W], d_idx [H][W], L [H][W] (per-pixel objective after the
     E-step), E1/E2 [H][W] (smallest and second smallest M-step energies)."""
     lam = lam_of(p) if lam is None else float(lam)
     f, rho, mu, q_in = _c(f, np.float64), _c(rho, np.float64), _c(mu_T, np.float32), _c(q_in, np.float64)
+    omr = None if omr is None else _c(omr, np.float64)
     out = {
         "q": np.zeros((p.K, p.H, p.W)), "d_idx": np.zeros((p.H, p.W), np.int32),
         "L": np.zeros((p.H, p.W)), "E1": np.zeros((p.H, p.W)), "E2": np.zeros((p.H, p.W)),
     }
     y0, y1 = _rows(p, rows)
     D = ctypes.c_double
-    lib().lfo_em_iteration(ctypes.byref(p), lam, _ptr(f, D), _ptr(rho, D), _ptr(mu, ctypes.c_float),
+    lib().lfo_em_iteration(ctypes.byref(p), lam, _ptr(f, D), _ptr(rho, D), _ptr(omr, D), _ptr(mu, ctypes.c_float),
                            _ptr(q_in, D), _ptr(out["q"], D), _ptr(out["d_idx"], ctypes.c_int32),
                            _ptr(out["L"], D), _ptr(out["E1"], D), _ptr(out["E2"], D), y0, y1)
     return out
@@ -184,6 +195,7 @@ def reconstruct(p: Params, views, S_P, mu_T, n_iters, q_warm=None, rows=None) ->
     qw = None if q_warm is None else _c(q_warm, np.float64)
     f = np.zeros((K, H, W, 2))
     rho = np.zeros((K, H, W))
+    omr = np.ones((K, H, W))
     qa = np.zeros((K, H, W))
     qb = np.zeros((K, H, W))
     d = np.zeros((H, W), np.int32)
@@ -195,7 +207,7 @@ def reconstruct(p: Params, views, S_P, mu_T, n_iters, q_warm=None, rows=None) ->
     D = ctypes.c_double
     th = lib().lfo_reconstruct(ctypes.byref(p), _ptr(v, ctypes.c_uint8), _ptr(sp, ctypes.c_float),
                                _ptr(mu, ctypes.c_float), _ptr(qw, D), int(n_iters), y0, y1,
-                               _ptr(f, D), _ptr(rho, D), _ptr(qa, D), _ptr(qb, D),
+                               _ptr(f, D), _ptr(rho, D), _ptr(omr, D), _ptr(qa, D), _ptr(qb, D),
                                _ptr(d, ctypes.c_int32), _ptr(L, D), _ptr(Ls, D), _ptr(rgb, D),
                                _ptr(hole, ctypes.c_uint8))
     return {"q": qa, "d_idx": d, "L": L, "L_sum": Ls[:n_iters], "rgb": rgb, "hole": hole,

@@ -152,25 +152,34 @@ static double sample_row(const double *row, int W, int stride, double u)
 /* first-iteration weights by thresholding it (Sec. III-F).                  */
 /* ------------------------------------------------------------------------ */
 
-void lfo_ray_prior(const lfo_params *p, const float *S_P, const float *mu_T, double *rho, double *q0,
-                   int32_t y0, int32_t y1)
+/* rho is the static prior of the ray into view k; omr = 1 - rho, the dynamic
+ * prior, is interpolated from 1 - S_P directly so that it keeps its relative
+ * accuracy when rho is close to 1 (the E-step takes its logarithm). */
+void lfo_ray_prior(const lfo_params *p, const float *S_P, const float *mu_T, double *rho, double *omr,
+                   double *q0, int32_t y0, int32_t y1)
 {
     const int K = p->K, H = p->H, W = p->W;
 #pragma omp parallel for schedule(static)
     for (int y = y0; y < y1; ++y) {
         double *row = (double *)malloc(sizeof(double) * (size_t)W);
+        double *row1m = (double *)malloc(sizeof(double) * (size_t)W);
         for (int k = 0; k < K; ++k) {
             const float *sp = S_P + ((size_t)k * H + y) * W;
-            for (int x = 0; x < W; ++x) row[x] = lfo_round_storage((double)sp[x], p->storage);
+            for (int x = 0; x < W; ++x) {
+                row[x] = lfo_round_storage((double)sp[x], p->storage);
+                row1m[x] = 1.0 - row[x];
+            }
             for (int x = 0; x < W; ++x) {
                 double u = (double)x - p->baselines[k] * (double)mu_T[(size_t)y * W + x];
                 double r = sample_row(row, W, 1, u);
                 size_t i = ((size_t)k * H + y) * W + x;
                 rho[i] = r;
+                if (omr) omr[i] = sample_row(row1m, W, 1, u);
                 if (q0) q0[i] = (r >= p->tau) ? 1.0 : 0.0;
             }
         }
         free(row);
+        free(row1m);
     }
 }
 
@@ -228,7 +237,7 @@ static double weighted_spread(int K, const double fk[][2], const double *q, doub
 }
 
 void lfo_em_iteration(const lfo_params *p, double lambda, const double *f, const double *rho,
-                      const float *mu_T, const double *q_in, double *q_out, int32_t *d_idx,
+                      const double *omr, const float *mu_T, const double *q_in, double *q_out, int32_t *d_idx,
                       double *L_pix, double *E1, double *E2, int32_t y0, int32_t y1)
 {
     const int K = p->K, H = p->H, W = p->W, D = p->D;
@@ -263,8 +272,9 @@ void lfo_em_iteration(const lfo_params *p, double lambda, const double *f, const
                 double a = fk[k][0] - m[0], b = fk[k][1] - m[1];
                 double e = a * a + b * b;
                 double r = rho[(size_t)k * H * W + pix];
+                double r1 = omr ? omr[(size_t)k * H * W + pix] : 1.0 - r;
                 double a1 = (r > 0.0 ? log(r) : -INFINITY) + lambda - bp * e;
-                double a0 = (r < 1.0 ? log(1.0 - r) : -INFINITY);
+                double a0 = (r1 > 0.0 ? log(r1) : -INFINITY);
                 double qk;
                 if (p->mode == 1) {
                     qk = (a1 >= a0) ? 1.0 : 0.0;
@@ -332,19 +342,19 @@ void lfo_refocus(const lfo_params *p, const uint8_t *views, const int32_t *d_idx
 
 int32_t lfo_reconstruct(const lfo_params *p, const uint8_t *views, const float *S_P, const float *mu_T,
                         const double *q_warm, int32_t n_iters, int32_t y0, int32_t y1,
-                        double *f, double *rho, double *q_a, double *q_b,
+                        double *f, double *rho, double *omr, double *q_a, double *q_b,
                         int32_t *d_idx, double *L_pix, double *L_sum, double *rgb, uint8_t *hole)
 {
     const int K = p->K, H = p->H, W = p->W;
     double lambda = isnan(p->lambda) ? lfo_derive_lambda(p) : p->lambda;
     lfo_descriptors(p, views, f, y0, y1);
-    lfo_ray_prior(p, S_P, mu_T, rho, q_a, y0, y1);
+    lfo_ray_prior(p, S_P, mu_T, rho, omr, q_a, y0, y1);
     if (q_warm)
         for (int k = 0; k < K; ++k)
             memcpy(q_a + ((size_t)k * H + y0) * W, q_warm + ((size_t)k * H + y0) * W,
                    sizeof(double) * (size_t)(y1 - y0) * W);
     for (int t = 0; t < n_iters; ++t) {
-        lfo_em_iteration(p, lambda, f, rho, mu_T, q_a, q_b, d_idx, L_pix, NULL, NULL, y0, y1);
+        lfo_em_iteration(p, lambda, f, rho, omr, mu_T, q_a, q_b, d_idx, L_pix, NULL, NULL, y0, y1);
         if (L_sum) {
             double s = 0.0;
             for (int y = y0; y < y1; ++y)

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "LF_OK", 1: "LF_EINVAL", 2: "LF_ENOMEM", 3: "LF_EDEVICE", 4: 
 LF_MAX_VIEWS = 16
 LF_F32, LF_F16, LF_BF16 = 0, 1, 2
 LF_SOFT, LF_HARD = 0, 1
-LF_INPUTS_ON_DEVICE, LF_OUTPUTS_ON_DEVICE = 0x1, 0x2
+LF_INPUTS_ON_DEVICE, LF_OUTPUTS_ON_DEVICE, LF_EXHAUSTIVE_SWEEP = 0x1, 0x2, 0x4
 STORAGE = {"f32": LF_F32, "f16": LF_F16, "bf16": LF_BF16}
 
 
@@ -85,18 +85,29 @@ def lib():
     return _lib
 
 
+class lf_server_stats_t(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+        ("rejected", ctypes.c_int64), ("batches", ctypes.c_int64), ("mean_batch_frames", ctypes.c_double),
+        ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+        ("max_ms", ctypes.c_double), ("wall_s", ctypes.c_double), ("frames_per_s", ctypes.c_double),
+        ("hbm_in_use", ctypes.c_int64), ("hbm_peak", ctypes.c_int64),
+    ]
+
+
+lf_done_fn = ctypes.CFUNCTYPE(None, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p)
+
+
 def _bind_server(L):
-    if not hasattr(L, "lf_server_create"):
-        return
     vp, i32, P = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(lf_params)
-    L.lf_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, i32, i32, vp]
-    L.lf_submit_frame.argtypes = [vp, i32, P, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]
-    L.lf_server_poll.argtypes = [vp, ctypes.POINTER(i32)]
+    L.lf_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, i32, i32, ctypes.c_size_t]
+    L.lf_submit_frame.argtypes = [vp, i32, P, vp, vp, vp, vp, vp, vp, lf_done_fn, vp, ctypes.POINTER(ctypes.c_int64)]
     L.lf_server_drain.argtypes = [vp]
-    L.lf_server_stats.argtypes = [vp, vp]
+    L.lf_server_stats.argtypes = [vp, ctypes.POINTER(lf_server_stats_t)]
+    L.lf_server_reset_stats.argtypes = [vp]
     L.lf_server_destroy.argtypes = [vp]
     L.lf_server_destroy.restype = None
-    for f in ("lf_server_create", "lf_submit_frame", "lf_server_poll", "lf_server_drain", "lf_server_stats"):
+    for f in ("lf_server_create", "lf_submit_frame", "lf_server_drain", "lf_server_stats", "lf_server_reset_stats"):
         getattr(L, f).restype = i32
 
 
@@ -161,3 +172,39 @@ def lf_em_intermediates(ctx, feat=None, rho=None):
 def lf_em_destroy(ctx):
     if ctx:
         lib().lf_em_destroy(ctx)
+
+
+def lf_server_create(hbm_budget_bytes, max_streams, n_iters, staging_bytes=0) -> int:
+    out = ctypes.c_void_p()
+    _check(lib().lf_server_create(ctypes.byref(out), int(hbm_budget_bytes), int(max_streams), int(n_iters),
+                                  int(staging_bytes)))
+    return out.value
+
+
+def lf_submit_frame(srv, stream_id, p: lf_params, views, S_P, mu_T, rgb_out, d_out=None, q_out=None, done=None,
+                    user=None) -> int:
+    """`done` must be an lf_done_fn the caller keeps alive until it has run."""
+    fid = ctypes.c_int64(-1)
+    _check(lib().lf_submit_frame(srv, int(stream_id), ctypes.byref(p), addr(views), addr(S_P), addr(mu_T),
+                                 addr(rgb_out), addr(d_out), addr(q_out), done if done is not None else lf_done_fn(),
+                                 user, ctypes.byref(fid)))
+    return fid.value
+
+
+def lf_server_drain(srv):
+    return _check(lib().lf_server_drain(srv))
+
+
+def lf_server_stats(srv) -> lf_server_stats_t:
+    st = lf_server_stats_t()
+    _check(lib().lf_server_stats(srv, ctypes.byref(st)))
+    return st
+
+
+def lf_server_reset_stats(srv):
+    return _check(lib().lf_server_reset_stats(srv))
+
+
+def lf_server_destroy(srv):
+    if srv:
+        lib().lf_server_destroy(srv)

@@ -1,7 +1,7 @@
 // Host side of the C ABI declared in include/lf_em.h: parameter validation,
 // device buffer plan, precision and view-count dispatch, launches and copies.
 #include "lf_em.h"
-#include "lf_em_kernels.h"
+#include "lf_frame_kernels.h"
 #include "lf_internal.h"
 
 #include <cmath>
@@ -69,7 +69,8 @@ lf_status validate_params(const lf_params *p) {
     if (!(p->tau_init >= 0.0f && p->tau_init <= 1.0f)) return set_error(LF_EINVAL, "tau_init outside [0,1]");
     if (p->storage < LF_F32 || p->storage > LF_BF16) return set_error(LF_EINVAL, "storage=%d unknown", p->storage);
     if (p->mode != LF_SOFT && p->mode != LF_HARD) return set_error(LF_EINVAL, "mode=%d unknown", p->mode);
-    if (p->flags & ~(LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE)) return set_error(LF_EINVAL, "unknown flags");
+    if (p->flags & ~(LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE | LF_EXHAUSTIVE_SWEEP))
+        return set_error(LF_EINVAL, "unknown flags");
     return LF_OK;
 }
 
@@ -130,33 +131,17 @@ size_t em_window_pairs(const lf_params *p, const Geometry &g, int tile) {
 
 size_t pair_bytes(int storage) { return storage == LF_F32 ? 8 : 4; }
 
-// ---------------------------------------------------------------------------
-// Kernel dispatch over (K, storage, integer/fractional shifts).
-// ---------------------------------------------------------------------------
-using EmKernel = void (*)(EmArgs);
+// LDS record of one staged position: the pair plus |f|^2 (FP32 padded to 16 B).
+size_t rec_bytes(int storage) { return storage == LF_F32 ? 16 : 8; }
 
-template <int K, int ST>
-static EmKernel pick_em2(bool frac) {
-    return frac ? (EmKernel)lf_em_kernel<K, ST, true> : (EmKernel)lf_em_kernel<K, ST, false>;
-}
-
-template <int K>
-static EmKernel pick_em1(int st, bool frac) {
+// ---------------------------------------------------------------------------
+// Kernel dispatch over (K, storage, integer/fractional shifts, sweep kind).
+// ---------------------------------------------------------------------------
+EmKernel pick_em(int K, int st, bool frac, bool exh) {
     switch (st) {
-        case LF_F32: return pick_em2<K, 0>(frac);
-        case LF_F16: return pick_em2<K, 1>(frac);
-        default: return pick_em2<K, 2>(frac);
-    }
-}
-
-EmKernel pick_em(int K, int st, bool frac) {
-    switch (K) {
-#define LF_CASE(n) \
-    case n: return pick_em1<n>(st, frac);
-        LF_CASE(2) LF_CASE(3) LF_CASE(4) LF_CASE(5) LF_CASE(6) LF_CASE(7) LF_CASE(8) LF_CASE(9)
-        LF_CASE(10) LF_CASE(11) LF_CASE(12) LF_CASE(13) LF_CASE(14) LF_CASE(15) LF_CASE(16)
-#undef LF_CASE
-        default: return nullptr;
+        case LF_F32: return pick_em_f32(K, frac, exh);
+        case LF_F16: return pick_em_f16(K, frac, exh);
+        default: return pick_em_bf16(K, frac, exh);
     }
 }
 
@@ -180,12 +165,13 @@ hipError_t launch_descriptors(const lf_params *p, const uint8_t *views, void *fe
 }
 
 hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *mu_T, const float *q_warm,
-                            float *rho, float *q, uint32_t *bad, int check, hipStream_t s) {
+                            float *rho, float *omr, float *q, uint32_t *bad, int check, hipStream_t s) {
     PriorArgs a{};
     a.S_P = S_P;
     a.mu_T = mu_T;
     a.q_warm = q_warm;
     a.rho = rho;
+    a.omr = omr;
     a.q = q;
     a.bad = bad;
     a.K = p->K;
@@ -202,6 +188,30 @@ hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *m
 
 EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
     EmArgs a{};
+    // kernel view order: the reference first, then the others in array order
+    int n = 0;
+    a.perm[n++] = p->ref;
+    for (int k = 0; k < p->K; ++k)
+        if (k != p->ref) a.perm[n++] = k;
+    for (int k = 0; k < p->K; ++k) {
+        a.bi[k] = g.bi[a.perm[k]];
+        a.b[k] = p->baselines[a.perm[k]];
+    }
+    // |d - mu| beyond which exp(-(d-mu)^2/(2 sigma^2)) < gamma * 2^-28, so that
+    // gamma + g rounds to gamma in FP32 (half an ulp of gamma is >= gamma 2^-25)
+    {
+        const double c2 = 1.4426950408889634 / (2.0 * (double)p->sigma * p->sigma);
+        const double e = 28.0 - std::log2((double)p->gamma);
+        a.prior_T = e > 0.0 ? (float)std::sqrt(e / c2) : -1.0f;
+    }
+    // bound of |one-pass energy - two-pass energy| in FP32 (see the kernel):
+    // beta' * (16K + 64) u * S + 64 u (|ln gamma| + 1), u = 2^-24
+    {
+        const double u = std::ldexp(1.0, -24);
+        a.margin_k = (float)((16.0 * p->K + 64.0) * u);
+        a.margin_c = (float)(64.0 * u * (std::max(std::fabs(std::log((double)p->gamma)),
+                                                  std::log1p((double)p->gamma)) + 1.0));
+    }
     a.H = p->H;
     a.W = p->W;
     a.D = p->D;
@@ -216,15 +226,11 @@ EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
     const double s2 = 2.0 * (double)p->sigma * p->sigma;
     a.c_exp2 = (float)(1.4426950408889634 / s2);
     a.c_exp = (float)(1.0 / s2);
-    for (int k = 0; k < p->K; ++k) {
-        a.bi[k] = g.bi[k];
-        a.b[k] = p->baselines[k];
-    }
     return a;
 }
 
 hipError_t launch_em(const lf_params *p, const Geometry &g, EmArgs a, int tile, size_t lds, hipStream_t s) {
-    EmKernel kern = pick_em(p->K, p->storage, g.frac);
+    EmKernel kern = pick_em(p->K, p->storage, g.frac, (p->flags & LF_EXHAUSTIVE_SWEEP) != 0);
     a.tile = tile;
     dim3 block(tile), grid((p->W + tile - 1) / tile, p->H);
     a.n_blocks = grid.x * grid.y;
@@ -265,7 +271,7 @@ hipError_t launch_median3(const lf_params *p, const float *in, float *out, hipSt
 int choose_tile(const lf_params *p, const Geometry &g, size_t lds_limit, size_t *lds_out) {
     int tile = p->W >= 128 ? 128 : 64;
     for (;;) {
-        const size_t lds = em_window_pairs(p, g, tile) * pair_bytes(p->storage);
+        const size_t lds = em_window_pairs(p, g, tile) * rec_bytes(p->storage);
         if (lds <= lds_limit || tile == 64) {
             *lds_out = lds;
             return lds <= lds_limit ? tile : 0;
@@ -294,7 +300,7 @@ struct lf_ctx {
     const uint8_t *views;   // the frame's views on the device (own copy or caller's)
     const float *mu_dev;    // the frame's mu_T on the device (own copy or caller's)
     void *feat;
-    float *rho, *q, *lpix, *rgb, *rgb_med;
+    float *rho, *omr, *q, *lpix, *rgb, *rgb_med;
     int32_t *d_idx;
     uint8_t *hole;
     double *obj;
@@ -333,6 +339,7 @@ static lf_status ctx_alloc(lf_ctx *c) {
     }
     plan.add(&c->feat, KHW * pair_bytes(p.storage));
     plan.add(&c->rho, KHW * 4);
+    plan.add(&c->omr, KHW * 4);
     plan.add(&c->q, KHW * 4);
     plan.add(&c->d_idx, HW * 4);
     plan.add(&c->lpix, HW * 4);
@@ -375,7 +382,8 @@ static lf_status ctx_load(lf_ctx *c, const uint8_t *views, const float *S_P, con
         LF_HIP(hipMemsetAsync(c->bad, 0, 4, c->stream), "clear counter");
     }
     LF_HIP(launch_descriptors(&p, c->views, c->feat, c->stream), "descriptor launch");
-    LF_HIP(launch_ray_prior(&p, sp, mu, qw, c->rho, c->q, c->bad, dev_in ? 1 : 0, c->stream), "ray prior launch");
+    LF_HIP(launch_ray_prior(&p, sp, mu, qw, c->rho, c->omr, c->q, c->bad, dev_in ? 1 : 0, c->stream),
+           "ray prior launch");
     if (dev_in) {
         LF_HIP(hipMemcpyAsync(c->h_bad, c->bad, 4, hipMemcpyDeviceToHost, c->stream), "copy counter");
         LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
@@ -481,6 +489,7 @@ lf_status lf_em_iterate(lf_ctx *c, int32_t n_iters, double *objective) {
     EmArgs a = make_em_args(&c->p, c->g, c->lambda);
     a.feat = c->feat;
     a.rho = c->rho;
+    a.omr = c->omr;
     a.mu_T = c->mu_dev;
     a.q = c->q;
     a.d_idx = c->d_idx;
@@ -490,6 +499,7 @@ lf_status lf_em_iterate(lf_ctx *c, int32_t n_iters, double *objective) {
     while (done < n_iters) {
         const int n = std::min(kMaxItersPerLaunch, n_iters - done);
         a.n_iters = n;
+        a.seed_from_d = (c->iters + done) > 0;   // start the sweep at the last level
         LF_HIP(launch_em(&c->p, c->g, a, c->tile, c->lds, c->stream), "EM launch");
         if (objective) {
             LF_HIP(hipMemcpyAsync(c->h_obj, c->obj, (size_t)n * c->n_blocks * 8, hipMemcpyDeviceToHost, c->stream),

@@ -1,0 +1,29 @@
+// Instantiation of the EM kernel for every view count, shift kind and sweep
+// kind of one storage precision.  Each storage precision is compiled in its
+// own translation unit (lf_em_f32.hip, lf_em_f16.hip, lf_em_bf16.hip).
+#pragma once
+
+#include "lf_em_kernels.h"
+#include "lf_internal.h"
+
+namespace lfem {
+
+template <int K, int ST>
+static EmKernel pick_em_k(bool frac, bool exh) {
+    if (exh) return frac ? (EmKernel)lf_em_kernel<K, ST, true, true> : (EmKernel)lf_em_kernel<K, ST, false, true>;
+    return frac ? (EmKernel)lf_em_kernel<K, ST, true, false> : (EmKernel)lf_em_kernel<K, ST, false, false>;
+}
+
+template <int ST>
+static EmKernel pick_em_storage(int K, bool frac, bool exh) {
+    switch (K) {
+#define LF_CASE(n) \
+    case n: return pick_em_k<n, ST>(frac, exh);
+        LF_CASE(2) LF_CASE(3) LF_CASE(4) LF_CASE(5) LF_CASE(6) LF_CASE(7) LF_CASE(8) LF_CASE(9)
+        LF_CASE(10) LF_CASE(11) LF_CASE(12) LF_CASE(13) LF_CASE(14) LF_CASE(15) LF_CASE(16)
+#undef LF_CASE
+        default: return nullptr;
+    }
+}
+
+}  // namespace lfem

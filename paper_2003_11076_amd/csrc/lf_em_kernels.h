@@ -1,15 +1,10 @@
-// Device code of the EM static-background reconstruction for gfx950.
-//
-// Each kernel is one step of the per-pixel method (Sec. III-F: every pixel is
-// processed independently):
-//   lf_descriptors_kernel  3x3 Sobel responses of R+G+B (Sec. III-C)
-//   lf_ray_prior_kernel    S_P of each view at the ray footprint of mu_T and the
-//                          thresholded first weights (Sec. III-B, III-F)
-//   lf_em_kernel           n EM iterations: M-step sweep over all disparity
-//                          levels (Eq. 6, E(d)), E-step posterior (Eq. 7),
-//                          per-pixel objective and its FP64 block sums
-//   lf_refocus_kernel      mean of the static rays (Eq. 2)
-//   lf_median3_kernel      3x3 per-channel median of the refocused image (Sec. III-E)
+// Device code of the EM static-background reconstruction for gfx950: the
+// storage formats, footprint helpers and the fused EM kernel
+//   lf_em_kernel   n EM iterations: M-step sweep over all disparity levels
+//                  (Eq. 6, E(d)), E-step posterior (Eq. 7), per-pixel
+//                  objective and its FP64 block sums
+// The per-frame kernels before and after it are in lf_frame_kernels.h.
+// Every pixel is processed independently (Sec. III-F).
 //
 // A rectified linear array shifts views along x only, so the EM kernel stages
 // one row tile of every view plus its disparity halo in LDS once per launch
@@ -83,100 +78,135 @@ __device__ __forceinline__ void footprint(int x, float b, float d, int &i0, floa
     frac = r - fr;
 }
 
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
-
-// ---------------------------------------------------------------------------
-// Descriptors.  grid (ceil(W/blockDim), H, K).
-// ---------------------------------------------------------------------------
-template <int ST>
-__global__ __launch_bounds__(256) void lf_descriptors_kernel(const uint8_t *__restrict__ views,
-                                                             typename Pair<ST>::T *__restrict__ feat,
-                                                             int H, int W) {
-    const int k = blockIdx.z, y = blockIdx.y;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= W) return;
-    const uint8_t *v = views + (size_t)k * H * W * 3;
-    int L[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        const int yy = clampi(y + r - 1, 0, H - 1);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int xx = clampi(x + c - 1, 0, W - 1);
-            const uint8_t *px = v + ((size_t)yy * W + xx) * 3;
-            L[r][c] = (int)px[0] + (int)px[1] + (int)px[2];
-        }
+// The same footprint with both t = frac(u) and 1 - t returned to full
+// relative precision (each is formed from the exact product's pieces rather
+// than as a difference of nearly equal numbers); used where a prior that is
+// nearly 0 or nearly 1 must keep its relative accuracy.
+__device__ __forceinline__ void footprint_precise(int x, float b, float d, int &i0, float &t, float &omt) {
+#pragma clang fp contract(off)
+    const float th = b * d;
+    const float err = fmaf(b, d, -th);   // b*d = th + err exactly
+    const float fl = floorf(th);
+    const float s = th - fl;              // exact, in [0, 1)
+    const float F = s + err;              // frac(b d), up to rounding; picks the case
+    const int base = x - (int)fl;
+    if (F <= 0.0f) {                      // u = base + (-s - err), 0 <= -s - err < 1
+        i0 = base;
+        t = (-s) - err;
+        omt = 1.0f - t;
+    } else if (F < 1.0f) {                // u = base - 1 + (1 - s - err)
+        i0 = base - 1;
+        t = (1.0f - s) - err;
+        omt = s + err;
+    } else {                              // s close to 1 and err > 0
+        i0 = base - 2;
+        omt = (s - 1.0f) + err;
+        t = 1.0f - omt;
     }
-    const int gx = (L[0][2] - L[0][0]) + 2 * (L[1][2] - L[1][0]) + (L[2][2] - L[2][0]);
-    const int gy = (L[2][0] - L[0][0]) + 2 * (L[2][1] - L[0][1]) + (L[2][2] - L[0][2]);
-    const float s = 1.0f / 4096.0f;  // exact: |G| <= 3060
-    feat[((size_t)k * H + y) * W + x] = make_pair<ST>((float)gx * s, (float)gy * s);
 }
 
-// ---------------------------------------------------------------------------
-// Ray prior and first weights.  grid (ceil(W/blockDim), H, K).
-// ---------------------------------------------------------------------------
-struct PriorArgs {
-    const float *S_P, *mu_T, *q_warm;
-    float *rho, *q;
-    uint32_t *bad;  // count of invalid input values (device-resident inputs only)
-    int K, H, W, storage, check;
-    float tau;
-    float b[kMaxViews];
-};
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
-__global__ __launch_bounds__(256) void lf_ray_prior_kernel(PriorArgs a) {
-    const int k = blockIdx.z, y = blockIdx.y;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= a.W) return;
-    const size_t pix = (size_t)y * a.W + x;
-    const size_t i = (size_t)k * a.H * a.W + pix;
-    const float mu = a.mu_T[pix];
-    const float *row = a.S_P + ((size_t)k * a.H + y) * a.W;
+// Ray prior of one ray (Sec. III-B): S_P of the view (held in the storage
+// precision) interpolated at the footprint x - b mu, and its complement
+// interpolated from 1 - S_P; both from the nearer end of the interval so they
+// keep their relative accuracy as they approach 0 (the E-step takes their
+// logarithms).
+__device__ __forceinline__ void ray_prior_value(const float *row, int W, int x, float b, float mu, int storage,
+                                                float &rho, float &omr) {
     int i0;
-    float t;
-    footprint(x, a.b[k], mu, i0, t);
-    const float s0 = as_stored(row[clampi(i0, 0, a.W - 1)], a.storage);
-    const float s1 = as_stored(row[clampi(i0 + 1, 0, a.W - 1)], a.storage);
-    const float r = lerp(s0, s1, t);
-    a.rho[i] = r;
-    float q0 = (r >= a.tau) ? 1.0f : 0.0f;
-    if (a.q_warm) q0 = a.q_warm[i];
-    a.q[i] = q0;
-    if (a.check) {
-        const float s = row[x];
-        uint32_t nbad = !(s >= 0.0f && s <= 1.0f);
-        if (k == 0) nbad += !(fabsf(mu) <= 1e6f);
-        if (a.q_warm) nbad += !(q0 >= 0.0f && q0 <= 1.0f);
-        if (nbad) atomicAdd(a.bad, nbad);
+    float t, omt;
+    footprint_precise(x, b, mu, i0, t, omt);
+    const float s0 = as_stored(row[clampi(i0, 0, W - 1)], storage);
+    const float s1 = as_stored(row[clampi(i0 + 1, 0, W - 1)], storage);
+    if (t <= 0.5f) {
+        rho = fmaf(t, s1 - s0, s0);
+        omr = fmaf(-t, s1 - s0, 1.0f - s0);
+    } else {
+        rho = fmaf(omt, s0 - s1, s1);
+        omr = fmaf(-omt, s0 - s1, 1.0f - s1);
     }
 }
 
 // ---------------------------------------------------------------------------
 // EM iterations.  grid (ceil(W/tile), H), block = tile threads, one pixel per
-// lane.  Dynamic LDS: the descriptor window of every view for this tile.
+// lane.  Dynamic LDS: for every view, the tile's descriptor window plus its
+// disparity halo, one record per position holding (Gx, Gy) at storage
+// precision and the squared norm |f|^2 in FP32.
+//
+// Views are processed in "kernel order": kernel view 0 is the reference view
+// (baseline 0), whose descriptor does not move with the level and is kept in
+// registers; perm[k] maps kernel order to the [K][H][W] array index.
+//
+// The M-step sweep scores each level with the one-pass energy
+//   E^ = beta' (S - |A|^2 / W) - P_j,  A = sum w_k f_k, S = sum w_k |f_k|^2,
+// (3 FMAs per view) and re-evaluates a level exactly, with the two-pass
+// weighted spread of the exhaustive sweep, whenever it could beat the best
+// exact energy so far: E^ - M <= E_best, M = beta' margin_k S + margin_c a
+// bound of |E^ - E| for this formula in FP32.  The sweep is seeded with the
+// previous iteration's level, so re-evaluations are rare, and the arg min and
+// tie rule (lowest level) are exactly those of the exhaustive sweep.  The
+// prior term is evaluated only inside a wave-uniform window |d - mu| <= T;
+// outside it gamma + g rounds to gamma in FP32, so the constant used there is
+// bit-identical to the full evaluation.
 // ---------------------------------------------------------------------------
 struct EmArgs {
     const void *feat;     // [K][H][W] pairs at storage precision
-    const float *rho;     // [K][H][W]
+    const float *rho;     // [K][H][W] static prior of each ray
+    const float *omr;     // [K][H][W] dynamic prior 1 - rho
     const float *mu_T;    // [H][W]
     float *q;             // [K][H][W], read at entry, written at exit
-    int32_t *d_idx;       // [H][W]
+    int32_t *d_idx;       // [H][W], read at entry when seed_from_d, written at exit
     float *lpix;          // [H][W], objective of the last iteration
     double *obj;          // [n_iters][n_blocks] block sums of the objective
-    int H, W, D, n_iters, n_blocks, tile, mode;
+    int H, W, D, n_iters, n_blocks, tile, mode, seed_from_d;
     int dmin_i, dstep_i;  // integer levels (integer-shift path)
     float d_min, d_step;
     float beta_p;         // beta / K
     float lambda, gamma;
     float c_exp2;         // log2(e) / (2 sigma^2)
     float c_exp;          // 1 / (2 sigma^2)
-    int bi[kMaxViews];    // integer baselines (integer-shift path)
-    float b[kMaxViews];
+    float prior_T;        // |d - mu| beyond which gamma + g == gamma in FP32
+    float margin_k;       // one-pass error bound, in units of beta' * S
+    float margin_c;       // absolute slack of the bound
+    int perm[kMaxViews];  // kernel view order -> array view index (perm[0] = reference)
+    int bi[kMaxViews];    // integer baselines, kernel order (integer-shift path)
+    float b[kMaxViews];   // baselines, kernel order
 };
 
+// LDS record: descriptor pair at storage precision plus |f|^2 in FP32.
+template <int ST> struct Rec;
+template <> struct Rec<0> { using T = float4; };  // (Gx, Gy, |f|^2, unused)
+template <> struct Rec<1> { using T = float2; };  // (half2 bits, |f|^2)
+template <> struct Rec<2> { using T = float2; };  // (2 x bf16 bits, |f|^2)
+
+template <int ST>
+__device__ __forceinline__ typename Rec<ST>::T make_rec(typename Pair<ST>::T v) {
+    const float2 f = widen(v);
+    const float n = fmaf(f.x, f.x, f.y * f.y);
+    if constexpr (ST == 0) return make_float4(f.x, f.y, n, 0.0f);
+    else if constexpr (ST == 1) return make_float2(__uint_as_float(*reinterpret_cast<const uint32_t *>(&v)), n);
+    else return make_float2(__uint_as_float(v), n);
+}
+
+template <int ST>
+__device__ __forceinline__ float2 rec_f(const typename Rec<ST>::T &r) {
+    if constexpr (ST == 0) return make_float2(r.x, r.y);
+    else {
+        const uint32_t u = __float_as_uint(r.x);
+        if constexpr (ST == 1) return widen(*reinterpret_cast<const __half2 *>(&u));
+        else return widen(u);
+    }
+}
+
+template <int ST>
+__device__ __forceinline__ float rec_n(const typename Rec<ST>::T &r) {
+    if constexpr (ST == 0) return r.z;
+    else return r.y;
+}
+
 struct Window {
-    int umin, off, len;  // first staged position, offset in LDS (pairs), staged length
+    int umin, off, len;  // first staged position, offset in LDS (records), staged length
 };
 
 template <int K, bool FRAC>
@@ -210,34 +240,221 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Descriptor (and |f|^2) of kernel view k at level j for pixel x.
 template <int K, int ST, bool FRAC>
-__device__ __forceinline__ void gather(const typename Pair<ST>::T *win, const Window (&w)[K], const EmArgs &a,
-                                       int x, int j, float2 (&f)[K]) {
+__device__ __forceinline__ void fetch(const typename Rec<ST>::T *win, const Window &w, const EmArgs &a, int k,
+                                      int x, int j, float2 &f, float &n) {
     if (FRAC) {
         const float d = fmaf((float)j, a.d_step, a.d_min);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            int i0;
-            float t;
-            footprint(x, a.b[k], d, i0, t);
-            // the window margins cover float rounding of the footprint; the
-            // clamp keeps every read inside this view's window regardless
-            const int p = clampi(w[k].off + i0 - w[k].umin, w[k].off, w[k].off + w[k].len - 2);
-            const float2 v0 = widen(win[p]), v1 = widen(win[p + 1]);
-            f[k] = make_float2(lerp(v0.x, v1.x, t), lerp(v0.y, v1.y, t));
-        }
+        int i0;
+        float t;
+        footprint(x, a.b[k], d, i0, t);
+        // the window margins cover float rounding of the footprint; the
+        // clamp keeps every read inside this view's window regardless
+        const int p = clampi(w.off + i0 - w.umin, w.off, w.off + w.len - 2);
+        const float2 v0 = rec_f<ST>(win[p]), v1 = rec_f<ST>(win[p + 1]);
+        f = make_float2(lerp(v0.x, v1.x, t), lerp(v0.y, v1.y, t));
+        n = fmaf(f.x, f.x, f.y * f.y);
     } else {
-        const int d = a.dmin_i + j * a.dstep_i;
-#pragma unroll
-        for (int k = 0; k < K; ++k) f[k] = widen(win[w[k].off + x - a.bi[k] * d - w[k].umin]);
+        const typename Rec<ST>::T r = win[w.off + x - a.bi[k] * (a.dmin_i + j * a.dstep_i) - w.umin];
+        f = rec_f<ST>(r);
+        n = rec_n<ST>(r);
     }
 }
 
-template <int K, int ST, bool FRAC>
+// Exact energy at one level, E = cw * C - logP: two-pass q-weighted mean and
+// spread, summed in kernel view order; shared by the exact re-evaluation and
+// the exhaustive sweep so both give the same bits.
+template <int K>
+__device__ __forceinline__ float exact_energy(const float2 (&f)[K], const float (&wt)[K], float invW, float cw,
+                                              float P, float &mx, float &my) {
+    float ax = 0.0f, ay = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        ax = fmaf(wt[k], f[k].x, ax);
+        ay = fmaf(wt[k], f[k].y, ay);
+    }
+    mx = ax * invW;
+    my = ay * invW;
+    float C = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const float dx = f[k].x - mx, dy = f[k].y - my;
+        C = fmaf(wt[k], fmaf(dx, dx, dy * dy), C);
+    }
+    return fmaf(cw, C, -P);
+}
+
+// ln(gamma + exp(-(d_j - mu)^2 / (2 sigma^2))), the log disparity prior up to
+// a constant, through the hardware base-2 exponential and logarithm.
+__device__ __forceinline__ float log_prior(const EmArgs &a, int j, float mu) {
+    const float t = fmaf((float)j, a.d_step, a.d_min) - mu;
+    const float g = __builtin_amdgcn_exp2f(-(t * t) * a.c_exp2);
+    return kLn2 * __builtin_amdgcn_logf(a.gamma + g);
+}
+
+// Per-lane state of one pixel across EM iterations.
+template <int K>
+struct Lane {
+    float q[K];    // weights (kernel view order)
+    float la[K];   // ln rho_k + lambda
+    float lb[K];   // ln(1 - rho_k)
+    float2 f0;     // reference-view descriptor (constant over levels)
+    float n0;      // its squared norm
+    float mu;      // prior disparity
+    float L;       // objective after the last E-step
+    int best_j;    // level of the last M-step (seed of the next sweep)
+};
+
+// Wave-uniform window [jlo, jhi] of levels where the log prior differs from
+// the constant ln(gamma); outside it gamma + g rounds to gamma in FP32.
+__device__ __forceinline__ void prior_window(const EmArgs &a, bool active, float mu, int &jlo, int &jhi) {
+    jlo = a.D;
+    jhi = -1;
+    if (active) {
+        jlo = (int)fmaxf(ceilf((mu - a.prior_T - a.d_min) / a.d_step), 0.0f);
+        jhi = (int)fminf(floorf((mu + a.prior_T - a.d_min) / a.d_step), (float)(a.D - 1));
+        jlo = min(jlo, a.D);
+        jhi = max(jhi, -1);
+    }
+    // uniform across the wave: keep them in scalar registers
+    jlo = __builtin_amdgcn_readfirstlane(wave_min(jlo));
+    jhi = __builtin_amdgcn_readfirstlane(wave_max(jhi));
+}
+
+// Seed level of the first sweep: the level nearest the prior disparity.
+__device__ __forceinline__ int nearest_level(const EmArgs &a, float mu) {
+    const float jf = rintf((mu - a.d_min) / a.d_step);
+    return (int)fminf(fmaxf(jf, 0.0f), (float)(a.D - 1));
+}
+
+// One EM iteration of one active lane: M-step sweep over all levels with the
+// current weights, then the E-step and the objective at the chosen level.
+template <int K, int ST, bool FRAC, bool EXH>
+__device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, const Window (&w)[K], const EmArgs &a,
+                                             int x, int jlo, int jhi, float Pc, Lane<K> &s) {
+    // ---- M-step: weights from the previous E-step (or the start) ----
+    float Q = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) Q += s.q[k];
+    const bool empty = !(Q > 0.0f);
+    float wt[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) wt[k] = empty ? 1.0f : s.q[k];
+    const float invW = 1.0f / (empty ? (float)K : Q);
+    const float cw = empty ? 0.0f : a.beta_p;
+    const float mu = s.mu;
+    int best_j = s.best_j;
+
+    if (EXH) {
+        float best_E = INFINITY;
+        best_j = 0;
+        for (int j = 0; j < a.D; ++j) {
+            float2 f[K];
+            float nn, mx, my;
+            f[0] = s.f0;
+#pragma unroll
+            for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, j, f[k], nn);
+            const float E = exact_energy<K>(f, wt, invW, cw, log_prior(a, j, mu), mx, my);
+            if (E < best_E) {
+                best_E = E;
+                best_j = j;
+            }
+        }
+    } else {
+        // seed: exact energy at the previous level
+        float best_E;
+        {
+            float2 f[K];
+            float nn, mx, my;
+            f[0] = s.f0;
+#pragma unroll
+            for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, best_j, f[k], nn);
+            best_E = exact_energy<K>(f, wt, invW, cw, log_prior(a, best_j, mu), mx, my);
+        }
+        const float A0x = wt[0] * s.f0.x, A0y = wt[0] * s.f0.y, S0 = wt[0] * s.n0;
+        const float cwm = cw * a.margin_k;
+        auto level = [&](int j, float Pj) {
+            float2 f[K];
+            f[0] = s.f0;
+            float ax = A0x, ay = A0y, S = S0;
+#pragma unroll
+            for (int k = 1; k < K; ++k) {
+                float n;
+                fetch<K, ST, FRAC>(win, w[k], a, k, x, j, f[k], n);
+                ax = fmaf(wt[k], f[k].x, ax);
+                ay = fmaf(wt[k], f[k].y, ay);
+                S = fmaf(wt[k], n, S);
+            }
+            const float Chat = fmaf(-fmaf(ax, ax, ay * ay), invW, S);
+            const float Ehat = fmaf(cw, Chat, -Pj);
+            // the current best level is already exact: skip it
+            const bool cand = (Ehat - fmaf(cwm, S, a.margin_c)) <= best_E && j != best_j;
+            if (__any(cand)) {
+                if (cand) {
+                    float mx, my;
+                    const float E = exact_energy<K>(f, wt, invW, cw, Pj, mx, my);
+                    if (E < best_E || (E == best_E && j < best_j)) {
+                        best_E = E;
+                        best_j = j;
+                    }
+                }
+            }
+        };
+        // levels below, inside and above the prior window
+        const int j1 = min(jlo, a.D), j2 = min(jhi + 1, a.D);
+        int j = 0;
+        for (; j < j1; ++j) level(j, Pc);
+        for (; j < j2; ++j) level(j, log_prior(a, j, mu));
+        for (; j < a.D; ++j) level(j, Pc);
+    }
+    s.best_j = best_j;
+
+    // ---- E-step at the new disparity ----
+    float2 f[K];
+    float nn, mx, my;
+    f[0] = s.f0;
+#pragma unroll
+    for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, best_j, f[k], nn);
+    (void)exact_energy<K>(f, wt, invW, cw, 0.0f, mx, my);
+    const float t = fmaf((float)best_j, a.d_step, a.d_min) - mu;
+    float L = logf(a.gamma + expf(-(t * t) * a.c_exp));
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const float dx = f[k].x - mx, dy = f[k].y - my;
+        const float e = fmaf(dx, dx, dy * dy);
+        const float a1 = s.la[k] - a.beta_p * e;
+        const float a0 = s.lb[k];
+        if (a.mode == 1) {
+            s.q[k] = (a1 >= a0) ? 1.0f : 0.0f;
+            L += fmaxf(a1, a0);
+        } else {
+            s.q[k] = 1.0f / (1.0f + __expf(a0 - a1));
+            const float hi = fmaxf(a1, a0);
+            L += hi + log1pf(expf(-fabsf(a1 - a0)));
+        }
+    }
+    s.L = L;
+}
+
+template <int K, int ST, bool FRAC, bool EXH>
 __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
+    using R = typename Rec<ST>::T;
     using P = typename Pair<ST>::T;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    P *win = reinterpret_cast<P *>(lds_raw);
+    R *win = reinterpret_cast<R *>(lds_raw);
     __shared__ double red[8];
 
     const int y = blockIdx.y;
@@ -252,106 +469,50 @@ __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
     int total;
     view_windows<K, FRAC>(a, x0, w, total);
 
-    // Stage the windows (replicated border outside the image).
+    // Stage the windows (replicated border outside the image) with |f|^2.
     const P *feat = reinterpret_cast<const P *>(a.feat);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const P *row = feat + ((size_t)k * a.H + y) * a.W;
-        for (int p = tid; p < w[k].len; p += blockDim.x) win[w[k].off + p] = row[clampi(w[k].umin + p, 0, a.W - 1)];
+        const P *row = feat + ((size_t)a.perm[k] * a.H + y) * a.W;
+        for (int p = tid; p < w[k].len; p += blockDim.x)
+            win[w[k].off + p] = make_rec<ST>(row[clampi(w[k].umin + p, 0, a.W - 1)]);
     }
     __syncthreads();
 
-    float q[K], la[K], lb[K];
-    float mu = 0.0f;
+    Lane<K> s;
+    s.mu = 0.0f;
+    s.L = 0.0f;
+    s.best_j = 0;
+    s.f0 = make_float2(0.0f, 0.0f);
+    s.n0 = 0.0f;
     if (active) {
-        mu = a.mu_T[pix];
+        s.mu = a.mu_T[pix];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const float r = a.rho[k * HW + pix];
-            q[k] = a.q[k * HW + pix];
-            la[k] = (r > 0.0f ? logf(r) : -INFINITY) + a.lambda;   // ln rho + lambda
-            lb[k] = (r < 1.0f ? log1pf(-r) : -INFINITY);           // ln(1 - rho)
+            const size_t i = (size_t)a.perm[k] * HW + pix;
+            const float r = a.rho[i], om = a.omr[i];
+            s.q[k] = a.q[i];
+            s.la[k] = (r > 0.0f ? logf(r) : -INFINITY) + a.lambda;   // ln rho + lambda
+            s.lb[k] = (om > 0.0f ? logf(om) : -INFINITY);            // ln(1 - rho)
         }
+        s.best_j = a.seed_from_d ? a.d_idx[pix] : nearest_level(a, s.mu);
+        fetch<K, ST, FRAC>(win, w[0], a, 0, x, 0, s.f0, s.n0);
     } else {
 #pragma unroll
-        for (int k = 0; k < K; ++k) q[k] = la[k] = lb[k] = 0.0f;
+        for (int k = 0; k < K; ++k) s.q[k] = s.la[k] = s.lb[k] = 0.0f;
     }
 
-    int best_j = 0;
-    float L = 0.0f;
+    const float Pc = kLn2 * __builtin_amdgcn_logf(a.gamma);
+    int jlo, jhi;
+    prior_window(a, active, s.mu, jlo, jhi);
+
     const int block_id = blockIdx.y * gridDim.x + blockIdx.x;
     for (int it = 0; it < a.n_iters; ++it) {
-        if (active) {
-            // ---- M-step: weights from the previous E-step (or the start) ----
-            float Q = 0.0f;
-#pragma unroll
-            for (int k = 0; k < K; ++k) Q += q[k];
-            const bool empty = !(Q > 0.0f);
-            float wt[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) wt[k] = empty ? 1.0f : q[k];
-            const float invW = 1.0f / (empty ? (float)K : Q);
-            const float cw = empty ? 0.0f : a.beta_p;
-            float best_E = INFINITY;
-            best_j = 0;
-            for (int j = 0; j < a.D; ++j) {
-                float2 f[K];
-                gather<K, ST, FRAC>(win, w, a, x, j, f);
-                float mx = 0.0f, my = 0.0f;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    mx = fmaf(wt[k], f[k].x, mx);
-                    my = fmaf(wt[k], f[k].y, my);
-                }
-                mx *= invW;
-                my *= invW;
-                float C = 0.0f;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const float dx = f[k].x - mx, dy = f[k].y - my;
-                    C = fmaf(wt[k], fmaf(dx, dx, dy * dy), C);
-                }
-                const float t = fmaf((float)j, a.d_step, a.d_min) - mu;
-                const float g = __builtin_amdgcn_exp2f(-(t * t) * a.c_exp2);
-                const float E = fmaf(cw, C, -kLn2 * __builtin_amdgcn_logf(a.gamma + g));
-                if (E < best_E) {
-                    best_E = E;
-                    best_j = j;
-                }
-            }
-            // ---- E-step at the new disparity ----
-            float2 f[K];
-            gather<K, ST, FRAC>(win, w, a, x, best_j, f);
-            float mx = 0.0f, my = 0.0f;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                mx = fmaf(wt[k], f[k].x, mx);
-                my = fmaf(wt[k], f[k].y, my);
-            }
-            mx *= invW;
-            my *= invW;
-            const float t = fmaf((float)best_j, a.d_step, a.d_min) - mu;
-            L = logf(a.gamma + expf(-(t * t) * a.c_exp));
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const float dx = f[k].x - mx, dy = f[k].y - my;
-                const float e = fmaf(dx, dx, dy * dy);
-                const float a1 = la[k] - a.beta_p * e;
-                const float a0 = lb[k];
-                if (a.mode == 1) {
-                    q[k] = (a1 >= a0) ? 1.0f : 0.0f;
-                    L += fmaxf(a1, a0);
-                } else {
-                    q[k] = 1.0f / (1.0f + __expf(a0 - a1));
-                    const float hi = fmaxf(a1, a0);
-                    L += hi + log1pf(expf(-fabsf(a1 - a0)));
-                }
-            }
-        }
+        if (active) em_iteration<K, ST, FRAC, EXH>(win, w, a, x, jlo, jhi, Pc, s);
         // ---- FP64 block sum of the objective ----
-        double s = wave_sum(active ? (double)L : 0.0);
+        double sum = wave_sum(active ? (double)s.L : 0.0);
         const int lane = tid & 63, wv = tid >> 6;
-        if (lane == 0) red[wv] = s;
+        if (lane == 0) red[wv] = sum;
         __syncthreads();
         if (tid == 0) {
             double tot = 0.0;
@@ -362,109 +523,9 @@ __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
     }
     if (active && a.n_iters > 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) a.q[k * HW + pix] = q[k];
-        a.d_idx[pix] = best_j;
-        a.lpix[pix] = L;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Refocus (Eq. 2).  grid (ceil(W/blockDim), H).
-// ---------------------------------------------------------------------------
-struct RefocusArgs {
-    const uint8_t *views;
-    const int32_t *d_idx;
-    const float *q;
-    float *rgb;
-    uint8_t *hole;
-    int K, H, W, ref, frac;
-    int dmin_i, dstep_i;
-    float d_min, d_step;
-    int bi[kMaxViews];
-    float b[kMaxViews];
-};
-
-__global__ __launch_bounds__(256) void lf_refocus_kernel(RefocusArgs a) {
-    const int y = blockIdx.y;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= a.W) return;
-    const size_t HW = (size_t)a.H * a.W;
-    const size_t pix = (size_t)y * a.W + x;
-    const int j = a.d_idx[pix];
-    float acc[3] = {0.0f, 0.0f, 0.0f};
-    int n = 0;
-    if (!a.frac) {
-        int iacc[3] = {0, 0, 0};
-        const int d = a.dmin_i + j * a.dstep_i;
-        for (int k = 0; k < a.K; ++k) {
-            if (!(a.q[k * HW + pix] >= 0.5f)) continue;
-            const int u = clampi(x - a.bi[k] * d, 0, a.W - 1);
-            const uint8_t *px = a.views + (((size_t)k * a.H + y) * a.W + u) * 3;
-            iacc[0] += px[0];
-            iacc[1] += px[1];
-            iacc[2] += px[2];
-            ++n;
-        }
-        acc[0] = (float)iacc[0];
-        acc[1] = (float)iacc[1];
-        acc[2] = (float)iacc[2];
-    } else {
-        const float d = fmaf((float)j, a.d_step, a.d_min);
-        for (int k = 0; k < a.K; ++k) {
-            if (!(a.q[k * HW + pix] >= 0.5f)) continue;
-            int i0;
-            float t;
-            footprint(x, a.b[k], d, i0, t);
-            const uint8_t *r = a.views + ((size_t)k * a.H + y) * a.W * 3;
-            const uint8_t *p0 = r + (size_t)clampi(i0, 0, a.W - 1) * 3;
-            const uint8_t *p1 = r + (size_t)clampi(i0 + 1, 0, a.W - 1) * 3;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) acc[c] += lerp((float)p0[c], (float)p1[c], t);
-            ++n;
-        }
-    }
-    float *o = a.rgb + pix * 3;
-    if (n > 0) {
-        const float den = 255.0f * (float)n;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) o[c] = acc[c] / den;
-        if (a.hole) a.hole[pix] = 0;
-    } else {
-        const uint8_t *c_ref = a.views + (((size_t)a.ref * a.H + y) * a.W + x) * 3;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) o[c] = (float)c_ref[c] / 255.0f;
-        if (a.hole) a.hole[pix] = 1;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// 3x3 per-channel median with replicated border.  grid (ceil(W/blockDim), H).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void cswap(float &p, float &q) {
-    const float lo = fminf(p, q), hi = fmaxf(p, q);
-    p = lo;
-    q = hi;
-}
-
-__global__ __launch_bounds__(256) void lf_median3_kernel(const float *__restrict__ in, float *__restrict__ out,
-                                                         int H, int W) {
-    const int y = blockIdx.y;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= W) return;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        float v[9];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int s = 0; s < 3; ++s)
-                v[r * 3 + s] = in[((size_t)clampi(y + r - 1, 0, H - 1) * W + clampi(x + s - 1, 0, W - 1)) * 3 + c];
-        // median of 9 by a full sorting network on the nine values
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-#pragma unroll
-            for (int m = (i & 1); m + 1 < 9; m += 2) cswap(v[m], v[m + 1]);
-        out[((size_t)y * W + x) * 3 + c] = v[4];
+        for (int k = 0; k < K; ++k) a.q[(size_t)a.perm[k] * HW + pix] = s.q[k];
+        a.d_idx[pix] = s.best_j;
+        a.lpix[pix] = s.L;
     }
 }
 

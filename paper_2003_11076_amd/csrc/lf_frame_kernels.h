@@ -1,0 +1,179 @@
+// Per-frame kernels around the EM iterations (gfx950):
+//   lf_descriptors_kernel  3x3 Sobel responses of R+G+B (Sec. III-C)
+//   lf_ray_prior_kernel    S_P of each view at the ray footprint of mu_T, its
+//                          complement, and the thresholded first weights
+//                          (Sec. III-B, III-F)
+//   lf_refocus_kernel      mean of the static rays (Eq. 2)
+//   lf_median3_kernel      3x3 per-channel median of the refocused image (Sec. III-E)
+// Included by one translation unit only.
+#pragma once
+
+#include "lf_em_kernels.h"
+
+namespace lfem {
+
+// ---------------------------------------------------------------------------
+// Descriptors.  grid (ceil(W/blockDim), H, K).
+// ---------------------------------------------------------------------------
+template <int ST>
+__global__ __launch_bounds__(256) void lf_descriptors_kernel(const uint8_t *__restrict__ views,
+                                                             typename Pair<ST>::T *__restrict__ feat,
+                                                             int H, int W) {
+    const int k = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= W) return;
+    const uint8_t *v = views + (size_t)k * H * W * 3;
+    int L[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int yy = clampi(y + r - 1, 0, H - 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int xx = clampi(x + c - 1, 0, W - 1);
+            const uint8_t *px = v + ((size_t)yy * W + xx) * 3;
+            L[r][c] = (int)px[0] + (int)px[1] + (int)px[2];
+        }
+    }
+    const int gx = (L[0][2] - L[0][0]) + 2 * (L[1][2] - L[1][0]) + (L[2][2] - L[2][0]);
+    const int gy = (L[2][0] - L[0][0]) + 2 * (L[2][1] - L[0][1]) + (L[2][2] - L[0][2]);
+    const float s = 1.0f / 4096.0f;  // exact: |G| <= 3060
+    feat[((size_t)k * H + y) * W + x] = make_pair<ST>((float)gx * s, (float)gy * s);
+}
+
+// ---------------------------------------------------------------------------
+// Ray prior and first weights.  grid (ceil(W/blockDim), H, K).
+// ---------------------------------------------------------------------------
+struct PriorArgs {
+    const float *S_P, *mu_T, *q_warm;
+    float *rho, *omr, *q;   // static prior, dynamic prior 1 - rho, weights
+    uint32_t *bad;  // count of invalid input values (device-resident inputs only)
+    int K, H, W, storage, check;
+    float tau;
+    float b[kMaxViews];
+};
+
+__global__ __launch_bounds__(256) void lf_ray_prior_kernel(PriorArgs a) {
+    const int k = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.W) return;
+    const size_t pix = (size_t)y * a.W + x;
+    const size_t i = (size_t)k * a.H * a.W + pix;
+    const float mu = a.mu_T[pix];
+    const float *row = a.S_P + ((size_t)k * a.H + y) * a.W;
+    float r, om;
+    ray_prior_value(row, a.W, x, a.b[k], mu, a.storage, r, om);
+    a.rho[i] = r;
+    a.omr[i] = om;
+    float q0 = (r >= a.tau) ? 1.0f : 0.0f;
+    if (a.q_warm) q0 = a.q_warm[i];
+    a.q[i] = q0;
+    if (a.check) {
+        const float s = row[x];
+        uint32_t nbad = !(s >= 0.0f && s <= 1.0f);
+        if (k == 0) nbad += !(fabsf(mu) <= 1e6f);
+        if (a.q_warm) nbad += !(q0 >= 0.0f && q0 <= 1.0f);
+        if (nbad) atomicAdd(a.bad, nbad);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Refocus (Eq. 2).  grid (ceil(W/blockDim), H).
+// ---------------------------------------------------------------------------
+struct RefocusArgs {
+    const uint8_t *views;
+    const int32_t *d_idx;
+    const float *q;
+    float *rgb;
+    uint8_t *hole;
+    int K, H, W, ref, frac;
+    int dmin_i, dstep_i;
+    float d_min, d_step;
+    int bi[kMaxViews];
+    float b[kMaxViews];
+};
+
+__global__ __launch_bounds__(256) void lf_refocus_kernel(RefocusArgs a) {
+    const int y = blockIdx.y;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.W) return;
+    const size_t HW = (size_t)a.H * a.W;
+    const size_t pix = (size_t)y * a.W + x;
+    const int j = a.d_idx[pix];
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    int n = 0;
+    if (!a.frac) {
+        int iacc[3] = {0, 0, 0};
+        const int d = a.dmin_i + j * a.dstep_i;
+        for (int k = 0; k < a.K; ++k) {
+            if (!(a.q[k * HW + pix] >= 0.5f)) continue;
+            const int u = clampi(x - a.bi[k] * d, 0, a.W - 1);
+            const uint8_t *px = a.views + (((size_t)k * a.H + y) * a.W + u) * 3;
+            iacc[0] += px[0];
+            iacc[1] += px[1];
+            iacc[2] += px[2];
+            ++n;
+        }
+        acc[0] = (float)iacc[0];
+        acc[1] = (float)iacc[1];
+        acc[2] = (float)iacc[2];
+    } else {
+        const float d = fmaf((float)j, a.d_step, a.d_min);
+        for (int k = 0; k < a.K; ++k) {
+            if (!(a.q[k * HW + pix] >= 0.5f)) continue;
+            int i0;
+            float t, omt;
+            footprint_precise(x, a.b[k], d, i0, t, omt);
+            const uint8_t *r = a.views + ((size_t)k * a.H + y) * a.W * 3;
+            const uint8_t *p0 = r + (size_t)clampi(i0, 0, a.W - 1) * 3;
+            const uint8_t *p1 = r + (size_t)clampi(i0 + 1, 0, a.W - 1) * 3;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] += lerp((float)p0[c], (float)p1[c], t);
+            ++n;
+        }
+    }
+    float *o = a.rgb + pix * 3;
+    if (n > 0) {
+        const float den = 255.0f * (float)n;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o[c] = acc[c] / den;
+        if (a.hole) a.hole[pix] = 0;
+    } else {
+        const uint8_t *c_ref = a.views + (((size_t)a.ref * a.H + y) * a.W + x) * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o[c] = (float)c_ref[c] / 255.0f;
+        if (a.hole) a.hole[pix] = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 per-channel median with replicated border.  grid (ceil(W/blockDim), H).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cswap(float &p, float &q) {
+    const float lo = fminf(p, q), hi = fmaxf(p, q);
+    p = lo;
+    q = hi;
+}
+
+__global__ __launch_bounds__(256) void lf_median3_kernel(const float *__restrict__ in, float *__restrict__ out,
+                                                         int H, int W) {
+    const int y = blockIdx.y;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= W) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float v[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int s = 0; s < 3; ++s)
+                v[r * 3 + s] = in[((size_t)clampi(y + r - 1, 0, H - 1) * W + clampi(x + s - 1, 0, W - 1)) * 3 + c];
+        // median of 9 by a full sorting network on the nine values
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int m = (i & 1); m + 1 < 9; m += 2) cswap(v[m], v[m + 1]);
+        out[((size_t)y * W + x) * 3 + c] = v[4];
+    }
+}
+
+}  // namespace lfem

@@ -14,6 +14,17 @@ namespace lfem {
 
 struct EmArgs;
 struct RefocusArgs;
+using EmKernel = void (*)(EmArgs);
+
+EmKernel pick_em_f32(int K, bool frac, bool exh);
+EmKernel pick_em_f16(int K, bool frac, bool exh);
+EmKernel pick_em_bf16(int K, bool frac, bool exh);
+
+struct ServeJob;
+using ServeKernel = void (*)(const ServeJob *, int);
+ServeKernel pick_serve_f32();
+ServeKernel pick_serve_f16();
+ServeKernel pick_serve_bf16();
 
 // Integer-shift geometry: when every baseline and both level parameters are
 // integers, footprints x - b_k d_j are exact integers and the kernels index
@@ -49,6 +60,7 @@ struct DeviceArena {
     void release();
 };
 
+EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda);
 lf_status set_error(lf_status s, const char *fmt, ...);
 lf_status hip_error(hipError_t e, const char *what);
 lf_status validate_params(const lf_params *p);
@@ -57,11 +69,12 @@ float derived_lambda(const lf_params *p);
 Geometry make_geometry(const lf_params *p);
 size_t em_window_pairs(const lf_params *p, const Geometry &g, int tile);
 size_t pair_bytes(int storage);
+size_t rec_bytes(int storage);
 int choose_tile(const lf_params *p, const Geometry &g, size_t lds_limit, size_t *lds_out);
 
 hipError_t launch_descriptors(const lf_params *p, const uint8_t *views, void *feat, hipStream_t s);
 hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *mu_T, const float *q_warm,
-                            float *rho, float *q, uint32_t *bad, int check, hipStream_t s);
+                            float *rho, float *omr, float *q, uint32_t *bad, int check, hipStream_t s);
 hipError_t launch_median3(const lf_params *p, const float *in, float *out, hipStream_t s);
 
 }  // namespace lfem

@@ -1,0 +1,208 @@
+// Batched frame kernel of the frame server (gfx950).
+//
+// One launch covers every (frame, row tile) pair of a batch of admitted
+// frames, which may differ in size, view count, level count and storage of
+// their own: block b finds its frame through the batch's tile prefix table.
+// Each block runs the whole method for one row tile of 128 pixels of one
+// frame, with nothing written to HBM in between:
+//   descriptors of the tile's windows, from three staged rows of R+G+B
+//   (Sec. III-C) -> ray prior of each pixel's rays (Sec. III-B) -> n EM
+//   iterations (Sec. III-C, III-D) -> refocus of the static rays (Eq. 2).
+// Tiles depend on nothing but their frame's inputs (and the stream's
+// previous weights), so a frame gives the same bits alone or in any mix.
+#pragma once
+
+#include "lf_em_kernels.h"
+
+namespace lfem {
+
+constexpr int kServeTile = 128;
+constexpr int kServeMaxViews = 9;
+
+struct ServeJob {
+    EmArgs em;               // levels, prior, margins, view order, shape; em.mu_T, em.q, em.d_idx
+    const uint8_t *views;    // [K][H][W][3]
+    const float *S_P;        // [K][H][W]
+    const float *q_warm;     // [K][H][W] previous weights of the stream, or null (threshold start)
+    float *rgb;              // [H][W][3]
+    uint8_t *hole;           // [H][W]
+    int K, ref, frac, tiles_x, tile_start, n_tiles;
+    float tau;
+    int pad_;
+};
+
+// LDS bytes a job needs: descriptor records plus three int16 rows of
+// intensity sums per view window (with one column of border on each side).
+template <int ST>
+__host__ __device__ inline size_t serve_rec_bytes() { return ST == 0 ? 16 : 8; }
+
+template <int K, int ST, bool FRAC>
+__device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsigned char *lds) {
+    using R = typename Rec<ST>::T;
+    const EmArgs &a = job.em;
+    const int tid = threadIdx.x;
+    const int y = tile / job.tiles_x;
+    const int x0 = (tile - y * job.tiles_x) * kServeTile;
+    const int x = x0 + tid;
+    const int W = a.W, H = a.H;
+    const bool active = x < W;
+    const size_t HW = (size_t)H * W;
+    const size_t pix = (size_t)y * W + x;
+
+    Window w[K];
+    int total;
+    view_windows<K, FRAC>(a, x0, w, total);
+    R *win = reinterpret_cast<R *>(lds);
+    int16_t *lsum = reinterpret_cast<int16_t *>(lds + (size_t)total * sizeof(R));
+
+    // 1) rows y-1, y, y+1 of R+G+B over each window's columns (+1 border)
+    int c0[K], nc[K], loff[K];
+    int lo = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int ulo = clampi(w[k].umin, 0, W - 1), uhi = clampi(w[k].umin + w[k].len - 1, 0, W - 1);
+        c0[k] = max(ulo - 1, 0);
+        nc[k] = min(uhi + 1, W - 1) - c0[k] + 1;
+        loff[k] = lo;
+        lo += 3 * nc[k];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint8_t *v = job.views + (size_t)a.perm[k] * HW * 3;
+        for (int i = tid; i < 3 * nc[k]; i += kServeTile) {
+            const int r = i / nc[k], c = c0[k] + (i - r * nc[k]);
+            const int yy = clampi(y + r - 1, 0, H - 1);
+            const uint8_t *px = v + ((size_t)yy * W + c) * 3;
+            lsum[loff[k] + i] = (int16_t)((int)px[0] + (int)px[1] + (int)px[2]);
+        }
+    }
+    __syncthreads();
+    // 2) descriptor records of every window position (replicated border)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int16_t *L0 = lsum + loff[k], *L1 = L0 + nc[k], *L2 = L1 + nc[k];
+        for (int p = tid; p < w[k].len; p += kServeTile) {
+            const int uc = clampi(w[k].umin + p, 0, W - 1);
+            const int cl = max(uc - 1, 0) - c0[k], cm = uc - c0[k], cr = min(uc + 1, W - 1) - c0[k];
+            const int gx = (L0[cr] - L0[cl]) + 2 * (L1[cr] - L1[cl]) + (L2[cr] - L2[cl]);
+            const int gy = (L2[cl] - L0[cl]) + 2 * (L2[cm] - L0[cm]) + (L2[cr] - L0[cr]);
+            const float sc = 1.0f / 4096.0f;
+            win[w[k].off + p] = make_rec<ST>(make_pair<ST>((float)gx * sc, (float)gy * sc));
+        }
+    }
+    __syncthreads();
+
+    // 3) ray prior and first weights of each of the pixel's rays
+    Lane<K> s;
+    s.mu = 0.0f;
+    s.L = 0.0f;
+    s.best_j = 0;
+    s.f0 = make_float2(0.0f, 0.0f);
+    s.n0 = 0.0f;
+    if (active) {
+        s.mu = a.mu_T[pix];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const size_t row = ((size_t)a.perm[k] * H + y) * W;
+            float r, om;
+            ray_prior_value(job.S_P + row, W, x, a.b[k], s.mu, ST, r, om);
+            s.la[k] = (r > 0.0f ? logf(r) : -INFINITY) + a.lambda;
+            s.lb[k] = (om > 0.0f ? logf(om) : -INFINITY);
+            s.q[k] = job.q_warm ? job.q_warm[row + x] : ((r >= job.tau) ? 1.0f : 0.0f);
+        }
+        s.best_j = nearest_level(a, s.mu);
+        fetch<K, ST, FRAC>(win, w[0], a, 0, x, 0, s.f0, s.n0);
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) s.q[k] = s.la[k] = s.lb[k] = 0.0f;
+    }
+
+    // 4) EM iterations
+    const float Pc = kLn2 * __builtin_amdgcn_logf(a.gamma);
+    int jlo, jhi;
+    prior_window(a, active, s.mu, jlo, jhi);
+    if (active)
+        for (int it = 0; it < a.n_iters; ++it) em_iteration<K, ST, FRAC, false>(win, w, a, x, jlo, jhi, Pc, s);
+
+    // 5) outputs: weights, level, refocus of the static rays
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) a.q[(size_t)a.perm[k] * HW + pix] = s.q[k];
+        a.d_idx[pix] = s.best_j;
+        float acc[3] = {0.0f, 0.0f, 0.0f};
+        int n = 0;
+        if (!FRAC) {
+            int iacc[3] = {0, 0, 0};
+            const int d = a.dmin_i + s.best_j * a.dstep_i;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (!(s.q[k] >= 0.5f)) continue;
+                const int u = clampi(x - a.bi[k] * d, 0, W - 1);
+                const uint8_t *px = job.views + (((size_t)a.perm[k] * H + y) * W + u) * 3;
+                iacc[0] += px[0];
+                iacc[1] += px[1];
+                iacc[2] += px[2];
+                ++n;
+            }
+            acc[0] = (float)iacc[0];
+            acc[1] = (float)iacc[1];
+            acc[2] = (float)iacc[2];
+        } else {
+            const float d = fmaf((float)s.best_j, a.d_step, a.d_min);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (!(s.q[k] >= 0.5f)) continue;
+                int i0;
+                float t, omt;
+                footprint_precise(x, a.b[k], d, i0, t, omt);
+                const uint8_t *r = job.views + ((size_t)a.perm[k] * H + y) * W * 3;
+                const uint8_t *p0 = r + (size_t)clampi(i0, 0, W - 1) * 3;
+                const uint8_t *p1 = r + (size_t)clampi(i0 + 1, 0, W - 1) * 3;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[c] += lerp((float)p0[c], (float)p1[c], t);
+                ++n;
+            }
+        }
+        float *o = job.rgb + pix * 3;
+        if (n > 0) {
+            const float den = 255.0f * (float)n;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o[c] = acc[c] / den;
+            job.hole[pix] = 0;
+        } else {
+            const uint8_t *c_ref = job.views + (((size_t)job.ref * H + y) * W + x) * 3;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o[c] = (float)c_ref[c] / 255.0f;
+            job.hole[pix] = 1;
+        }
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(kServeTile) void lf_serve_kernel(const ServeJob *__restrict__ jobs, int n_jobs) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ int s_job;
+    if (threadIdx.x == 0) {
+        int j = 0;
+        while (j + 1 < n_jobs && (int)blockIdx.x >= jobs[j + 1].tile_start) ++j;
+        s_job = j;
+    }
+    __syncthreads();
+    const int j = __builtin_amdgcn_readfirstlane(s_job);
+    const ServeJob &job = jobs[j];
+    const int tile = (int)blockIdx.x - job.tile_start;
+    const bool frac = job.frac != 0;
+    switch (job.K) {
+#define LF_SERVE_CASE(n)                                         \
+    case n:                                                      \
+        if (frac) serve_tile<n, ST, true>(job, tile, lds);       \
+        else serve_tile<n, ST, false>(job, tile, lds);           \
+        break;
+        LF_SERVE_CASE(2) LF_SERVE_CASE(3) LF_SERVE_CASE(4) LF_SERVE_CASE(5)
+        LF_SERVE_CASE(6) LF_SERVE_CASE(7) LF_SERVE_CASE(8) LF_SERVE_CASE(9)
+#undef LF_SERVE_CASE
+        default: break;
+    }
+}
+
+}  // namespace lfem

@@ -116,11 +116,11 @@ def feat_bytes(storage, K, H, W):
 # ---------------------------------------------------------------------------
 
 class GpuRun:
-    def __init__(self, case: Case, device_inputs=True, q_warm=None):
+    def __init__(self, case: Case, device_inputs=True, q_warm=None, extra_flags=0):
         import torch
         import paper_2003_11076_amd as LF
         self.LF, self.case = LF, case
-        flags = LF.LF_INPUTS_ON_DEVICE if device_inputs else 0
+        flags = (LF.LF_INPUTS_ON_DEVICE if device_inputs else 0) | extra_flags
         stream = torch.cuda.current_stream().cuda_stream
         if device_inputs:
             dev = torch.device("cuda")
@@ -221,7 +221,9 @@ def teacher_forced(case: Case, n_iters: int, rows=None, device_inputs=True, chec
     y0, y1 = rows if rows is not None else (0, case.H)
     orows = (max(0, y0 - 1), min(case.H, y1 + 1))
     f_o = O.descriptors(op, case.views, rows=orows)
-    rho_o, q0_o = O.ray_prior(op, case.S_P, case.mu_T, rows=(y0, y1))
+    pr = O.ray_prior(op, case.S_P, case.mu_T, rows=(y0, y1))
+    rho_o, q0_o = pr
+    omr_o = pr.omr
     run = GpuRun(case, device_inputs=device_inputs)
     try:
         f_g, rho_g = run.intermediates()
@@ -236,11 +238,11 @@ def teacher_forced(case: Case, n_iters: int, rows=None, device_inputs=True, chec
         for t in range(n_iters):
             run.iterate(1)
             q_g, d_g, L_g = run.state()
-            ref = O.em_iteration(op, f_o, rho_o, case.mu_T, q_prev.astype(np.float64), rows=(y0, y1))
+            ref = O.em_iteration(op, f_o, rho_o, case.mu_T, q_prev.astype(np.float64), rows=(y0, y1), omr=omr_o)
             ref_soft = ref
             if case.mode == "hard":
                 ref_soft = O.em_iteration(case.oracle_params(mode="soft"), f_o, rho_o, case.mu_T,
-                                          q_prev.astype(np.float64), rows=(y0, y1))
+                                          q_prev.astype(np.float64), rows=(y0, y1), omr=omr_o)
             stats.append(compare_iteration(case, ref, ref_soft, q_g, d_g, L_g, rows=(y0, y1), label=f"iter {t + 1}"))
             q_prev = q_g
         if check_refocus and n_iters > 0:

@@ -27,7 +27,8 @@ def _declared_functions():
 def test_header_declares_the_boundary():
     names = _declared_functions()
     for required in ("lf_em_init", "lf_em_load", "lf_em_iterate", "lf_refocus", "lf_em_state",
-                     "lf_em_destroy", "lf_last_error"):
+                     "lf_em_destroy", "lf_last_error", "lf_server_create", "lf_submit_frame",
+                     "lf_server_drain", "lf_server_destroy"):
         assert required in names, required
 
 
@@ -125,3 +126,16 @@ def test_params_struct_layout_matches_header():
 def test_nan_lambda_is_the_derivation_flag():
     p = _params()
     assert math.isnan(p.lambda_)
+
+
+def test_server_argument_checks_without_device():
+    out = ctypes.c_void_p()
+    lib = LF.lib()
+    assert lib.lf_server_create(ctypes.byref(out), 1 << 30, 0, 8, 0) == LF.LF_EINVAL
+    assert lib.lf_server_create(ctypes.byref(out), 1 << 30, 4, -1, 0) == LF.LF_EINVAL
+    assert lib.lf_server_create(ctypes.byref(out), 1000, 4, 8, 0) == LF.LF_EINVAL   # below 64 KiB
+    assert lib.lf_server_create(None, 1 << 30, 4, 8, 0) == LF.LF_EINVAL
+    assert lib.lf_submit_frame(None, 0, None, None, None, None, None, None, None, LF.lf_done_fn(), None,
+                               None) == LF.LF_EINVAL
+    assert lib.lf_server_drain(None) == LF.LF_EINVAL
+    lib.lf_server_destroy(None)

@@ -1,0 +1,227 @@
+"""Frame server (continuous batching) through the C ABI.
+
+The server runs the same per-pixel steps as the plain context, fused per
+row tile; for integer shifts its outputs equal the plain context's bit for
+bit, and each frame's outputs are the same alone and in any mix of streams.
+"""
+import ctypes
+import sys
+import threading
+
+import numpy as np
+import pytest
+
+from lfcase import random_case, Case, GpuRun
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _outputs(case):
+    return (np.zeros((case.H, case.W, 3), np.float32), np.zeros((case.H, case.W), np.int32),
+            np.zeros((case.K, case.H, case.W), np.float32))
+
+
+class Server:
+    """Test handle of a server.  Output arrays are kept referenced here until
+    the server is drained and destroyed (the server writes them when frames
+    complete), and `with Server(...)` destroys it on every exit path."""
+
+    def __init__(self, budget=1 << 30, streams=16, n_iters=3, staging=0):
+        import paper_2003_11076_amd as LF
+        self.LF = LF
+        self.lock = threading.Lock()
+        self.done = {}
+        self.keep = []
+        self._cb = LF.lf_done_fn(self._on_done)
+        self.srv = LF.lf_server_create(budget, streams, n_iters, staging)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def _on_done(self, fid, status, user):
+        with self.lock:
+            self.done[fid] = status
+
+    def submit(self, stream, case, q=True):
+        rgb, d, qq = _outputs(case)
+        self.keep.append((rgb, d, qq))
+        fid = self.LF.lf_submit_frame(self.srv, stream, case.api_params(), case.views, case.S_P, case.mu_T,
+                                      rgb, d, qq if q else None, self._cb)
+        return fid, (rgb, d, qq)
+
+    def drain(self):
+        self.LF.lf_server_drain(self.srv)
+
+    def stats(self):
+        return self.LF.lf_server_stats(self.srv)
+
+    def close(self):
+        if self.srv:
+            self.LF.lf_server_destroy(self.srv)   # drains first
+            self.srv = None
+        self.keep.clear()
+
+
+def _plain(case, n_iters, q_warm=None):
+    run = GpuRun(case, q_warm=q_warm)
+    run.iterate(n_iters)
+    rgb, d, q, hole = run.refocus()
+    run.close()
+    return rgb, d, q
+
+
+CASES = [
+    dict(K=3, H=9, W=200, D=24, storage="f16"),
+    dict(K=5, H=7, W=300, D=32, storage="f32"),
+    dict(K=7, H=5, W=129, D=40, storage="bf16"),
+    dict(K=9, H=4, W=64, D=16, storage="f16", mode="hard"),
+    dict(K=2, H=3, W=37, D=9, storage="f32", baselines=[0, 1]),
+]
+
+
+@pytest.mark.parametrize("kw", CASES)
+def test_server_equals_plain_context(kw):
+    kw = dict(kw)
+    case = random_case(kw.pop("K"), kw.pop("H"), kw.pop("W"), kw.pop("D"), seed=11, **kw)
+    _say(f"server vs plain context K={case.K} {case.H}x{case.W} D={case.D} {case.storage} {case.mode}")
+    with Server(n_iters=3) as srv:
+        fid, (rgb, d, q) = srv.submit(0, case)
+        srv.drain()
+        assert srv.done == {fid: 0}
+    prgb, pd, pq = _plain(case, 3)
+    assert np.array_equal(d, pd)
+    assert np.array_equal(q, pq)
+    assert np.array_equal(rgb, prgb)
+
+
+def test_server_fractional_shifts_close_to_plain():
+    case = random_case(4, 6, 150, 20, baselines=[-1.5, 0, 0.5, 2.25], d_min=-1.0, d_step=0.5, storage="f32", seed=3)
+    _say("server vs plain context, fractional shifts")
+    with Server(n_iters=3) as srv:
+        fid, (rgb, d, q) = srv.submit(0, case)
+        srv.drain()
+    prgb, pd, pq = _plain(case, 3)
+    assert np.array_equal(d, pd) and np.array_equal(q, pq)
+    assert np.abs(rgb - prgb).max() <= 1e-6       # refocus sums in a different view order
+
+
+def test_server_warm_start_is_previous_weights():
+    c0 = random_case(5, 6, 160, 24, storage="f16", seed=21)
+    c1 = random_case(5, 6, 160, 24, storage="f16", seed=22)
+    _say("server warm start")
+    with Server(n_iters=2) as srv:
+        _, (rgb0, d0, q0) = srv.submit(3, c0)
+        _, (rgb1, d1, q1) = srv.submit(3, c1)
+        srv.drain()
+    prgb, pd, pq = _plain(c1, 2, q_warm=q0)
+    assert np.array_equal(d1, pd) and np.array_equal(q1, pq) and np.array_equal(rgb1, prgb)
+
+
+def _mix_cases():
+    shapes = [(3, 8, 96, 16, "f16"), (5, 12, 200, 32, "f16"), (7, 6, 130, 24, "bf16"), (5, 10, 160, 20, "f32"),
+              (3, 5, 300, 40, "f16"), (9, 4, 80, 12, "f32")]
+    streams = []
+    for si, (K, H, W, D, st) in enumerate(shapes):
+        streams.append([random_case(K, H, W, D, storage=st, seed=100 * si + f) for f in range(3)])
+    return streams
+
+
+def test_same_results_alone_and_in_the_mix():
+    streams = _mix_cases()
+    _say("server: frames alone vs interleaved across 6 streams")
+    alone = {}
+    with Server(n_iters=3) as srv:
+        for si, frames in enumerate(streams):
+            for fi, c in enumerate(frames):
+                _, out = srv.submit(si, c)
+                srv.drain()
+                alone[si, fi] = out
+    mixed = {}
+    with Server(n_iters=3) as srv:
+        for fi in range(3):
+            for si, frames in enumerate(streams):
+                _, out = srv.submit(si, frames[fi])
+                mixed[si, fi] = out
+        srv.drain()
+        st = srv.stats()
+    assert st.completed == 18 and st.failed == 0
+    assert st.mean_batch_frames > 1.0           # frames really shared launches
+    for key in alone:
+        for a, b in zip(alone[key], mixed[key]):
+            assert np.array_equal(a, b), key
+
+
+def test_admission_waits_for_budget_and_drops_nothing():
+    streams = _mix_cases()
+    # every stream's warm weights plus one or two frames fit, not all frames
+    budget = 420 * 1024
+    _say(f"server with a {budget} byte HBM budget")
+    n = 0
+    # ample pinned staging: only the HBM budget limits admission here
+    with Server(budget=budget, n_iters=2, staging=64 << 20) as srv:
+        for fi in range(3):
+            for si, frames in enumerate(streams):
+                srv.submit(si, frames[fi])
+                n += 1
+        srv.drain()
+        st = srv.stats()
+    assert st.completed == n and st.failed == 0
+    assert 0 < st.hbm_peak <= budget
+
+
+def test_submission_backpressure():
+    """Staging full -> LF_EAGAIN.  The first frame's completion callback holds
+    the service thread (at most 30 s) until the test has seen LF_EAGAIN, so
+    the staged frames cannot complete in the meantime."""
+    import paper_2003_11076_amd as LF
+    case = random_case(5, 16, 256, 16, storage="f16", seed=5)
+    _say("server staging back-pressure")
+    release = threading.Event()
+    got_eagain = False
+    with Server(n_iters=1, staging=700 * 1024) as srv:      # two frames of 311 KB fit
+        first = {}
+
+        def hold(fid, status, user):
+            if not first.get("held"):          # the first completion holds the service thread
+                first["held"] = True
+                release.wait(30.0)
+            srv._on_done(fid, status, user)
+
+        srv._cb = LF.lf_done_fn(hold)
+        try:
+            for i in range(20):
+                try:
+                    srv.submit(i % 4, case)
+                except LF.LFError as e:
+                    assert e.status == LF.LF_EAGAIN
+                    got_eagain = True
+                    break
+        finally:
+            release.set()
+        srv.drain()
+        srv.submit(0, case)                       # accepted again once frames completed
+        srv.drain()
+    assert got_eagain
+
+
+def test_server_rejects_bad_frames():
+    import paper_2003_11076_amd as LF
+    case = random_case(3, 4, 32, 8, storage="f32", seed=1)
+    _say("server argument checks")
+    with Server(streams=2) as srv:
+        with pytest.raises(LF.LFError) as e:
+            srv.submit(5, case)
+        assert e.value.status == LF.LF_EINVAL
+        big = random_case(10, 2, 16, 4, storage="f32", seed=1)
+        with pytest.raises(LF.LFError) as e:
+            srv.submit(0, big)
+        assert e.value.status == LF.LF_EINVAL

@@ -120,12 +120,14 @@ def test_ray_prior_is_interp_of_SP(storage):
     S_P = RNG.uniform(0, 1, (K, H, W)).astype(np.float32)
     mu = RNG.uniform(-3, 12, (H, W)).astype(np.float32)
     p = _params(K, H, W, b, 8, 100.0, ref=1, storage=storage)
-    rho, q0 = O.ray_prior(p, S_P, mu)
+    pr = O.ray_prior(p, S_P, mu)
+    rho, q0 = pr
     sp = S_P.astype(np.float16).astype(np.float64) if storage == "f16" else S_P.astype(np.float64)
     for k in range(K):
         for y in range(H):
-            want = _interp_row(sp[k, y], np.arange(W) - b[k] * mu[y].astype(np.float64))
-            np.testing.assert_allclose(rho[k, y], want, rtol=0, atol=1e-15)
+            u = np.arange(W) - b[k] * mu[y].astype(np.float64)
+            np.testing.assert_allclose(rho[k, y], _interp_row(sp[k, y], u), rtol=0, atol=1e-15)
+            np.testing.assert_allclose(pr.omr[k, y], _interp_row(1.0 - sp[k, y], u), rtol=1e-14, atol=0)
     assert np.array_equal(q0, (rho >= 0.7).astype(np.float64))
 
 
@@ -388,3 +390,18 @@ def test_median3_matches_scipy():
     out = O.median3(p, rgb)
     for c in range(3):
         assert np.array_equal(out[:, :, c], median_filter(rgb[:, :, c], size=3, mode="nearest"))
+
+
+def test_dynamic_prior_keeps_relative_accuracy_near_certainty():
+    # rho within 1e-12 of 1: omr carries the dynamic prior to full relative
+    # precision (the E-step takes its logarithm)
+    K, H, W = 2, 1, 4
+    S_P = np.array([[[1.0, np.float32(1.0 - 2 ** -20), 1.0, 1.0]], [[0.5] * 4]], np.float32)
+    mu = np.full((H, W), 1e-6, np.float32)
+    p = _params(K, H, W, [0.0, 1.0], 4, 100.0, ref=0)
+    pr = O.ray_prior(p, np.ascontiguousarray(S_P[[1, 0]]), mu)
+    u = 2 - 1.0 * np.float64(np.float32(1e-6))          # view 1, pixel 2: just left of column 2
+    t = u - np.floor(u)
+    want = (1 - t) * 2.0 ** -20                          # interpolation of 1 - S_P between columns 1 and 2
+    assert abs(pr.omr[1, 0, 2] - want) <= 1e-12 * want
+    assert pr.omr[1, 0, 3] == 0.0 and pr[0][1, 0, 3] == 1.0   # exact certainty stays exact
