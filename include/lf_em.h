@@ -127,7 +127,8 @@ lf_status lf_em_load(lf_ctx *c, const uint8_t *views, const float *S_P, const fl
  *               sum_p L_t(p) after each iteration, L_t(p) = ln(gamma +
  *               exp(-(d_t-mu)^2/(2 sigma^2))) + sum_k logaddexp(a1_k, a0_k)
  *               (SOFT) or sum_k max(a1_k, a0_k) (HARD); summed in FP64.
- *               With NULL the call only queues work and returns.
+ *               With NULL the call only queues work and returns, and only the
+ *               last iteration's objective is formed (for lf_em_state).
  * iterate(a) followed by iterate(b) gives bit-identical state to iterate(a+b).
  * Errors: LF_EINVAL (n_iters < 0), LF_ESTATE (no frame loaded), LF_EDEVICE.
  */

@@ -101,6 +101,9 @@ Geometry make_geometry(const lf_params *p) {
     }
     g.dmin_i = g.frac ? 0 : (int)p->d_min;
     g.dstep_i = g.frac ? 0 : (int)p->d_step;
+    g.sym = !g.frac && g.dstep_i == 1 && p->ref == (p->K - 1) / 2;
+    for (int k = 0; k < p->K && g.sym; ++k)
+        if (g.bi[k] != k - p->ref) g.sym = false;
     if (!g.frac) {
         // integer levels must also keep integer shifts inside int range
         for (int k = 0; k < p->K; ++k) {
@@ -123,7 +126,8 @@ size_t em_window_pairs(const lf_params *p, const Geometry &g, int tile) {
         } else {
             const long long dmax_i = g.dmin_i + (long long)(p->D - 1) * g.dstep_i;
             const long long s0 = (long long)g.bi[k] * g.dmin_i, s1 = (long long)g.bi[k] * dmax_i;
-            tot += (size_t)tile + (size_t)std::llabs(s1 - s0);
+            const size_t len = (size_t)tile + (size_t)std::llabs(s1 - s0);
+            tot += len;
         }
     }
     return tot;
@@ -137,11 +141,11 @@ size_t rec_bytes(int storage) { return storage == LF_F32 ? 16 : 8; }
 // ---------------------------------------------------------------------------
 // Kernel dispatch over (K, storage, integer/fractional shifts, sweep kind).
 // ---------------------------------------------------------------------------
-EmKernel pick_em(int K, int st, bool frac, bool exh) {
+EmKernel pick_em(int K, int st, bool frac, bool exh, bool sym) {
     switch (st) {
-        case LF_F32: return pick_em_f32(K, frac, exh);
-        case LF_F16: return pick_em_f16(K, frac, exh);
-        default: return pick_em_bf16(K, frac, exh);
+        case LF_F32: return pick_em_f32(K, frac, exh, sym);
+        case LF_F16: return pick_em_f16(K, frac, exh, sym);
+        default: return pick_em_bf16(K, frac, exh, sym);
     }
 }
 
@@ -230,7 +234,7 @@ EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
 }
 
 hipError_t launch_em(const lf_params *p, const Geometry &g, EmArgs a, int tile, size_t lds, hipStream_t s) {
-    EmKernel kern = pick_em(p->K, p->storage, g.frac, (p->flags & LF_EXHAUSTIVE_SWEEP) != 0);
+    EmKernel kern = pick_em(p->K, p->storage, g.frac, (p->flags & LF_EXHAUSTIVE_SWEEP) != 0, g.sym);
     a.tile = tile;
     dim3 block(tile), grid((p->W + tile - 1) / tile, p->H);
     a.n_blocks = grid.x * grid.y;
@@ -500,6 +504,7 @@ lf_status lf_em_iterate(lf_ctx *c, int32_t n_iters, double *objective) {
         const int n = std::min(kMaxItersPerLaunch, n_iters - done);
         a.n_iters = n;
         a.seed_from_d = (c->iters + done) > 0;   // start the sweep at the last level
+        a.want_obj = objective != nullptr;      // else only the last iteration's (kept as L_pix)
         LF_HIP(launch_em(&c->p, c->g, a, c->tile, c->lds, c->stream), "EM launch");
         if (objective) {
             LF_HIP(hipMemcpyAsync(c->h_obj, c->obj, (size_t)n * c->n_blocks * 8, hipMemcpyDeviceToHost, c->stream),

@@ -9,16 +9,18 @@
 namespace lfem {
 
 template <int K, int ST>
-static EmKernel pick_em_k(bool frac, bool exh) {
-    if (exh) return frac ? (EmKernel)lf_em_kernel<K, ST, true, true> : (EmKernel)lf_em_kernel<K, ST, false, true>;
-    return frac ? (EmKernel)lf_em_kernel<K, ST, true, false> : (EmKernel)lf_em_kernel<K, ST, false, false>;
+static EmKernel pick_em_k(bool frac, bool exh, bool sym) {
+    if (exh)
+        return frac ? (EmKernel)lf_em_kernel<K, ST, true, true, false> : (EmKernel)lf_em_kernel<K, ST, false, true, false>;
+    if (frac) return (EmKernel)lf_em_kernel<K, ST, true, false, false>;
+    return sym ? (EmKernel)lf_em_kernel<K, ST, false, false, true> : (EmKernel)lf_em_kernel<K, ST, false, false, false>;
 }
 
 template <int ST>
-static EmKernel pick_em_storage(int K, bool frac, bool exh) {
+static EmKernel pick_em_storage(int K, bool frac, bool exh, bool sym) {
     switch (K) {
 #define LF_CASE(n) \
-    case n: return pick_em_k<n, ST>(frac, exh);
+    case n: return pick_em_k<n, ST>(frac, exh, sym);
         LF_CASE(2) LF_CASE(3) LF_CASE(4) LF_CASE(5) LF_CASE(6) LF_CASE(7) LF_CASE(8) LF_CASE(9)
         LF_CASE(10) LF_CASE(11) LF_CASE(12) LF_CASE(13) LF_CASE(14) LF_CASE(15) LF_CASE(16)
 #undef LF_CASE

@@ -3,6 +3,6 @@
 #include "lf_serve_kernels.h"
 
 namespace lfem {
-EmKernel pick_em_f16(int K, bool frac, bool exh) { return pick_em_storage<1>(K, frac, exh); }
+EmKernel pick_em_f16(int K, bool frac, bool exh, bool sym) { return pick_em_storage<1>(K, frac, exh, sym); }
 ServeKernel pick_serve_f16() { return (ServeKernel)lf_serve_kernel<1>; }
 }  // namespace lfem

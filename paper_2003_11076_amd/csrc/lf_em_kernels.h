@@ -15,6 +15,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lfem {
 
 constexpr int kMaxViews = 16;
@@ -143,7 +145,8 @@ __device__ __forceinline__ void ray_prior_value(const float *row, int W, int x, 
 // (3 FMAs per view) and re-evaluates a level exactly, with the two-pass
 // weighted spread of the exhaustive sweep, whenever it could beat the best
 // exact energy so far: E^ - M <= E_best, M = beta' margin_k S + margin_c a
-// bound of |E^ - E| for this formula in FP32.  The sweep is seeded with the
+// bound of |E^ - E| for this formula in FP32 (margin_k carries a factor 4
+// of slack over the bound, which also covers the folded form evaluated).  The sweep is seeded with the
 // previous iteration's level, so re-evaluations are rare, and the arg min and
 // tie rule (lowest level) are exactly those of the exhaustive sweep.  The
 // prior term is evaluated only inside a wave-uniform window |d - mu| <= T;
@@ -160,6 +163,7 @@ struct EmArgs {
     float *lpix;          // [H][W], objective of the last iteration
     double *obj;          // [n_iters][n_blocks] block sums of the objective
     int H, W, D, n_iters, n_blocks, tile, mode, seed_from_d;
+    int want_obj;         // objective of every iteration (else only of the last)
     int dmin_i, dstep_i;  // integer levels (integer-shift path)
     float d_min, d_step;
     float beta_p;         // beta / K
@@ -205,8 +209,10 @@ __device__ __forceinline__ float rec_n(const typename Rec<ST>::T &r) {
     else return r.y;
 }
 
+// LDS window of one view for one row tile: positions umin .. umin+len-1 of
+// the view's row (replicated border), one record each, consecutive.
 struct Window {
-    int umin, off, len;  // first staged position, offset in LDS (records), staged length
+    int umin, off, len;  // first staged position, offset in LDS (records), staged positions
 };
 
 template <int K, bool FRAC>
@@ -234,6 +240,23 @@ __device__ __forceinline__ void view_windows(const EmArgs &a, int x0, Window (&w
     total = off;
 }
 
+// LDS record index of staged position p (0 <= p < len) of a window.
+__device__ __forceinline__ int win_index(const Window &w, int p) { return w.off + p; }
+
+// Record index of a lane's footprint at level 0 (integer shifts); level j is
+// at that index - b_k * d_step * j.
+__device__ __forceinline__ int lane_index0(const Window &w, int bi, int dmin_i, int x) {
+    return win_index(w, x - bi * dmin_i - w.umin);
+}
+
+// Unit-spaced symmetric arrays (b_k = k - ref, ref = (K-1)/2, d_step = 1):
+// the baseline of kernel view kk (kernel view 0 is the reference, the others
+// follow in array order) is a compile-time constant.
+template <int K>
+__host__ __device__ constexpr int sym_baseline(int kk) {
+    return kk == 0 ? 0 : ((kk - 1 < (K - 1) / 2 ? kk - 1 : kk) - (K - 1) / 2);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -252,10 +275,11 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
-// Descriptor (and |f|^2) of kernel view k at level j for pixel x.
+// Descriptor (and |f|^2) of kernel view k at level j for pixel x; idx0 is
+// the lane's level-0 record index of the view (integer shifts).
 template <int K, int ST, bool FRAC>
 __device__ __forceinline__ void fetch(const typename Rec<ST>::T *win, const Window &w, const EmArgs &a, int k,
-                                      int x, int j, float2 &f, float &n) {
+                                      int x, int j, int idx0, float2 &f, float &n) {
     if (FRAC) {
         const float d = fmaf((float)j, a.d_step, a.d_min);
         int i0;
@@ -268,7 +292,7 @@ __device__ __forceinline__ void fetch(const typename Rec<ST>::T *win, const Wind
         f = make_float2(lerp(v0.x, v1.x, t), lerp(v0.y, v1.y, t));
         n = fmaf(f.x, f.x, f.y * f.y);
     } else {
-        const typename Rec<ST>::T r = win[w.off + x - a.bi[k] * (a.dmin_i + j * a.dstep_i) - w.umin];
+        const typename Rec<ST>::T r = win[idx0 - a.bi[k] * a.dstep_i * j];
         f = rec_f<ST>(r);
         n = rec_n<ST>(r);
     }
@@ -316,7 +340,12 @@ struct Lane {
     float mu;      // prior disparity
     float L;       // objective after the last E-step
     int best_j;    // level of the last M-step (seed of the next sweep)
+    int idx0[K];   // level-0 LDS record index of each view (integer shifts)
 };
+
+// Levels swept per unrolled group: the group's records stay in registers.
+template <int K>
+constexpr int sweep_group() { return K - 1 <= 4 ? 4 : (K - 1 <= 8 ? 2 : 1); }
 
 // Wave-uniform window [jlo, jhi] of levels where the log prior differs from
 // the constant ln(gamma); outside it gamma + g rounds to gamma in FP32.
@@ -342,9 +371,12 @@ __device__ __forceinline__ int nearest_level(const EmArgs &a, float mu) {
 
 // One EM iteration of one active lane: M-step sweep over all levels with the
 // current weights, then the E-step and the objective at the chosen level.
-template <int K, int ST, bool FRAC, bool EXH>
+constexpr float kLog2e = 1.44269504088896341f;
+
+template <int K, int ST, bool FRAC, bool EXH, bool SYM>
 __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, const Window (&w)[K], const EmArgs &a,
-                                             int x, int jlo, int jhi, float Pc, Lane<K> &s) {
+                                             int x, int jlo, int jhi, float Pc, Lane<K> &s, bool with_obj) {
+    using R = typename Rec<ST>::T;
     // ---- M-step: weights from the previous E-step (or the start) ----
     float Q = 0.0f;
 #pragma unroll
@@ -366,7 +398,7 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
             float nn, mx, my;
             f[0] = s.f0;
 #pragma unroll
-            for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, j, f[k], nn);
+            for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, j, s.idx0[k], f[k], nn);
             const float E = exact_energy<K>(f, wt, invW, cw, log_prior(a, j, mu), mx, my);
             if (E < best_E) {
                 best_E = E;
@@ -381,44 +413,74 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
             float nn, mx, my;
             f[0] = s.f0;
 #pragma unroll
-            for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, best_j, f[k], nn);
+            for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, best_j, s.idx0[k], f[k], nn);
             best_E = exact_energy<K>(f, wt, invW, cw, log_prior(a, best_j, mu), mx, my);
         }
         const float A0x = wt[0] * s.f0.x, A0y = wt[0] * s.f0.y, S0 = wt[0] * s.n0;
-        const float cwm = cw * a.margin_k;
-        auto level = [&](int j, float Pj) {
-            float2 f[K];
-            f[0] = s.f0;
-            float ax = A0x, ay = A0y, S = S0;
+        // candidate test  E^ - M <= E_best  with the margin folded in:
+        //   cw (1 - margin_k) S - (cw / W) |A|^2  <=  E_best + margin_c + P_j
+        const float alpha = cw * (1.0f - a.margin_k), gam = cw * invW;
+        float bound = best_E + a.margin_c;
+        // Scores G consecutive levels from j0, then re-evaluates the
+        // candidates among them exactly, in increasing level order.
+        auto group = [&](auto Gc, int j0, bool inwin) {
+            constexpr int G = decltype(Gc)::value;
+            float2 f[G][K];
+            float lhs[G], P[G];
 #pragma unroll
-            for (int k = 1; k < K; ++k) {
-                float n;
-                fetch<K, ST, FRAC>(win, w[k], a, k, x, j, f[k], n);
-                ax = fmaf(wt[k], f[k].x, ax);
-                ay = fmaf(wt[k], f[k].y, ay);
-                S = fmaf(wt[k], n, S);
+            for (int i = 0; i < G; ++i) {
+                f[i][0] = s.f0;
+                float ax = A0x, ay = A0y, S = S0;
+#pragma unroll
+                for (int k = 1; k < K; ++k) {
+                    float n;
+                    if constexpr (FRAC) {
+                        fetch<K, ST, FRAC>(win, w[k], a, k, x, j0 + i, 0, f[i][k], n);
+                    } else if constexpr (SYM) {
+                        // compile-time step per level: immediate LDS offsets
+                        const int b = sym_baseline<K>(k);   // folds once k is unrolled
+                        const R *base = win + s.idx0[k] - b * (b > 0 ? j0 + G - 1 : j0);
+                        const R r = base[b > 0 ? b * (G - 1 - i) : -b * i];
+                        f[i][k] = rec_f<ST>(r);
+                        n = rec_n<ST>(r);
+                    } else {
+                        const R r = win[s.idx0[k] - a.bi[k] * a.dstep_i * (j0 + i)];
+                        f[i][k] = rec_f<ST>(r);
+                        n = rec_n<ST>(r);
+                    }
+                    ax = fmaf(wt[k], f[i][k].x, ax);
+                    ay = fmaf(wt[k], f[i][k].y, ay);
+                    S = fmaf(wt[k], n, S);
+                }
+                P[i] = inwin ? log_prior(a, j0 + i, mu) : Pc;
+                lhs[i] = fmaf(-gam, fmaf(ax, ax, ay * ay), alpha * S);
             }
-            const float Chat = fmaf(-fmaf(ax, ax, ay * ay), invW, S);
-            const float Ehat = fmaf(cw, Chat, -Pj);
-            // the current best level is already exact: skip it
-            const bool cand = (Ehat - fmaf(cwm, S, a.margin_c)) <= best_E && j != best_j;
-            if (__any(cand)) {
-                if (cand) {
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                const int j = j0 + i;
+                // the current best level is already exact: skip it
+                if (lhs[i] <= bound + P[i] && j != best_j) {
                     float mx, my;
-                    const float E = exact_energy<K>(f, wt, invW, cw, Pj, mx, my);
+                    const float E = exact_energy<K>(f[i], wt, invW, cw, P[i], mx, my);
                     if (E < best_E || (E == best_E && j < best_j)) {
                         best_E = E;
                         best_j = j;
+                        bound = best_E + a.margin_c;
                     }
                 }
             }
         };
+        constexpr int G = sweep_group<K>();
+        auto sweep = [&](int jb, int je, bool inwin) {
+            int j = jb;
+            for (; j + G <= je; j += G) group(std::integral_constant<int, G>{}, j, inwin);
+            for (; j < je; ++j) group(std::integral_constant<int, 1>{}, j, inwin);
+        };
         // levels below, inside and above the prior window
-        const int j1 = min(jlo, a.D), j2 = min(jhi + 1, a.D);
-        int j = 0;
-        for (; j < j1; ++j) level(j, Pc);
-        for (; j < j2; ++j) level(j, log_prior(a, j, mu));
-        for (; j < a.D; ++j) level(j, Pc);
+        const int j1 = min(jlo, a.D), j2 = max(min(jhi + 1, a.D), j1);
+        sweep(0, j1, false);
+        sweep(j1, j2, true);
+        sweep(j2, a.D, false);
     }
     s.best_j = best_j;
 
@@ -427,10 +489,12 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
     float nn, mx, my;
     f[0] = s.f0;
 #pragma unroll
-    for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, best_j, f[k], nn);
+    for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, best_j, s.idx0[k], f[k], nn);
     (void)exact_energy<K>(f, wt, invW, cw, 0.0f, mx, my);
-    const float t = fmaf((float)best_j, a.d_step, a.d_min) - mu;
-    float L = logf(a.gamma + expf(-(t * t) * a.c_exp));
+    // posterior in the logit domain with the hardware base-2 exponential and
+    // reciprocal (about 1e-7 absolute error; q = 0 or 1 exactly at +-inf)
+    float L = 0.0f;
+    if (with_obj) L = log_prior(a, best_j, mu);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const float dx = f[k].x - mx, dy = f[k].y - my;
@@ -439,17 +503,20 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
         const float a0 = s.lb[k];
         if (a.mode == 1) {
             s.q[k] = (a1 >= a0) ? 1.0f : 0.0f;
-            L += fmaxf(a1, a0);
+            if (with_obj) L += fmaxf(a1, a0);
         } else {
-            s.q[k] = 1.0f / (1.0f + __expf(a0 - a1));
-            const float hi = fmaxf(a1, a0);
-            L += hi + log1pf(expf(-fabsf(a1 - a0)));
+            s.q[k] = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f((a0 - a1) * kLog2e));
+            if (with_obj) {
+                // logaddexp(a1, a0) = max + ln(1 + exp(-|a1 - a0|))
+                const float r = __builtin_amdgcn_exp2f(-fabsf(a1 - a0) * kLog2e);
+                L += fmaxf(a1, a0) + kLn2 * __builtin_amdgcn_logf(1.0f + r);
+            }
         }
     }
     s.L = L;
 }
 
-template <int K, int ST, bool FRAC, bool EXH>
+template <int K, int ST, bool FRAC, bool EXH, bool SYM>
 __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
     using R = typename Rec<ST>::T;
     using P = typename Pair<ST>::T;
@@ -475,7 +542,7 @@ __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
     for (int k = 0; k < K; ++k) {
         const P *row = feat + ((size_t)a.perm[k] * a.H + y) * a.W;
         for (int p = tid; p < w[k].len; p += blockDim.x)
-            win[w[k].off + p] = make_rec<ST>(row[clampi(w[k].umin + p, 0, a.W - 1)]);
+            win[win_index(w[k], p)] = make_rec<ST>(row[clampi(w[k].umin + p, 0, a.W - 1)]);
     }
     __syncthreads();
 
@@ -496,7 +563,9 @@ __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
             s.lb[k] = (om > 0.0f ? logf(om) : -INFINITY);            // ln(1 - rho)
         }
         s.best_j = a.seed_from_d ? a.d_idx[pix] : nearest_level(a, s.mu);
-        fetch<K, ST, FRAC>(win, w[0], a, 0, x, 0, s.f0, s.n0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) s.idx0[k] = FRAC ? 0 : lane_index0(w[k], a.bi[k], a.dmin_i, x);
+        fetch<K, ST, FRAC>(win, w[0], a, 0, x, 0, s.idx0[0], s.f0, s.n0);
     } else {
 #pragma unroll
         for (int k = 0; k < K; ++k) s.q[k] = s.la[k] = s.lb[k] = 0.0f;
@@ -508,7 +577,9 @@ __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
 
     const int block_id = blockIdx.y * gridDim.x + blockIdx.x;
     for (int it = 0; it < a.n_iters; ++it) {
-        if (active) em_iteration<K, ST, FRAC, EXH>(win, w, a, x, jlo, jhi, Pc, s);
+        const bool with_obj = a.want_obj || it == a.n_iters - 1;
+        if (active) em_iteration<K, ST, FRAC, EXH, SYM>(win, w, a, x, jlo, jhi, Pc, s, with_obj);
+        if (!with_obj) continue;
         // ---- FP64 block sum of the objective ----
         double sum = wave_sum(active ? (double)s.L : 0.0);
         const int lane = tid & 63, wv = tid >> 6;

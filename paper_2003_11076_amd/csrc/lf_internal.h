@@ -16,9 +16,9 @@ struct EmArgs;
 struct RefocusArgs;
 using EmKernel = void (*)(EmArgs);
 
-EmKernel pick_em_f32(int K, bool frac, bool exh);
-EmKernel pick_em_f16(int K, bool frac, bool exh);
-EmKernel pick_em_bf16(int K, bool frac, bool exh);
+EmKernel pick_em_f32(int K, bool frac, bool exh, bool sym);
+EmKernel pick_em_f16(int K, bool frac, bool exh, bool sym);
+EmKernel pick_em_bf16(int K, bool frac, bool exh, bool sym);
 
 struct ServeJob;
 using ServeKernel = void (*)(const ServeJob *, int);
@@ -31,6 +31,7 @@ ServeKernel pick_serve_bf16();
 // directly; otherwise they interpolate (frac = true).
 struct Geometry {
     bool frac;
+    bool sym;   // integer shifts of a unit-spaced array centred on the reference, d_step = 1
     int dmin_i, dstep_i;
     int bi[LF_MAX_VIEWS];
 };

@@ -26,9 +26,8 @@ struct ServeJob {
     const float *q_warm;     // [K][H][W] previous weights of the stream, or null (threshold start)
     float *rgb;              // [H][W][3]
     uint8_t *hole;           // [H][W]
-    int K, ref, frac, tiles_x, tile_start, n_tiles;
+    int K, ref, frac, sym, tiles_x, tile_start, n_tiles;
     float tau;
-    int pad_;
 };
 
 // LDS bytes a job needs: descriptor records plus three int16 rows of
@@ -36,7 +35,7 @@ struct ServeJob {
 template <int ST>
 __host__ __device__ inline size_t serve_rec_bytes() { return ST == 0 ? 16 : 8; }
 
-template <int K, int ST, bool FRAC>
+template <int K, int ST, bool FRAC, bool SYM>
 __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsigned char *lds) {
     using R = typename Rec<ST>::T;
     const EmArgs &a = job.em;
@@ -54,6 +53,7 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
     view_windows<K, FRAC>(a, x0, w, total);
     R *win = reinterpret_cast<R *>(lds);
     int16_t *lsum = reinterpret_cast<int16_t *>(lds + (size_t)total * sizeof(R));
+    // staged positions of all windows (the intensity rows are sized by these)
 
     // 1) rows y-1, y, y+1 of R+G+B over each window's columns (+1 border)
     int c0[K], nc[K], loff[K];
@@ -87,7 +87,7 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
             const int gx = (L0[cr] - L0[cl]) + 2 * (L1[cr] - L1[cl]) + (L2[cr] - L2[cl]);
             const int gy = (L2[cl] - L0[cl]) + 2 * (L2[cm] - L0[cm]) + (L2[cr] - L0[cr]);
             const float sc = 1.0f / 4096.0f;
-            win[w[k].off + p] = make_rec<ST>(make_pair<ST>((float)gx * sc, (float)gy * sc));
+            win[win_index(w[k], p)] = make_rec<ST>(make_pair<ST>((float)gx * sc, (float)gy * sc));
         }
     }
     __syncthreads();
@@ -111,7 +111,9 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
             s.q[k] = job.q_warm ? job.q_warm[row + x] : ((r >= job.tau) ? 1.0f : 0.0f);
         }
         s.best_j = nearest_level(a, s.mu);
-        fetch<K, ST, FRAC>(win, w[0], a, 0, x, 0, s.f0, s.n0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) s.idx0[k] = FRAC ? 0 : lane_index0(w[k], a.bi[k], a.dmin_i, x);
+        fetch<K, ST, FRAC>(win, w[0], a, 0, x, 0, s.idx0[0], s.f0, s.n0);
     } else {
 #pragma unroll
         for (int k = 0; k < K; ++k) s.q[k] = s.la[k] = s.lb[k] = 0.0f;
@@ -122,7 +124,7 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
     int jlo, jhi;
     prior_window(a, active, s.mu, jlo, jhi);
     if (active)
-        for (int it = 0; it < a.n_iters; ++it) em_iteration<K, ST, FRAC, false>(win, w, a, x, jlo, jhi, Pc, s);
+        for (int it = 0; it < a.n_iters; ++it) em_iteration<K, ST, FRAC, false, SYM>(win, w, a, x, jlo, jhi, Pc, s, false);
 
     // 5) outputs: weights, level, refocus of the static rays
     if (active) {
@@ -193,10 +195,11 @@ __global__ __launch_bounds__(kServeTile) void lf_serve_kernel(const ServeJob *__
     const int tile = (int)blockIdx.x - job.tile_start;
     const bool frac = job.frac != 0;
     switch (job.K) {
-#define LF_SERVE_CASE(n)                                         \
-    case n:                                                      \
-        if (frac) serve_tile<n, ST, true>(job, tile, lds);       \
-        else serve_tile<n, ST, false>(job, tile, lds);           \
+#define LF_SERVE_CASE(n)                                              \
+    case n:                                                           \
+        if (frac) serve_tile<n, ST, true, false>(job, tile, lds);     \
+        else if (job.sym) serve_tile<n, ST, false, true>(job, tile, lds); \
+        else serve_tile<n, ST, false, false>(job, tile, lds);         \
         break;
         LF_SERVE_CASE(2) LF_SERVE_CASE(3) LF_SERVE_CASE(4) LF_SERVE_CASE(5)
         LF_SERVE_CASE(6) LF_SERVE_CASE(7) LF_SERVE_CASE(8) LF_SERVE_CASE(9)

@@ -207,6 +207,7 @@ bool launch_batch(lf_server *s, SrvBatch *b, std::string &err) {
             J.K = p.K;
             J.ref = p.ref;
             J.frac = f->g.frac ? 1 : 0;
+            J.sym = f->g.sym ? 1 : 0;
             J.tiles_x = f->tiles_x;
             J.tile_start = tiles[stg];
             J.n_tiles = f->n_tiles;
