@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the frame-server legs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM traffic counters)")
     return ap.parse_args()
@@ -77,6 +78,212 @@ def cpu_baseline(spec, frame, storage, mode, budget_s):
             "frames_per_s": frames / el}
 
 
+# ---------------------------------------------------------------------------
+# Serving leg: the frame server under the 16-stream mix, and on the bench
+# workload's frames for a like-for-like comparison with the plain path.
+# ---------------------------------------------------------------------------
+
+def _frame_arrays(spec):
+    import lf_scenes as S
+    fr = S.make_frame(spec)
+    return spec, fr.views, fr.S_P, fr.mu_T, fr.beta
+
+
+def _make_frames(specs, workers):
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_frame_arrays, specs))
+
+
+class _Driver:
+    """Submits frames to a server from a few threads (submission copies the
+    inputs) and keeps each frame's output arrays alive until it completes."""
+
+    def __init__(self, LF, srv, frames, storage):
+        import queue
+        import threading
+        self.LF, self.srv, self.frames = LF, srv, frames
+        self.params = []
+        for spec, views, sp, mu, beta in frames:
+            self.params.append(LF.make_params(spec.K, spec.H, spec.W, spec.ref, spec.baselines, spec.d_min,
+                                              spec.d_step, spec.D, beta, gamma=spec.gamma, sigma=spec.sigma,
+                                              tau_init=spec.tau, storage=storage))
+        self.lock = threading.Lock()
+        self.live = {}
+        self.done_q = queue.Queue()
+        self._cb = LF.lf_done_fn(self._on_done)
+
+    def _on_done(self, fid, status, user):
+        self.done_q.put((fid, status))
+
+    def submit(self, stream, idx):
+        import time as _t
+        spec, views, sp, mu, _ = self.frames[idx]
+        out = (np.empty((spec.H, spec.W, 3), np.float32), np.empty((spec.H, spec.W), np.int32))
+        while True:
+            try:
+                fid = self.LF.lf_submit_frame(self.srv, stream, self.params[idx], views, sp, mu, out[0], out[1],
+                                              None, self._cb)
+                break
+            except self.LF.LFError as e:
+                if e.status != self.LF.LF_EAGAIN:
+                    raise
+                _t.sleep(0.0002)
+        with self.lock:
+            self.live[fid] = (stream, out)
+        return fid
+
+    def wait_one(self):
+        fid, status = self.done_q.get()
+        assert status == 0, status
+        with self.lock:
+            stream, _ = self.live.pop(fid)
+        return fid, stream
+
+
+def _units(spec, n_iters):
+    return spec.H * spec.W * spec.D * spec.K * n_iters
+
+
+SERVE_STREAMS = 16
+
+
+def serving_frames(S, log_fn):
+    """Two frames of each of the 16 mix streams.  Generated in worker
+    processes before this process touches the GPU (the workers are forked)."""
+    log_fn(f"serving: generating 2 frames for each of {SERVE_STREAMS} streams")
+    specs = [S.serving_stream_spec(s, f) for s in range(SERVE_STREAMS) for f in range(2)]
+    return _make_frames(specs, min(8, os.cpu_count() or 1))
+
+
+def serve_leg(args, LF, frames, log_fn):
+    import random
+    from concurrent.futures import ThreadPoolExecutor
+    n_streams = SERVE_STREAMS
+    n_iters = frames[0][0].n_iters
+    budget = 1 << 30
+    srv = LF.lf_server_create(budget, n_streams, n_iters, 3 << 30)
+    drv = _Driver(LF, srv, frames, "f16")
+    idx_of = lambda stream, k: 2 * stream + (k % 2)
+    pool = ThreadPoolExecutor(max_workers=4)
+    try:
+        # warm-up: one frame per stream
+        for st in range(n_streams):
+            drv.submit(st, idx_of(st, 0))
+        LF.lf_server_drain(srv)
+        while not drv.done_q.empty():
+            drv.wait_one()
+        # saturation: closed loop, two frames outstanding per stream
+        per_stream = 12
+        LF.lf_server_reset_stats(srv)
+        sent = {st: 0 for st in range(n_streams)}
+        futs = []
+        t0 = time.perf_counter()
+        for st in range(n_streams):
+            for _ in range(2):
+                futs.append(pool.submit(drv.submit, st, idx_of(st, sent[st])))
+                sent[st] += 1
+        completed, units = 0, 0
+        total = n_streams * per_stream
+        while completed < total:
+            fid, st = drv.wait_one()
+            completed += 1
+            units += _units(frames[idx_of(st, 0)][0], n_iters)
+            if sent[st] < per_stream:
+                futs.append(pool.submit(drv.submit, st, idx_of(st, sent[st])))
+                sent[st] += 1
+        t_sat = time.perf_counter() - t0
+        for f in futs:
+            f.result()
+        sat = LF.lf_server_stats(srv)
+        fps_sat = total / t_sat
+        log_fn(f"serving: saturation {fps_sat:.0f} frames/s, p99 {sat.p99_ms:.2f} ms")
+        # open loop: Poisson arrivals at 0.7 x saturation over the 16 streams
+        rate = 0.7 * fps_sat
+        n_frames = max(200, int(rate * 3.0))
+        rng = random.Random(7)
+        LF.lf_server_reset_stats(srv)
+        futs, t = [], 0.0
+        t0 = time.perf_counter()
+        counter = {st: 0 for st in range(n_streams)}
+        for i in range(n_frames):
+            t += rng.expovariate(rate)
+            st = rng.randrange(n_streams)
+            k = counter[st]
+            counter[st] += 1
+            delay = t0 + t - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            futs.append(pool.submit(drv.submit, st, idx_of(st, k)))
+        for f in futs:
+            f.result()
+        LF.lf_server_drain(srv)
+        t_open = time.perf_counter() - t0
+        units_open = 0
+        while not drv.done_q.empty():
+            _, st = drv.wait_one()
+            units_open += _units(frames[idx_of(st, 0)][0], n_iters)
+        op = LF.lf_server_stats(srv)
+    finally:
+        pool.shutdown(wait=True)
+        LF.lf_server_destroy(srv)
+    return {
+        "workload": "serving-mix-fp16-i8: 16 streams, 320x240/640x480/1280x960 (5/8/3 streams), K 3/5/7, "
+                    "D 32/64/128, objects moving 2 px/frame, warm start per stream",
+        "hbm_budget_bytes": budget,
+        "saturation": {"frames_per_s": fps_sat, "gunits_per_s": units / t_sat / 1e9, "p50_ms": sat.p50_ms,
+                       "p99_ms": sat.p99_ms, "mean_batch_frames": sat.mean_batch_frames, "frames": total},
+        "poisson_0.7": {"offered_frames_per_s": rate, "frames_per_s": op.completed / t_open,
+                        "gunits_per_s": units_open / t_open / 1e9, "p50_ms": op.p50_ms, "p99_ms": op.p99_ms,
+                        "mean_batch_frames": op.mean_batch_frames, "frames": int(op.completed),
+                        "hbm_peak_bytes": int(op.hbm_peak)},
+    }
+
+
+def serve_same_workload(args, LF, frame, spec, n_frames=200, n_streams=4):
+    """The bench workload's frame through the FP16 frame server (streams in a
+    closed loop): frames/s and latency beside the plain path's."""
+    from concurrent.futures import ThreadPoolExecutor
+    frames = [(spec, frame.views, frame.S_P, frame.mu_T, frame.beta)]
+    srv = LF.lf_server_create(2 << 30, n_streams, spec.n_iters, 1 << 30)
+    drv = _Driver(LF, srv, frames, "f16")
+    pool = ThreadPoolExecutor(max_workers=4)
+    try:
+        for st in range(n_streams):
+            drv.submit(st, 0)
+        LF.lf_server_drain(srv)
+        while not drv.done_q.empty():
+            drv.wait_one()
+        LF.lf_server_reset_stats(srv)
+        sent = {st: 0 for st in range(n_streams)}
+        per = n_frames // n_streams
+        futs = []
+        t0 = time.perf_counter()
+        for st in range(n_streams):
+            for _ in range(2):
+                futs.append(pool.submit(drv.submit, st, 0))
+                sent[st] += 1
+        done = 0
+        while done < per * n_streams:
+            _, st = drv.wait_one()
+            done += 1
+            if sent[st] < per:
+                futs.append(pool.submit(drv.submit, st, 0))
+                sent[st] += 1
+        dt = time.perf_counter() - t0
+        for f in futs:
+            f.result()
+        stt = LF.lf_server_stats(srv)
+    finally:
+        pool.shutdown(wait=True)
+        LF.lf_server_destroy(srv)
+    units = spec.H * spec.W * spec.D * spec.K * spec.n_iters
+    return {"storage": "f16", "streams": n_streams, "frames_per_s": done / dt,
+            "gunits_per_s": units * done / dt / 1e9, "p50_ms": stt.p50_ms, "p99_ms": stt.p99_ms,
+            "mean_batch_frames": stt.mean_batch_frames,
+            "note": "host inputs and outputs (PCIe copies included), unlike the plain-path line"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -91,6 +298,8 @@ def main():
     storage = args.storage or spec.storage
     log(args, f"generating {spec.name} ({spec.W}x{spec.H}, K={spec.K}, D={spec.D}, I={spec.n_iters})")
     frame = S.make_frame(spec)
+    serve = not args.no_serving and args.config == 2
+    mix_frames = serving_frames(S, lambda m: log(args, m)) if serve else None
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
@@ -189,6 +398,10 @@ def main():
             "algorithmic_hbm_GBps": em_bytes / em_avg_s / 1e9,
         },
     }
+    if serve:
+        log(args, "serving the same workload through the FP16 frame server")
+        out["serving_same_workload"] = serve_same_workload(args, LF, frame, spec)
+        out["serving"] = serve_leg(args, LF, mix_frames, lambda m: log(args, m))
     if not args.no_cpu_baseline:
         log(args, "timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(spec, frame, storage, args.mode, args.cpu_seconds)

@@ -511,6 +511,7 @@ lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, c
                           const float *mu_T, float *rgb_out, int32_t *d_out, float *q_out, lf_done_fn done,
                           void *user, int64_t *frame_id) {
     if (!s) return set_error(LF_EINVAL, "server is NULL");
+    const Clock::time_point t_call = Clock::now();   // latency counts from the call
     lf_status st = validate_params(p);
     if (st != LF_OK) return st;
     if (stream_id < 0 || stream_id >= s->max_streams)
@@ -576,7 +577,7 @@ lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, c
     std::memcpy(h + f->in_views, views, KHW * 3);
     std::memcpy(h + f->in_sp, S_P, KHW * 4);
     std::memcpy(h + f->in_mu, mu_T, HW * 4);
-    f->t_submit = Clock::now();
+    f->t_submit = t_call;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (!s->any) {
