@@ -27,6 +27,9 @@ _SRC = os.path.join(_HERE, "lf_oracle.c")
 _LIB = os.path.join(_HERE, "liblforacle.so")
 MAX_VIEWS = 16
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+# soft / hard: per-view posterior of the factorised model; enum_*: the paper's
+# enumeration of all labelings with the coupled variance (marginals / arg max)
+MODES = {"soft": 0, "hard": 1, "enum_soft": 2, "enum_hard": 3}
 
 
 class Params(ctypes.Structure):
@@ -49,7 +52,7 @@ def make_params(K, H, W, ref, baselines, d_min, d_step, D, beta, lam=float("nan"
     p.d_min, p.d_step, p.D = float(d_min), float(d_step), int(D)
     p.beta, p.lam, p.gamma, p.sigma, p.tau = float(beta), float(lam), float(gamma), float(sigma), float(tau)
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
-    p.mode = {"soft": 0, "hard": 1}[mode] if isinstance(mode, str) else int(mode)
+    p.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     return p
 
 

@@ -33,7 +33,16 @@
  *   - objective L = ln prior(d) + sum_k logaddexp(a1_k, a0_k) (soft) or
  *     sum_k max(a1_k, a0_k) (hard), the quantity EM never decreases;
  *   - refocus with the views whose posterior is >= 0.5 (Eq. 2), keeping the
- *     reference colour where no view is static (Sec. IV-B).
+ *     reference colour where no view is static (Sec. IV-B);
+ *   - enumeration modes (2, 3): the E-step as the paper states it, over all
+ *     2^K labelings S of the rays (Sec. III-C, last sentence; Sec. III-D),
+ *     with the variance of the static descriptors normalised by the number
+ *     of static views (Sec. III-C, Var) and no constant between the static
+ *     and dynamic likelihoods: log weight of S is
+ *       sum_k ln P(S_k | rho_k) - beta Var_S,  Var_S = 0 for fewer than two
+ *     static views.  Mode 2 returns the marginals P(S_k = 1), mode 3 the
+ *     labeling of largest weight (ties: the largest mask, bit k = view k).
+ *     The M-step is unchanged (weights q, beta' = beta / K).
  */
 #include <math.h>
 #include <stdint.h>
@@ -52,7 +61,8 @@ typedef struct {
     int32_t D;
     double beta, lambda, gamma, sigma, tau;
     int32_t storage; /* 0: inputs used as given, 1: rounded to binary16, 2: rounded to bfloat16 */
-    int32_t mode;    /* 0: soft posterior, 1: hard assignment */
+    int32_t mode;    /* 0: soft posterior, 1: hard assignment, 2 / 3: enumeration over all
+                        labelings with the paper's coupled variance, marginals / arg max */
 } lfo_params;
 
 /* ------------------------------------------------------------------------ */
@@ -236,6 +246,65 @@ static double weighted_spread(int K, const double fk[][2], const double *q, doub
     return 0.0;
 }
 
+/* Enumeration E-step (modes 2, 3) of one pixel at the chosen level: fk are
+ * the descriptors there, lr1 / lr0 the logs of rho_k and 1 - rho_k.  Writes
+ * q and returns the log of the summed weights (mode 2) or the largest log
+ * weight (mode 3). */
+static double enumerate_labelings(const lfo_params *p, const double fk[][2], const double *lr1,
+                                  const double *lr0, double *q)
+{
+    const int K = p->K;
+    const int n_masks = 1 << K;
+    double best = -INFINITY, top = -INFINITY;
+    int best_mask = 0;
+    /* first pass: the largest log weight (scales the sums of the second) */
+    for (int pass = 0; pass < 2; ++pass) {
+        double Z = 0.0, acc[LFO_MAX_VIEWS] = {0};
+        for (int mask = 0; mask < n_masks; ++mask) {
+            double lw = 0.0;
+            int n = 0;
+            for (int k = 0; k < K; ++k) {
+                if (mask >> k & 1) { lw += lr1[k]; ++n; }
+                else lw += lr0[k];
+            }
+            double var = 0.0;
+            if (n >= 2) {
+                double m0 = 0.0, m1 = 0.0;
+                for (int k = 0; k < K; ++k)
+                    if (mask >> k & 1) { m0 += fk[k][0]; m1 += fk[k][1]; }
+                m0 /= n;
+                m1 /= n;
+                for (int k = 0; k < K; ++k)
+                    if (mask >> k & 1) {
+                        double a = fk[k][0] - m0, b = fk[k][1] - m1;
+                        var += a * a + b * b;
+                    }
+                var /= n;
+            }
+            lw -= p->beta * var;
+            if (pass == 0) {
+                if (lw >= best) { best = lw; best_mask = mask; }
+            } else if (lw > -INFINITY) {
+                double w = exp(lw - top);
+                Z += w;
+                for (int k = 0; k < K; ++k)
+                    if (mask >> k & 1) acc[k] += w;
+            }
+        }
+        if (pass == 0) {
+            if (p->mode == 3) {
+                for (int k = 0; k < K; ++k) q[k] = (best_mask >> k & 1) ? 1.0 : 0.0;
+                return best;
+            }
+            top = best;
+        } else {
+            for (int k = 0; k < K; ++k) q[k] = acc[k] / Z;
+            return top + log(Z);
+        }
+    }
+    return 0.0;
+}
+
 void lfo_em_iteration(const lfo_params *p, double lambda, const double *f, const double *rho,
                       const double *omr, const float *mu_T, const double *q_in, double *q_out, int32_t *d_idx,
                       double *L_pix, double *E1, double *E2, int32_t y0, int32_t y1)
@@ -268,7 +337,18 @@ void lfo_em_iteration(const lfo_params *p, double lambda, const double *f, const
             gather(p, f, x, y, d, fk);
             weighted_spread(K, fk, q, m);
             double L = log_prior(p, d, mu);
-            for (int k = 0; k < K; ++k) {
+            if (p->mode >= 2) {
+                double lr1[LFO_MAX_VIEWS], lr0[LFO_MAX_VIEWS], qk[LFO_MAX_VIEWS];
+                for (int k = 0; k < K; ++k) {
+                    double r = rho[(size_t)k * H * W + pix];
+                    double r1 = omr ? omr[(size_t)k * H * W + pix] : 1.0 - r;
+                    lr1[k] = r > 0.0 ? log(r) : -INFINITY;
+                    lr0[k] = r1 > 0.0 ? log(r1) : -INFINITY;
+                }
+                L += enumerate_labelings(p, fk, lr1, lr0, qk);
+                for (int k = 0; k < K; ++k) q_out[(size_t)k * H * W + pix] = qk[k];
+            }
+            for (int k = 0; k < K && p->mode < 2; ++k) {
                 double a = fk[k][0] - m[0], b = fk[k][1] - m[1];
                 double e = a * a + b * b;
                 double r = rho[(size_t)k * H * W + pix];

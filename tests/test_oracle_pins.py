@@ -306,6 +306,117 @@ def test_estep_beta_zero_is_logistic_prior():
     np.testing.assert_allclose(out["q"], expit(logit(rho) + lam), rtol=1e-12)
 
 
+# ---------------------------------------------------------------- enumeration E-step
+
+def _enum_case(K, H, W, b, beta, mode, rng, rho_lo=0.02, rho_hi=0.98, views=None):
+    views = _random_views(K, H, W, rng) if views is None else views
+    mu = rng.uniform(0, 4, (H, W)).astype(np.float32)
+    p = _params(K, H, W, b, 6, beta, mode=mode)
+    f = O.descriptors(p, views)
+    rho = rng.uniform(rho_lo, rho_hi, (K, H, W))
+    q_in = rng.uniform(0, 1, (K, H, W))
+    return p, f, rho, mu, q_in, O.em_iteration(p, f, rho, mu, q_in)
+
+
+@pytest.mark.parametrize("mode", ["enum_soft", "enum_hard"])
+def test_enum_two_views_closed_form(mode):
+    """K = 2: only the labeling with both views static has a variance, and
+    the population variance of two vectors is a quarter of their squared
+    distance; the other three labelings weigh by their priors alone."""
+    rng = np.random.default_rng(41)
+    beta = 40.0
+    p, f, rho, mu, q_in, out = _enum_case(2, 3, 14, [0.0, 1.0], beta, mode, rng)
+    for y in range(3):
+        for x in range(14):
+            d = float(out["d_idx"][y, x])
+            g = _gathered(f, [0.0, 1.0], y, x, d)
+            r1, r2 = rho[0, y, x], rho[1, y, x]
+            w11 = r1 * r2 * math.exp(-beta * float(((g[0] - g[1]) ** 2).sum()) / 4.0)
+            w10, w01, w00 = r1 * (1 - r2), (1 - r1) * r2, (1 - r1) * (1 - r2)
+            Z = w11 + w10 + w01 + w00
+            prior = math.log(p.gamma + math.exp(-(d - float(mu[y, x])) ** 2 / (2 * p.sigma ** 2)))
+            if mode == "enum_soft":
+                np.testing.assert_allclose(out["q"][:, y, x], [(w11 + w10) / Z, (w11 + w01) / Z], rtol=1e-12)
+                assert math.isclose(out["L"][y, x], prior + math.log(Z), rel_tol=1e-12)
+            else:
+                ws = {(1, 1): w11, (1, 0): w10, (0, 1): w01, (0, 0): w00}
+                best = max(ws, key=ws.get)
+                assert tuple(out["q"][:, y, x]) == best
+                assert math.isclose(out["L"][y, x], prior + math.log(ws[best]), rel_tol=1e-12)
+
+
+def test_enum_matches_brute_force_with_numpy_var():
+    """K = 4: marginals and the arg max of the joint over all 16 labelings,
+    weighted by exp(-beta numpy.var(static descriptors)) and the priors."""
+    rng = np.random.default_rng(42)
+    b = [-1.0, 0.0, 1.0, 2.0]
+    beta = 25.0
+    for mode in ("enum_soft", "enum_hard"):
+        p, f, rho, mu, q_in, out = _enum_case(4, 2, 12, b, beta, mode, rng)
+        for y in range(2):
+            for x in range(12):
+                g = _gathered(f, b, y, x, float(out["d_idx"][y, x]))
+                marg, tot, best, best_S = np.zeros(4), 0.0, -1.0, None
+                for S in itertools.product([0, 1], repeat=4):
+                    Sa = np.array(S, bool)
+                    var = float(np.var(g[Sa], axis=0).sum()) if Sa.sum() >= 2 else 0.0
+                    w = math.exp(-beta * var) * float(np.prod(np.where(Sa, rho[:, y, x], 1 - rho[:, y, x])))
+                    tot += w
+                    marg += w * Sa
+                    if w > best:
+                        best, best_S = w, Sa
+                if mode == "enum_soft":
+                    np.testing.assert_allclose(out["q"][:, y, x], marg / tot, rtol=1e-11, atol=1e-14)
+                else:
+                    assert np.array_equal(out["q"][:, y, x], best_S.astype(float))
+
+
+def test_enum_beta_zero_and_certain_priors():
+    rng = np.random.default_rng(43)
+    b = [-1.0, 0.0, 1.0]
+    # beta = 0: the labels are independent, the marginal is the prior
+    _, _, rho, _, _, out = _enum_case(3, 2, 10, b, 0.0, "enum_soft", rng)
+    np.testing.assert_allclose(out["q"], rho, rtol=1e-12)
+    _, _, rho, _, _, out = _enum_case(3, 2, 10, b, 0.0, "enum_hard", rng)
+    assert np.array_equal(out["q"], (rho >= 0.5).astype(float))
+    # every labeling ties at rho = 1/2: the tie goes to the largest mask (all static)
+    _, _, _, _, _, out = _enum_case(3, 2, 10, b, 0.0, "enum_hard", rng, rho_lo=0.5, rho_hi=0.5)
+    assert np.all(out["q"] == 1.0)
+    # certain priors stay certain whatever the descriptors say
+    for mode in ("enum_soft", "enum_hard"):
+        p, f, _, mu, q_in, _ = _enum_case(3, 2, 10, b, 300.0, mode, rng)
+        rho = rng.integers(0, 2, (3, 2, 10)).astype(np.float64)
+        out = O.em_iteration(p, f, rho, mu, q_in)
+        assert np.array_equal(out["q"], rho)
+
+
+def test_enum_identical_views_weigh_by_prior_only():
+    """Every view shows the same colours: every variance is zero, so the
+    enumeration returns the prior whatever beta is."""
+    rng = np.random.default_rng(44)
+    one = _random_views(1, 3, 16, rng)
+    views = np.repeat(one, 4, axis=0)
+    _, _, rho, _, _, out = _enum_case(4, 3, 16, [0.0, 0.0, 0.0, 0.0], 500.0, "enum_soft", rng, views=views)
+    np.testing.assert_allclose(out["q"], rho, rtol=1e-12)
+
+
+def test_enum_mstep_is_the_weighted_sweep():
+    """The enumeration modes change the E-step only: the M-step level is the
+    one of the factorised modes for the same weights."""
+    rng = np.random.default_rng(45)
+    K, H, W = 4, 3, 20
+    views = _random_views(K, H, W, rng)
+    b = [-1.0, 0.0, 1.0, 2.0]
+    mu = rng.uniform(0, 4, (H, W)).astype(np.float32)
+    rho = rng.uniform(0.05, 0.95, (K, H, W))
+    q_in = rng.uniform(0, 1, (K, H, W))
+    d = {}
+    for mode in ("soft", "enum_soft", "enum_hard"):
+        p = _params(K, H, W, b, 6, 80.0, mode=mode)
+        d[mode] = O.em_iteration(p, O.descriptors(p, views), rho, mu, q_in)["d_idx"]
+    assert np.array_equal(d["soft"], d["enum_soft"]) and np.array_equal(d["soft"], d["enum_hard"])
+
+
 # ---------------------------------------------------------------- EM loop
 
 @pytest.mark.parametrize("mode", ["soft", "hard"])
