@@ -54,10 +54,21 @@ typedef int32_t lf_status;
 #define LF_F16   1
 #define LF_BF16  2
 
-/* E-step form: SOFT = posterior P(S_k = 1); HARD = the arg max labeling
- * (the paper's delta / hard assignment, Sec. III-C and III-D). */
-#define LF_SOFT  0
-#define LF_HARD  1
+/* E-step form.  SOFT: posterior P(S_k = 1) of each ray under the per-view
+ * factorised likelihood (static exp(lambda - beta/K |f_k - m|^2), dynamic 1);
+ * HARD: its arg max per view, the paper's delta / hard assignment (Sec. III-C
+ * and III-D).  ENUM_SOFT / ENUM_HARD: the E-step as the paper states it, over
+ * all 2^K labelings S (Sec. III-C, last sentence; Sec. III-D): the log weight
+ * of S is sum_k ln P(S_k | rho_k) - beta Var_S, Var_S the variance of the
+ * static descriptors normalised by their count (0 for fewer than two static
+ * views, no lambda); ENUM_SOFT returns the marginals P(S_k = 1), ENUM_HARD
+ * the labeling of largest weight (ties: the largest mask, bit k = view k).
+ * The enumeration modes need K <= 12.  The M-step is the same in every mode. */
+#define LF_SOFT       0
+#define LF_HARD       1
+#define LF_ENUM_SOFT  2
+#define LF_ENUM_HARD  3
+#define LF_ENUM_MAX_VIEWS 12
 
 /* flags */
 #define LF_INPUTS_ON_DEVICE   0x1u  /* views, S_P, mu_T, q_warm are device pointers   */
@@ -78,7 +89,7 @@ typedef struct {
     float gamma, sigma;         /* disparity prior ln(gamma + exp(-(d-mu)^2/(2 sigma^2))) */
     float tau_init;             /* first-iteration threshold: static iff rho >= tau (0.7) */
     int32_t storage;            /* LF_F32, LF_F16, LF_BF16                            */
-    int32_t mode;               /* LF_SOFT, LF_HARD                                   */
+    int32_t mode;               /* LF_SOFT, LF_HARD, LF_ENUM_SOFT, LF_ENUM_HARD        */
     uint32_t flags;             /* LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE |       */
                                 /* LF_EXHAUSTIVE_SWEEP                                */
 } lf_params;
@@ -102,7 +113,7 @@ typedef struct lf_ctx lf_ctx;   /* opaque; owns all device buffers of one frame 
  * Errors: LF_EINVAL (checked before any device work: K outside [2,16], H or W
  * < 1, ref out of range, baselines[ref] != 0, non-finite baselines, D < 1,
  * d_step <= 0, beta < 0, lambda NaN with beta == 0, gamma <= 0, sigma <= 0,
- * tau_init outside [0,1], bad storage/mode/flags, max |baseline * level|
+ * tau_init outside [0,1], bad storage/mode/flags, K > 12 in an enumeration mode, max |baseline * level|
  * above 1e6, S_P outside [0,1] or NaN, mu_T not finite or |mu_T| above 1e6,
  * q_warm outside [0,1]; a disparity halo too wide for one workgroup's LDS);
  * LF_ENOMEM; LF_EDEVICE.  Value checks of device-resident inputs run on the
@@ -126,7 +137,10 @@ lf_status lf_em_load(lf_ctx *c, const uint8_t *views, const float *S_P, const fl
  *   objective : NULL, or host double [n_iters] receiving the frame objective
  *               sum_p L_t(p) after each iteration, L_t(p) = ln(gamma +
  *               exp(-(d_t-mu)^2/(2 sigma^2))) + sum_k logaddexp(a1_k, a0_k)
- *               (SOFT) or sum_k max(a1_k, a0_k) (HARD); summed in FP64.
+ *               (SOFT) or sum_k max(a1_k, a0_k) (HARD); in the enumeration
+ *               modes the log prior plus the log of the summed labeling
+ *               weights (ENUM_SOFT) or of the largest one (ENUM_HARD), which
+ *               EM does not guarantee to be monotone; summed in FP64.
  *               With NULL the call only queues work and returns, and only the
  *               last iteration's objective is formed (for lf_em_state).
  * iterate(a) followed by iterate(b) gives bit-identical state to iterate(a+b).

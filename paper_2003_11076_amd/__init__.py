@@ -21,7 +21,9 @@ LF_OK, LF_EINVAL, LF_ENOMEM, LF_EDEVICE, LF_EAGAIN, LF_ESTATE = 0, 1, 2, 3, 4, 5
 STATUS_NAMES = {0: "LF_OK", 1: "LF_EINVAL", 2: "LF_ENOMEM", 3: "LF_EDEVICE", 4: "LF_EAGAIN", 5: "LF_ESTATE"}
 LF_MAX_VIEWS = 16
 LF_F32, LF_F16, LF_BF16 = 0, 1, 2
-LF_SOFT, LF_HARD = 0, 1
+LF_SOFT, LF_HARD, LF_ENUM_SOFT, LF_ENUM_HARD = 0, 1, 2, 3
+LF_ENUM_MAX_VIEWS = 12
+MODES = {"soft": LF_SOFT, "hard": LF_HARD, "enum_soft": LF_ENUM_SOFT, "enum_hard": LF_ENUM_HARD}
 LF_INPUTS_ON_DEVICE, LF_OUTPUTS_ON_DEVICE, LF_EXHAUSTIVE_SWEEP = 0x1, 0x2, 0x4
 STORAGE = {"f32": LF_F32, "f16": LF_F16, "bf16": LF_BF16}
 
@@ -52,7 +54,7 @@ def make_params(K, H, W, ref, baselines, d_min, d_step, D, beta, lam=float("nan"
     p.d_min, p.d_step, p.D = float(d_min), float(d_step), int(D)
     p.beta, p.lambda_, p.gamma, p.sigma, p.tau_init = float(beta), float(lam), float(gamma), float(sigma), float(tau_init)
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
-    p.mode = {"soft": LF_SOFT, "hard": LF_HARD}[mode] if isinstance(mode, str) else int(mode)
+    p.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     p.flags = int(flags)
     return p
 

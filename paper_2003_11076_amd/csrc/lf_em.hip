@@ -68,7 +68,9 @@ lf_status validate_params(const lf_params *p) {
     if (!(p->sigma > 0.0f) || !std::isfinite(p->sigma)) return set_error(LF_EINVAL, "sigma must be > 0");
     if (!(p->tau_init >= 0.0f && p->tau_init <= 1.0f)) return set_error(LF_EINVAL, "tau_init outside [0,1]");
     if (p->storage < LF_F32 || p->storage > LF_BF16) return set_error(LF_EINVAL, "storage=%d unknown", p->storage);
-    if (p->mode != LF_SOFT && p->mode != LF_HARD) return set_error(LF_EINVAL, "mode=%d unknown", p->mode);
+    if (p->mode < LF_SOFT || p->mode > LF_ENUM_HARD) return set_error(LF_EINVAL, "mode=%d unknown", p->mode);
+    if (p->mode >= LF_ENUM_SOFT && p->K > LF_ENUM_MAX_VIEWS)
+        return set_error(LF_EINVAL, "K=%d above %d in an enumeration mode", p->K, LF_ENUM_MAX_VIEWS);
     if (p->flags & ~(LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE | LF_EXHAUSTIVE_SWEEP))
         return set_error(LF_EINVAL, "unknown flags");
     return LF_OK;
@@ -225,6 +227,7 @@ EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
     a.d_min = p->d_min;
     a.d_step = p->d_step;
     a.beta_p = (float)((double)p->beta / p->K);
+    a.beta = p->beta;
     a.lambda = lambda;
     a.gamma = p->gamma;
     const double s2 = 2.0 * (double)p->sigma * p->sigma;

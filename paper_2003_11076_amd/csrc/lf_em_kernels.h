@@ -167,6 +167,7 @@ struct EmArgs {
     int dmin_i, dstep_i;  // integer levels (integer-shift path)
     float d_min, d_step;
     float beta_p;         // beta / K
+    float beta;           // beta (enumeration modes: weight of the coupled variance)
     float lambda, gamma;
     float c_exp2;         // log2(e) / (2 sigma^2)
     float c_exp;          // 1 / (2 sigma^2)
@@ -369,9 +370,83 @@ __device__ __forceinline__ int nearest_level(const EmArgs &a, float mu) {
     return (int)fminf(fmaxf(jf, 0.0f), (float)(a.D - 1));
 }
 
+constexpr float kLog2e = 1.44269504088896341f;
+
+// E-step by enumeration of all 2^K labelings S of the pixel's rays (the
+// enumeration modes, Sec. III-C last sentence and Sec. III-D): the log weight
+// of S is sum_k ln P(S_k | rho_k) - beta Var_S, with Var_S the variance of
+// the static descriptors normalised by their number (0 for fewer than two).
+// f are the descriptors at the chosen level (kernel view order), (mx, my) the
+// M-step mean: the descriptors enter centred on it (the variance does not
+// change) so that the one-pass variance keeps its accuracy.  ENUM_SOFT sets
+// q to the marginals P(S_k = 1), accumulated with weights scaled by the
+// largest log weight so far; ENUM_HARD sets q to the labeling of largest
+// weight, ties to the largest mask in array view order.  Returns the log of
+// the summed weights (soft) or of the largest weight (hard).
+template <int K>
+__device__ __forceinline__ float enum_estep(const float2 (&f)[K], float mx, float my, const EmArgs &a, Lane<K> &s) {
+    float gx[K], gy[K], gn[K], l1[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        gx[k] = f[k].x - mx;
+        gy[k] = f[k].y - my;
+        gn[k] = fmaf(gx[k], gx[k], gy[k] * gy[k]);
+        l1[k] = s.la[k] - a.lambda;   // ln rho_k
+    }
+    const bool hard = a.mode == 3;
+    float top = -INFINITY, Z = 0.0f, acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0f;
+    int best_amask = 0, best_mask = 0;
+    for (int mask = 0; mask < (1 << K); ++mask) {
+        float ax = 0.0f, ay = 0.0f, s2 = 0.0f, lw = 0.0f;
+        int n = 0, amask = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const bool on = (mask >> k) & 1;
+            ax += on ? gx[k] : 0.0f;
+            ay += on ? gy[k] : 0.0f;
+            s2 += on ? gn[k] : 0.0f;
+            lw += on ? l1[k] : s.lb[k];
+            n += on ? 1 : 0;
+            amask |= on ? (1 << a.perm[k]) : 0;
+        }
+        if (n >= 2) {
+            const float inv = 1.0f / (float)n;
+            const float var = fmaxf(fmaf(-(ax * ax + ay * ay), inv, s2) * inv, 0.0f);
+            lw = fmaf(-a.beta, var, lw);
+        }
+        if (hard) {
+            if (lw > top || (lw == top && amask > best_amask)) {
+                top = lw;
+                best_amask = amask;
+                best_mask = mask;
+            }
+        } else {
+            const float mn = fmaxf(top, lw);
+            if (mn > -INFINITY) {
+                const float r = __builtin_amdgcn_exp2f((top - mn) * kLog2e);
+                const float w = __builtin_amdgcn_exp2f((lw - mn) * kLog2e);
+                Z = fmaf(Z, r, w);
+#pragma unroll
+                for (int k = 0; k < K; ++k) acc[k] = fmaf(acc[k], r, ((mask >> k) & 1) ? w : 0.0f);
+                top = mn;
+            }
+        }
+    }
+    if (hard) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) s.q[k] = ((best_mask >> k) & 1) ? 1.0f : 0.0f;
+        return top;
+    }
+    // a true division: a view static in every weighted labeling gets exactly 1
+#pragma unroll
+    for (int k = 0; k < K; ++k) s.q[k] = acc[k] / Z;
+    return top + kLn2 * __builtin_amdgcn_logf(Z);
+}
+
 // One EM iteration of one active lane: M-step sweep over all levels with the
 // current weights, then the E-step and the objective at the chosen level.
-constexpr float kLog2e = 1.44269504088896341f;
 
 template <int K, int ST, bool FRAC, bool EXH, bool SYM>
 __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, const Window (&w)[K], const EmArgs &a,
@@ -491,10 +566,14 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
 #pragma unroll
     for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, best_j, s.idx0[k], f[k], nn);
     (void)exact_energy<K>(f, wt, invW, cw, 0.0f, mx, my);
-    // posterior in the logit domain with the hardware base-2 exponential and
-    // reciprocal (about 1e-7 absolute error; q = 0 or 1 exactly at +-inf)
     float L = 0.0f;
     if (with_obj) L = log_prior(a, best_j, mu);
+    if (a.mode >= 2) {
+        s.L = L + enum_estep<K>(f, mx, my, a, s);
+        return;
+    }
+    // posterior in the logit domain with the hardware base-2 exponential and
+    // reciprocal (about 1e-7 absolute error; q = 0 or 1 exactly at +-inf)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const float dx = f[k].x - mx, dy = f[k].y - my;

@@ -65,7 +65,10 @@ def _params(**over):
     (dict(sigma=0.0), "sigma"),
     (dict(tau_init=1.5), "tau_init"),
     (dict(storage=3), "storage"),
-    (dict(mode=2), "mode"),
+    (dict(mode=4), "mode"),
+    (dict(mode=-1), "mode"),
+    (dict(K=13, ref=6, baselines=list(range(-6, 7)), mode=2), "enumeration"),
+    (dict(K=13, ref=6, baselines=list(range(-6, 7)), mode=3), "enumeration"),
     (dict(flags=0x10), "flags"),
     (dict(H=0), "H="),
     (dict(baselines=[-1, 0, float("inf")]), "baselines[2]"),
