@@ -40,11 +40,12 @@ class Params(ctypes.Structure):
         ("beta", ctypes.c_double), ("lam", ctypes.c_double), ("gamma", ctypes.c_double),
         ("sigma", ctypes.c_double), ("tau", ctypes.c_double),
         ("storage", ctypes.c_int32), ("mode", ctypes.c_int32),
+        ("window", ctypes.c_double), ("dyn_only", ctypes.c_int32),
     ]
 
 
 def make_params(K, H, W, ref, baselines, d_min, d_step, D, beta, lam=float("nan"), gamma=0.05,
-                sigma=2.0, tau=0.7, storage="f32", mode="soft") -> Params:
+                sigma=2.0, tau=0.7, storage="f32", mode="soft", window=0.0, dyn_only=False) -> Params:
     p = Params()
     p.K, p.H, p.W, p.ref = K, H, W, ref
     for k, b in enumerate(baselines):
@@ -53,6 +54,7 @@ def make_params(K, H, W, ref, baselines, d_min, d_step, D, beta, lam=float("nan"
     p.beta, p.lam, p.gamma, p.sigma, p.tau = float(beta), float(lam), float(gamma), float(sigma), float(tau)
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     p.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    p.window, p.dyn_only = float(window), int(bool(dyn_only))
     return p
 
 
@@ -86,7 +88,7 @@ def lib():
         L.lfo_descriptors.argtypes = [P, u8, dp, i32, i32]
         L.lfo_ray_prior.argtypes = [P, fp, fp, dp, dp, dp, i32, i32]
         L.lfo_em_iteration.argtypes = [P, ctypes.c_double, dp, dp, dp, fp, dp, dp, i32p, dp, dp, dp, i32, i32]
-        L.lfo_refocus.argtypes = [P, u8, i32p, dp, dp, u8, i32, i32]
+        L.lfo_refocus.argtypes = [P, u8, i32p, dp, dp, dp, u8, i32, i32]
         L.lfo_reconstruct.argtypes = [P, u8, fp, fp, dp, i32, i32, i32, dp, dp, dp, dp, dp, i32p, dp, dp, dp, u8]
         L.lfo_reconstruct.restype = i32
         L.lfo_threads.restype = i32
@@ -169,14 +171,17 @@ def em_iteration(p: Params, f, rho, mu_T, q_in, lam=None, rows=None, omr=None) -
     return out
 
 
-def refocus(p: Params, views, d_idx, q, rows=None):
-    """(rgb [H][W][3] in [0,1], hole [H][W] uint8)."""
+def refocus(p: Params, views, d_idx, q, rows=None, rho=None):
+    """(rgb [H][W][3] in [0,1], hole [H][W] uint8).  rho (the ray prior) is
+    needed only with dyn_only, to find the pixels with a static reference ray."""
     v, d, q = _c(views, np.uint8), _c(d_idx, np.int32), _c(q, np.float64)
+    rho = None if rho is None else _c(rho, np.float64)
     rgb = np.zeros((p.H, p.W, 3))
     hole = np.zeros((p.H, p.W), np.uint8)
     y0, y1 = _rows(p, rows)
     lib().lfo_refocus(ctypes.byref(p), _ptr(v, ctypes.c_uint8), _ptr(d, ctypes.c_int32),
-                      _ptr(q, ctypes.c_double), _ptr(rgb, ctypes.c_double), _ptr(hole, ctypes.c_uint8), y0, y1)
+                      _ptr(q, ctypes.c_double), _ptr(rho, ctypes.c_double), _ptr(rgb, ctypes.c_double),
+                      _ptr(hole, ctypes.c_uint8), y0, y1)
     return rgb, hole
 
 

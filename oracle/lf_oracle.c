@@ -43,6 +43,14 @@
  *     static views.  Mode 2 returns the marginals P(S_k = 1), mode 3 the
  *     labeling of largest weight (ties: the largest mask, bit k = view k).
  *     The M-step is unchanged (weights q, beta' = beta / K).
+ *   - work-avoiding variants (Sec. III-C, the prior "reduces the search
+ *     space"; Sec. III-F / IV, refocusing only the dynamic pixels): with
+ *     window > 0 the M-step takes the arg min over the levels within
+ *     `window` of mu_T only (the level nearest mu_T when there is none);
+ *     with dyn_only a pixel whose reference ray is static by the prior
+ *     threshold (rho_ref >= tau) is not reconstructed: it keeps its weights,
+ *     takes the level nearest mu_T, adds nothing to the objective and shows
+ *     its reference colour (not a hole).
  */
 #include <math.h>
 #include <stdint.h>
@@ -63,6 +71,9 @@ typedef struct {
     int32_t storage; /* 0: inputs used as given, 1: rounded to binary16, 2: rounded to bfloat16 */
     int32_t mode;    /* 0: soft posterior, 1: hard assignment, 2 / 3: enumeration over all
                         labelings with the paper's coupled variance, marginals / arg max */
+    double window;   /* > 0: the M-step searches only the levels with |d - mu_T| <= window */
+    int32_t dyn_only; /* 1: EM and refocus only where the reference ray is dynamic by the
+                         prior threshold (rho_ref < tau); elsewhere the reference pixel */
 } lfo_params;
 
 /* ------------------------------------------------------------------------ */
@@ -203,6 +214,15 @@ static double log_prior(const lfo_params *p, double d, double mu)
     return log(p->gamma + exp(-(z * z) / (2.0 * p->sigma * p->sigma)));
 }
 
+/* Level index nearest mu (clamped to the level range). */
+static int nearest_level(const lfo_params *p, double mu)
+{
+    double j = nearbyint((mu - p->d_min) / p->d_step);
+    if (j < 0.0) j = 0.0;
+    if (j > p->D - 1) j = p->D - 1;
+    return (int)j;
+}
+
 static double logaddexp(double a, double b)
 {
     if (a == -INFINITY) return b;
@@ -320,15 +340,33 @@ void lfo_em_iteration(const lfo_params *p, double lambda, const double *f, const
             const double mu = (double)mu_T[pix];
             for (int k = 0; k < K; ++k) q[k] = q_in[(size_t)k * H * W + pix];
 
-            /* M-step: exhaustive search over the disparity levels. */
-            int best = 0;
+            if (p->dyn_only && !(rho[(size_t)p->ref * H * W + pix] < p->tau)) {
+                /* static reference ray: not reconstructed */
+                for (int k = 0; k < K; ++k) q_out[(size_t)k * H * W + pix] = q[k];
+                d_idx[pix] = nearest_level(p, mu);
+                if (L_pix) L_pix[pix] = 0.0;
+                if (E1) E1[pix] = -INFINITY;
+                if (E2) E2[pix] = INFINITY;
+                continue;
+            }
+
+            /* M-step: exhaustive search over the disparity levels (those
+             * within the window around mu_T when it is set). */
+            int best = 0, searched = 0;
             double e_best = INFINITY, e_second = INFINITY;
-            for (int j = 0; j < D; ++j) {
-                double d = p->d_min + j * p->d_step;
+            for (int j = 0; j <= D; ++j) {
+                int jj = j;
+                if (j == D) {            /* empty window: the level nearest mu_T */
+                    if (searched) break;
+                    jj = nearest_level(p, mu);
+                }
+                double d = p->d_min + jj * p->d_step;
+                if (j < D && p->window > 0.0 && !(fabs(d - mu) <= p->window)) continue;
+                ++searched;
                 gather(p, f, x, y, d, fk);
                 double C = weighted_spread(K, fk, q, m);
                 double E = bp * C + c0 - log_prior(p, d, mu);
-                if (E < e_best) { e_second = e_best; e_best = E; best = j; }
+                if (E < e_best) { e_second = e_best; e_best = E; best = jj; }
                 else if (E < e_second) e_second = E;
             }
 
@@ -378,13 +416,20 @@ void lfo_em_iteration(const lfo_params *p, double lambda, const double *f, const
 /* ------------------------------------------------------------------------ */
 
 void lfo_refocus(const lfo_params *p, const uint8_t *views, const int32_t *d_idx, const double *q,
-                 double *rgb, uint8_t *hole, int32_t y0, int32_t y1)
+                 const double *rho, double *rgb, uint8_t *hole, int32_t y0, int32_t y1)
 {
     const int K = p->K, H = p->H, W = p->W;
 #pragma omp parallel for schedule(static)
     for (int y = y0; y < y1; ++y) {
         for (int x = 0; x < W; ++x) {
             const size_t pix = (size_t)y * W + x;
+            if (p->dyn_only && rho && !(rho[(size_t)p->ref * H * W + pix] < p->tau)) {
+                /* static reference ray: the reference pixel is the background */
+                const uint8_t *c_ref = views + (((size_t)p->ref * H + y) * W + x) * 3;
+                for (int c = 0; c < 3; ++c) rgb[pix * 3 + c] = (double)c_ref[c] / 255.0;
+                if (hole) hole[pix] = 0;
+                continue;
+            }
             double d = p->d_min + d_idx[pix] * p->d_step;
             double acc[3] = {0.0, 0.0, 0.0};
             int n = 0;
@@ -443,7 +488,7 @@ int32_t lfo_reconstruct(const lfo_params *p, const uint8_t *views, const float *
         }
         double *tmp = q_a; q_a = q_b; q_b = tmp;
     }
-    lfo_refocus(p, views, d_idx, q_a, rgb, hole, y0, y1);
+    lfo_refocus(p, views, d_idx, q_a, rho, rgb, hole, y0, y1);
     /* leave the final weights in the caller's first buffer */
     if (n_iters % 2 == 1)
         for (int k = 0; k < K; ++k)

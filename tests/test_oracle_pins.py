@@ -417,6 +417,102 @@ def test_enum_mstep_is_the_weighted_sweep():
     assert np.array_equal(d["soft"], d["enum_soft"]) and np.array_equal(d["soft"], d["enum_hard"])
 
 
+# ---------------------------------------------------------------- work-avoiding variants
+
+@pytest.mark.parametrize("window", [1.5, 3.0, 6.0])
+def test_window_sweep_is_arg_min_over_levels_near_prior(window):
+    """The windowed M-step is the arg min of the all-static energies
+    (beta numpy.var form) over the levels with |d - mu| <= window, and the
+    level nearest mu when no level is that close."""
+    K, H, W, D = 4, 4, 24, 12
+    b = [0.0, 1.0, 2.0, -1.0]
+    views = _random_views(K, H, W)
+    mu = RNG.uniform(-1, 7, (H, W)).astype(np.float32)
+    mu[0, :4] = [-9.0, 30.0, 5.001, 5.0]      # two empty windows; levels exactly at the window edge
+    d_min, d_step = -1.0, 0.75
+    p = _params(K, H, W, b, D, 300.0, ref=0, d_min=d_min, d_step=d_step, window=window)
+    f = O.descriptors(p, views)
+    out = O.em_iteration(p, f, np.ones((K, H, W)), mu, np.ones((K, H, W)))
+    levels = d_min + d_step * np.arange(D)
+    for y in range(H):
+        for x in range(W):
+            m = float(mu[y, x])
+            inside = np.abs(levels - m) <= window
+            E = _energies_from_variance(f, b, y, x, levels, 300.0, 0.05, 2.0, m)
+            if inside.any():
+                want = int(np.flatnonzero(inside)[np.argmin(E[inside])])
+            else:
+                want = int(np.argmin(np.abs(levels - m)))
+            assert out["d_idx"][y, x] == want, (y, x)
+
+
+def test_window_edge_levels_are_searched():
+    """A level exactly `window` away from mu is inside the window: with mu
+    half-way between two levels and window half a step, both are searched."""
+    K, H, W, D = 4, 2, 30, 12
+    b = [0.0, 1.0, 2.0, -1.0]
+    views = _random_views(K, H, W)
+    mu = np.full((H, W), 5.375, np.float32)          # between levels 8 (5.0) and 9 (5.75)
+    p = _params(K, H, W, b, D, 300.0, ref=0, d_min=-1.0, d_step=0.75, window=0.375)
+    f = O.descriptors(p, views)
+    out = O.em_iteration(p, f, np.ones((K, H, W)), mu, np.ones((K, H, W)))
+    levels = -1.0 + 0.75 * np.arange(D)
+    for y in range(H):
+        for x in range(W):
+            E = _energies_from_variance(f, b, y, x, levels[8:10], 300.0, 0.05, 2.0, 5.375)
+            assert out["d_idx"][y, x] == 8 + int(np.argmin(E))
+    assert (out["d_idx"] == 9).any()
+
+
+def test_window_covering_every_level_is_the_full_sweep():
+    K, H, W, D = 3, 3, 20, 10
+    views = _random_views(K, H, W)
+    mu = RNG.uniform(0, 9, (H, W)).astype(np.float32)
+    q = RNG.uniform(0, 1, (K, H, W))
+    rho = RNG.uniform(0.1, 0.9, (K, H, W))
+    outs = []
+    for window in (0.0, 100.0):
+        p = _params(K, H, W, [-1, 0, 1], D, 500.0, ref=1, window=window)
+        outs.append(O.em_iteration(p, O.descriptors(p, views), rho, mu, q))
+    for key in ("q", "d_idx", "L"):
+        assert np.array_equal(outs[0][key], outs[1][key])
+
+
+def test_dynamic_only_reconstructs_exactly_the_dynamic_reference_pixels():
+    """dyn_only: pixels whose reference ray is dynamic by the prior threshold
+    get the results of the full method; the others keep their weights, the
+    level nearest mu, no objective, and their reference colour."""
+    rng = np.random.default_rng(46)
+    K, H, W, D = 5, 6, 40, 12
+    b = [-2.0, -1.0, 0.0, 1.0, 2.0]
+    views = rng.integers(0, 256, size=(K, H, W, 3), dtype=np.uint8)
+    S_P = rng.uniform(0, 1, (K, H, W)).astype(np.float32)
+    tau = float(np.float32(0.7))
+    S_P[2, 0, :5] = tau                      # exactly tau: static
+    mu = rng.uniform(0, 11, (H, W)).astype(np.float32)
+    res = {}
+    for dyn in (False, True):
+        p = _params(K, H, W, b, D, 400.0, ref=2, dyn_only=dyn, tau=tau)
+        res[dyn] = O.reconstruct(p, views, S_P, mu, 3)
+    rho_ref = res[True]["rho"][2]
+    dyn = rho_ref < tau
+    assert dyn.any() and (~dyn).any() and not dyn[0, :5].any()
+    full, part = res[False], res[True]
+    assert np.array_equal(part["d_idx"][dyn], full["d_idx"][dyn])
+    assert np.array_equal(part["q"][:, dyn], full["q"][:, dyn])
+    assert np.array_equal(part["rgb"][dyn], full["rgb"][dyn])
+    assert np.array_equal(part["hole"][dyn], full["hole"][dyn])
+    levels = np.arange(D, dtype=np.float64)
+    nearest = np.argmin(np.abs(levels[None, None, :] - mu[..., None].astype(np.float64)), axis=-1)
+    assert np.array_equal(part["d_idx"][~dyn], nearest[~dyn])
+    p = _params(K, H, W, b, D, 400.0, ref=2, tau=tau)
+    _, q0 = O.ray_prior(p, S_P, mu)
+    assert np.array_equal(part["q"][:, ~dyn], q0[:, ~dyn])
+    assert np.all(part["L"][~dyn] == 0.0)
+    assert np.array_equal(part["rgb"][~dyn], views[2][~dyn] / 255.0)
+    assert not part["hole"][~dyn].any()
+
+
 # ---------------------------------------------------------------- EM loop
 
 @pytest.mark.parametrize("mode", ["soft", "hard"])
