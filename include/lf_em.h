@@ -75,6 +75,17 @@ typedef int32_t lf_status;
 #define LF_OUTPUTS_ON_DEVICE  0x2u  /* rgb, d_idx, q, hole, L_pix are device pointers  */
 #define LF_EXHAUSTIVE_SWEEP   0x4u  /* evaluate every level with the two-pass spread:   */
                                     /* same results, slower; for verification          */
+/* Work-avoiding variants (the paper's speed levers):
+ * LF_PRIOR_WINDOW: the M-step searches only the levels within 3 sigma of
+ *   mu_T (the level nearest mu_T when none is), the prior "reducing the
+ *   search space" (Sec. III-C, disparity prior).
+ * LF_DYNAMIC_ONLY: only pixels whose reference ray is dynamic by the prior
+ *   threshold (rho_ref < tau_init) are reconstructed, as the paper refocuses
+ *   only the dynamic pixels (Sec. III-F, IV-B).  Every other pixel keeps its
+ *   first weights, takes the level nearest mu_T, adds nothing to the
+ *   objective, and its refocused colour is its reference colour (hole = 0). */
+#define LF_PRIOR_WINDOW       0x8u
+#define LF_DYNAMIC_ONLY       0x10u
 
 typedef struct {
     int32_t K, H, W;            /* views, rows, columns; 2 <= K <= 16                 */
@@ -91,7 +102,8 @@ typedef struct {
     int32_t storage;            /* LF_F32, LF_F16, LF_BF16                            */
     int32_t mode;               /* LF_SOFT, LF_HARD, LF_ENUM_SOFT, LF_ENUM_HARD        */
     uint32_t flags;             /* LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE |       */
-                                /* LF_EXHAUSTIVE_SWEEP                                */
+                                /* LF_EXHAUSTIVE_SWEEP | LF_PRIOR_WINDOW |            */
+                                /* LF_DYNAMIC_ONLY                                    */
 } lf_params;
 
 typedef struct lf_ctx lf_ctx;   /* opaque; owns all device buffers of one frame shape */
@@ -246,8 +258,9 @@ lf_status lf_server_create(lf_server **out, size_t hbm_budget_bytes, int32_t max
  * output buffers must stay valid until `done` has run for the frame (or
  * lf_server_drain / lf_server_destroy has returned): the server writes them
  * from its service thread.
- * Errors: LF_EINVAL (as lf_em_init, plus K > 9, stream_id out of range, any
- * flag set, a frame larger than the arenas), LF_EAGAIN (staging full), or
+ * Errors: LF_EINVAL (as lf_em_init, plus K > 9, stream_id out of range, a
+ * flag other than LF_PRIOR_WINDOW and LF_DYNAMIC_ONLY set, a frame larger
+ * than the arenas), LF_EAGAIN (staging full), or
  * the error a previous device failure left.
  */
 lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, const uint8_t *views,

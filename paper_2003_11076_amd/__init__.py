@@ -25,6 +25,7 @@ LF_SOFT, LF_HARD, LF_ENUM_SOFT, LF_ENUM_HARD = 0, 1, 2, 3
 LF_ENUM_MAX_VIEWS = 12
 MODES = {"soft": LF_SOFT, "hard": LF_HARD, "enum_soft": LF_ENUM_SOFT, "enum_hard": LF_ENUM_HARD}
 LF_INPUTS_ON_DEVICE, LF_OUTPUTS_ON_DEVICE, LF_EXHAUSTIVE_SWEEP = 0x1, 0x2, 0x4
+LF_PRIOR_WINDOW, LF_DYNAMIC_ONLY = 0x8, 0x10
 STORAGE = {"f32": LF_F32, "f16": LF_F16, "bf16": LF_BF16}
 
 

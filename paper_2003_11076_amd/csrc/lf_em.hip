@@ -71,7 +71,8 @@ lf_status validate_params(const lf_params *p) {
     if (p->mode < LF_SOFT || p->mode > LF_ENUM_HARD) return set_error(LF_EINVAL, "mode=%d unknown", p->mode);
     if (p->mode >= LF_ENUM_SOFT && p->K > LF_ENUM_MAX_VIEWS)
         return set_error(LF_EINVAL, "K=%d above %d in an enumeration mode", p->K, LF_ENUM_MAX_VIEWS);
-    if (p->flags & ~(LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE | LF_EXHAUSTIVE_SWEEP))
+    if (p->flags & ~(LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE | LF_EXHAUSTIVE_SWEEP | LF_PRIOR_WINDOW |
+                     LF_DYNAMIC_ONLY))
         return set_error(LF_EINVAL, "unknown flags");
     return LF_OK;
 }
@@ -233,6 +234,9 @@ EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
     const double s2 = 2.0 * (double)p->sigma * p->sigma;
     a.c_exp2 = (float)(1.4426950408889634 / s2);
     a.c_exp = (float)(1.0 / s2);
+    a.win_half = (p->flags & LF_PRIOR_WINDOW) ? 3.0f * p->sigma : 0.0f;
+    a.dyn_only = (p->flags & LF_DYNAMIC_ONLY) ? 1 : 0;
+    a.tau = p->tau_init;
     return a;
 }
 
@@ -545,6 +549,8 @@ lf_status lf_refocus(lf_ctx *c, float *rgb, int32_t *d_idx, float *q, uint8_t *h
     r.views = c->views;
     r.d_idx = c->d_idx;
     r.q = c->q;
+    r.rho_ref = (p.flags & LF_DYNAMIC_ONLY) ? c->rho + (size_t)p.ref * HW : nullptr;
+    r.tau = p.tau_init;
     float *rgb_k = median ? c->rgb_med : (dev_out ? rgb : c->rgb);
     r.rgb = rgb_k;
     r.hole = dev_out ? hole : c->hole;

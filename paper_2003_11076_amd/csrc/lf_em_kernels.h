@@ -174,6 +174,9 @@ struct EmArgs {
     float prior_T;        // |d - mu| beyond which gamma + g == gamma in FP32
     float margin_k;       // one-pass error bound, in units of beta' * S
     float margin_c;       // absolute slack of the bound
+    float win_half;       // > 0: the M-step searches only |d - mu| <= win_half
+    int dyn_only;         // 1: only pixels with rho_ref < tau are reconstructed
+    float tau;            // first-iteration threshold (dynamic-only test)
     int perm[kMaxViews];  // kernel view order -> array view index (perm[0] = reference)
     int bi[kMaxViews];    // integer baselines, kernel order (integer-shift path)
     float b[kMaxViews];   // baselines, kernel order
@@ -445,12 +448,37 @@ __device__ __forceinline__ float enum_estep(const float2 (&f)[K], float mx, floa
     return top + kLn2 * __builtin_amdgcn_logf(Z);
 }
 
+// Levels a lane's M-step searches: all of them, or those within win_half of
+// the prior disparity (the level nearest it when none is).
+__device__ __forceinline__ void search_window(const EmArgs &a, float mu, int &wlo, int &whi) {
+    wlo = 0;
+    whi = a.D - 1;
+    if (a.win_half > 0.0f) {
+        const float lo = ceilf((mu - a.win_half - a.d_min) / a.d_step);
+        const float hi = floorf((mu + a.win_half - a.d_min) / a.d_step);
+        wlo = (int)fmaxf(lo, 0.0f);
+        whi = (int)fminf(hi, (float)(a.D - 1));
+        if (!(lo <= (float)(a.D - 1)) || !(hi >= 0.0f) || wlo > whi) wlo = whi = nearest_level(a, mu);
+    }
+}
+
+// A working lane's search window and the union of its wave's (uniform).
+__device__ __forceinline__ void search_windows(const EmArgs &a, bool work, float mu, int &wlo, int &whi, int &slo,
+                                               int &shi) {
+    search_window(a, mu, wlo, whi);
+    slo = __builtin_amdgcn_readfirstlane(wave_min(work ? wlo : a.D));
+    shi = __builtin_amdgcn_readfirstlane(wave_max(work ? whi : -1));
+}
+
 // One EM iteration of one active lane: M-step sweep over all levels with the
 // current weights, then the E-step and the objective at the chosen level.
 
+// [jlo, jhi] is the wave's prior window, [wlo, whi] the lane's search window
+// and [slo, shi] the union of its wave's search windows.
 template <int K, int ST, bool FRAC, bool EXH, bool SYM>
 __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, const Window (&w)[K], const EmArgs &a,
-                                             int x, int jlo, int jhi, float Pc, Lane<K> &s, bool with_obj) {
+                                             int x, int jlo, int jhi, int wlo, int whi, int slo, int shi, float Pc,
+                                             Lane<K> &s, bool with_obj) {
     using R = typename Rec<ST>::T;
     // ---- M-step: weights from the previous E-step (or the start) ----
     float Q = 0.0f;
@@ -467,8 +495,9 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
 
     if (EXH) {
         float best_E = INFINITY;
-        best_j = 0;
-        for (int j = 0; j < a.D; ++j) {
+        best_j = wlo;
+        for (int j = slo; j <= shi; ++j) {
+            if (j < wlo || j > whi) continue;
             float2 f[K];
             float nn, mx, my;
             f[0] = s.f0;
@@ -498,8 +527,9 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
         float bound = best_E + a.margin_c;
         // Scores G consecutive levels from j0, then re-evaluates the
         // candidates among them exactly, in increasing level order.
-        auto group = [&](auto Gc, int j0, bool inwin) {
+        auto group = [&](auto Gc, auto Wc, int j0, bool inwin) {
             constexpr int G = decltype(Gc)::value;
+            constexpr bool WIN = decltype(Wc)::value;
             float2 f[G][K];
             float lhs[G], P[G];
 #pragma unroll
@@ -534,7 +564,7 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
             for (int i = 0; i < G; ++i) {
                 const int j = j0 + i;
                 // the current best level is already exact: skip it
-                if (lhs[i] <= bound + P[i] && j != best_j) {
+                if (lhs[i] <= bound + P[i] && j != best_j && (!WIN || (j >= wlo && j <= whi))) {
                     float mx, my;
                     const float E = exact_energy<K>(f[i], wt, invW, cw, P[i], mx, my);
                     if (E < best_E || (E == best_E && j < best_j)) {
@@ -546,16 +576,20 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
             }
         };
         constexpr int G = sweep_group<K>();
-        auto sweep = [&](int jb, int je, bool inwin) {
+        auto sweep = [&](auto Wc, int jb, int je, bool inwin) {
             int j = jb;
-            for (; j + G <= je; j += G) group(std::integral_constant<int, G>{}, j, inwin);
-            for (; j < je; ++j) group(std::integral_constant<int, 1>{}, j, inwin);
+            for (; j + G <= je; j += G) group(std::integral_constant<int, G>{}, Wc, j, inwin);
+            for (; j < je; ++j) group(std::integral_constant<int, 1>{}, Wc, j, inwin);
         };
-        // levels below, inside and above the prior window
-        const int j1 = min(jlo, a.D), j2 = max(min(jhi + 1, a.D), j1);
-        sweep(0, j1, false);
-        sweep(j1, j2, true);
-        sweep(j2, a.D, false);
+        // levels [lo, hi) below, inside and above the prior window
+        auto segments = [&](auto Wc, int lo, int hi) {
+            const int j1 = min(max(jlo, lo), hi), j2 = min(max(jhi + 1, j1), hi);
+            sweep(Wc, lo, j1, false);
+            sweep(Wc, j1, j2, true);
+            sweep(Wc, j2, hi, false);
+        };
+        if (a.win_half > 0.0f) segments(std::true_type{}, slo, shi + 1);
+        else segments(std::false_type{}, 0, a.D);
     }
     s.best_j = best_j;
 
@@ -631,6 +665,7 @@ __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
     s.best_j = 0;
     s.f0 = make_float2(0.0f, 0.0f);
     s.n0 = 0.0f;
+    bool work = active;   // pixel reconstructed (all of them unless dynamic-only)
     if (active) {
         s.mu = a.mu_T[pix];
 #pragma unroll
@@ -640,8 +675,9 @@ __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
             s.q[k] = a.q[i];
             s.la[k] = (r > 0.0f ? logf(r) : -INFINITY) + a.lambda;   // ln rho + lambda
             s.lb[k] = (om > 0.0f ? logf(om) : -INFINITY);            // ln(1 - rho)
+            if (k == 0 && a.dyn_only) work = r < a.tau;                // kernel view 0 is the reference
         }
-        s.best_j = a.seed_from_d ? a.d_idx[pix] : nearest_level(a, s.mu);
+        s.best_j = (a.seed_from_d && work) ? a.d_idx[pix] : nearest_level(a, s.mu);
 #pragma unroll
         for (int k = 0; k < K; ++k) s.idx0[k] = FRAC ? 0 : lane_index0(w[k], a.bi[k], a.dmin_i, x);
         fetch<K, ST, FRAC>(win, w[0], a, 0, x, 0, s.idx0[0], s.f0, s.n0);
@@ -651,16 +687,17 @@ __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
     }
 
     const float Pc = kLn2 * __builtin_amdgcn_logf(a.gamma);
-    int jlo, jhi;
-    prior_window(a, active, s.mu, jlo, jhi);
+    int jlo, jhi, wlo, whi, slo, shi;
+    prior_window(a, work, s.mu, jlo, jhi);
+    search_windows(a, work, s.mu, wlo, whi, slo, shi);
 
     const int block_id = blockIdx.y * gridDim.x + blockIdx.x;
     for (int it = 0; it < a.n_iters; ++it) {
         const bool with_obj = a.want_obj || it == a.n_iters - 1;
-        if (active) em_iteration<K, ST, FRAC, EXH, SYM>(win, w, a, x, jlo, jhi, Pc, s, with_obj);
+        if (work) em_iteration<K, ST, FRAC, EXH, SYM>(win, w, a, x, jlo, jhi, wlo, whi, slo, shi, Pc, s, with_obj);
         if (!with_obj) continue;
         // ---- FP64 block sum of the objective ----
-        double sum = wave_sum(active ? (double)s.L : 0.0);
+        double sum = wave_sum(work ? (double)s.L : 0.0);
         const int lane = tid & 63, wv = tid >> 6;
         if (lane == 0) red[wv] = sum;
         __syncthreads();

@@ -83,6 +83,8 @@ struct RefocusArgs {
     const uint8_t *views;
     const int32_t *d_idx;
     const float *q;
+    const float *rho_ref;   // ray prior of the reference view (dynamic-only), else null
+    float tau;
     float *rgb;
     uint8_t *hole;
     int K, H, W, ref, frac;
@@ -98,6 +100,14 @@ __global__ __launch_bounds__(256) void lf_refocus_kernel(RefocusArgs a) {
     if (x >= a.W) return;
     const size_t HW = (size_t)a.H * a.W;
     const size_t pix = (size_t)y * a.W + x;
+    if (a.rho_ref && !(a.rho_ref[pix] < a.tau)) {
+        // dynamic-only: a static reference ray shows the background itself
+        const uint8_t *c_ref = a.views + (((size_t)a.ref * a.H + y) * a.W + x) * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.rgb[pix * 3 + c] = (float)c_ref[c] / 255.0f;
+        if (a.hole) a.hole[pix] = 0;
+        return;
+    }
     const int j = a.d_idx[pix];
     float acc[3] = {0.0f, 0.0f, 0.0f};
     int n = 0;

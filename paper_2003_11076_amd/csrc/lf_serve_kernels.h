@@ -99,6 +99,7 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
     s.best_j = 0;
     s.f0 = make_float2(0.0f, 0.0f);
     s.n0 = 0.0f;
+    bool work = active;   // pixel reconstructed (all of them unless dynamic-only)
     if (active) {
         s.mu = a.mu_T[pix];
 #pragma unroll
@@ -109,6 +110,7 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
             s.la[k] = (r > 0.0f ? logf(r) : -INFINITY) + a.lambda;
             s.lb[k] = (om > 0.0f ? logf(om) : -INFINITY);
             s.q[k] = job.q_warm ? job.q_warm[row + x] : ((r >= job.tau) ? 1.0f : 0.0f);
+            if (k == 0 && a.dyn_only) work = r < job.tau;    // kernel view 0 is the reference
         }
         s.best_j = nearest_level(a, s.mu);
 #pragma unroll
@@ -121,10 +123,12 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
 
     // 4) EM iterations
     const float Pc = kLn2 * __builtin_amdgcn_logf(a.gamma);
-    int jlo, jhi;
-    prior_window(a, active, s.mu, jlo, jhi);
-    if (active)
-        for (int it = 0; it < a.n_iters; ++it) em_iteration<K, ST, FRAC, false, SYM>(win, w, a, x, jlo, jhi, Pc, s, false);
+    int jlo, jhi, wlo, whi, slo, shi;
+    prior_window(a, work, s.mu, jlo, jhi);
+    search_windows(a, work, s.mu, wlo, whi, slo, shi);
+    if (work)
+        for (int it = 0; it < a.n_iters; ++it)
+            em_iteration<K, ST, FRAC, false, SYM>(win, w, a, x, jlo, jhi, wlo, whi, slo, shi, Pc, s, false);
 
     // 5) outputs: weights, level, refocus of the static rays
     if (active) {
@@ -166,7 +170,12 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
             }
         }
         float *o = job.rgb + pix * 3;
-        if (n > 0) {
+        if (!work) {              // static reference ray: the reference pixel is the background
+            const uint8_t *c_ref = job.views + (((size_t)job.ref * H + y) * W + x) * 3;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o[c] = (float)c_ref[c] / 255.0f;
+            job.hole[pix] = 0;
+        } else if (n > 0) {
             const float den = 255.0f * (float)n;
 #pragma unroll
             for (int c = 0; c < 3; ++c) o[c] = acc[c] / den;

@@ -518,7 +518,8 @@ lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, c
         return set_error(LF_EINVAL, "stream_id=%d outside [0,%d)", stream_id, s->max_streams);
     if (p->K > kServeMaxViews) return set_error(LF_EINVAL, "the server handles K <= %d views", kServeMaxViews);
     if (p->flags & (LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE | LF_EXHAUSTIVE_SWEEP))
-        return set_error(LF_EINVAL, "the server takes host inputs and outputs and no flags");
+        return set_error(LF_EINVAL, "the server takes host inputs and outputs, and of the flags only "
+                                    "LF_PRIOR_WINDOW and LF_DYNAMIC_ONLY");
     if (!views || !S_P || !mu_T || !rgb_out) return set_error(LF_EINVAL, "views, S_P, mu_T and rgb_out are required");
     st = validate_host_values(p, S_P, mu_T, nullptr);
     if (st != LF_OK) return st;

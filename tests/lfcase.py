@@ -14,7 +14,9 @@ comparing element by element:
     |a1 - a0| < 1e-3, the decision taken in different precisions; enumerated
     hard labels: exact except where the two largest labeling log weights are
     within 1e-3);
-  * per-pixel objective: |diff| <= 1e-5 * max(|L|, 1) on pixels with matching d.
+  * per-pixel objective: |diff| <= 1e-5 * max(|L|, 1) on pixels with matching d;
+  * variants (window, dynamic-only): d also exempt where mu_T puts a level
+    within 1e-4 of the window's edge or half-way between two levels.
 """
 from __future__ import annotations
 
@@ -57,6 +59,7 @@ class Case:
     S_P: np.ndarray
     mu_T: np.ndarray
     n_iters: int = 1
+    flags: int = 0          # LF_PRIOR_WINDOW / LF_DYNAMIC_ONLY (the variants), passed to both sides
 
     @classmethod
     def from_frame(cls, fr, storage=None, mode="soft", **over):
@@ -72,11 +75,22 @@ class Case:
     def api_params(self, flags=0):
         import paper_2003_11076_amd as LF
         return LF.make_params(self.K, self.H, self.W, self.ref, self.baselines, self.d_min, self.d_step, self.D,
-                              self.beta, self.lam, self.gamma, self.sigma, self.tau, self.storage, self.mode, flags)
+                              self.beta, self.lam, self.gamma, self.sigma, self.tau, self.storage, self.mode,
+                              flags | self.flags)
+
+    @property
+    def window(self):
+        # the C ABI's LF_PRIOR_WINDOW searches |d - mu| <= 3 sigma (sigma in float32)
+        return 3.0 * f32(self.sigma) if self.flags & 0x8 else 0.0
+
+    @property
+    def dyn_only(self):
+        return bool(self.flags & 0x10)
 
     def oracle_params(self, mode=None):
         return O.make_params(self.K, self.H, self.W, self.ref, self.baselines, self.d_min, self.d_step, self.D,
-                             self.beta, self.lam, self.gamma, self.sigma, self.tau, self.storage, mode or self.mode)
+                             self.beta, self.lam, self.gamma, self.sigma, self.tau, self.storage, mode or self.mode,
+                             window=f32(self.window), dyn_only=self.dyn_only)
 
 
 def random_case(K, H, W, D, *, baselines=None, d_min=0.0, d_step=1.0, storage="f32", mode="soft", beta=2133.0,
@@ -190,11 +204,27 @@ def rows_mask(H, W, rows):
     return m
 
 
+def level_edge_exempt(case):
+    """Pixels whose level set depends on a rounding of mu_T: a level within
+    1e-4 of the search window's edge, or mu_T within 1e-4 of half-way between
+    two levels (the nearest level, which the variants fall back to)."""
+    mu = case.mu_T.astype(np.float64)
+    t = (mu - case.d_min) / case.d_step
+    ex = np.abs(t - np.floor(t) - 0.5) < 1e-4
+    if case.window > 0:
+        for e in (mu - case.window, mu + case.window):
+            te = (e - case.d_min) / case.d_step
+            ex |= np.abs(te - np.rint(te)) < 1e-4
+    return ex
+
+
 def compare_iteration(case, ref, ref_soft, q_gpu, d_gpu, L_gpu, rows=None, label=""):
     """Compare one GPU iteration with the oracle's iteration from the same state.
     Returns a dict of statistics; raises AssertionError on a parity failure."""
     sel = rows_mask(case.H, case.W, rows)
     tie = near_tie(ref["E1"], ref["E2"]) & sel
+    if case.flags:
+        tie |= level_edge_exempt(case) & sel
     d_ok = (d_gpu == ref["d_idx"])
     bad_d = sel & ~d_ok & ~tie
     assert not bad_d.any(), f"{label}: d_idx differs off near-ties at {np.argwhere(bad_d)[:5].tolist()} " \
@@ -285,7 +315,7 @@ def teacher_forced(case: Case, n_iters: int, rows=None, device_inputs=True, chec
             q_prev = q_g
         if check_refocus and n_iters > 0:
             rgb_g, d_g, q_g, hole_g = run.refocus()
-            rgb_o, hole_o = O.refocus(op, case.views, d_g, q_g.astype(np.float64), rows=(y0, y1))
+            rgb_o, hole_o = O.refocus(op, case.views, d_g, q_g.astype(np.float64), rows=(y0, y1), rho=rho_o)
             assert np.array_equal(hole_g[y0:y1], hole_o[y0:y1]), "hole mask differs"
             near_half = (np.abs(q_g.astype(np.float64) - 0.5) < 1e-4).any(axis=0)
             cmp = ~near_half[y0:y1]

@@ -1,0 +1,128 @@
+"""Work-avoiding variants through the C ABI: the M-step window around mu_T
+(LF_PRIOR_WINDOW, Sec. III-C) and reconstruction of the dynamic reference
+pixels only (LF_DYNAMIC_ONLY, Sec. III-F / IV-B).  Parity against the FP64
+oracle run with the same variant, plus bitwise relations to the plain path."""
+import sys
+
+import numpy as np
+import pytest
+
+import lf_scenes as S
+from lfcase import Case, GpuRun, random_case, teacher_forced
+
+pytestmark = pytest.mark.gpu
+
+WINDOW, DYN = 0x8, 0x10
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("flags", [WINDOW, DYN, WINDOW | DYN])
+@pytest.mark.parametrize("mode", ["soft", "hard"])
+def test_config1_variants_teacher_forced(flags, mode):
+    case = Case.from_frame(S.make_frame(S.config_spec(1)), storage="f32", mode=mode, flags=flags)
+    _say(f"config1 160x120 K=5 D=32 fp32 {mode} flags={flags:#x} teacher-forced x3")
+    teacher_forced(case, 3)
+
+
+SMALL = [
+    # K, H, W, D, baselines, d_min, d_step, storage
+    (3, 5, 300, 24, [-1, 0, 2], -2, 1, "f16"),
+    (5, 4, 129, 40, None, 0, 1, "bf16"),
+    (4, 3, 70, 16, [-1.5, 0, 0.5, 2.25], 0, 0.5, "f32"),   # fractional shifts
+    (9, 2, 200, 48, None, 0, 1, "f32"),
+    (7, 2, 257, 33, None, 3, 2, "f16"),
+]
+
+
+@pytest.mark.parametrize("K,H,W,D,b,dmin,dstep,st", SMALL)
+@pytest.mark.parametrize("flags", [WINDOW, DYN | WINDOW])
+def test_small_variants_teacher_forced(K, H, W, D, b, dmin, dstep, st, flags):
+    case = random_case(K, H, W, D, baselines=b, d_min=dmin, d_step=dstep, storage=st, seed=K * 100 + W)
+    case.flags = flags
+    _say(f"variants small K={K} H={H} W={W} D={D} b={b} d=({dmin},{dstep}) {st} flags={flags:#x}")
+    teacher_forced(case, 3)
+
+
+def test_config5_window_sampled_rows():
+    case = Case.from_frame(S.make_frame(S.config_spec(5)), storage="bf16", flags=WINDOW | DYN)
+    _say("config5 1920x1080 K=9 D=192 bf16 window+dynamic-only teacher-forced x4, rows 530..538")
+    teacher_forced(case, 4, rows=(530, 538))
+
+
+def _run(case, flags, n=3):
+    run = GpuRun(case, extra_flags=flags)
+    run.iterate(n)
+    out = run.refocus()
+    L = run.state()[2]
+    run.close()
+    return out, L
+
+
+def test_dynamic_only_equals_plain_on_dynamic_pixels():
+    case = Case.from_frame(S.make_frame(S.config_spec(1)), storage="f32")
+    _say("config1 dynamic-only vs plain, bitwise on the dynamic reference pixels")
+    (rgb0, d0, q0, h0), L0 = _run(case, 0)
+    (rgb1, d1, q1, h1), L1 = _run(case, DYN)
+    run = GpuRun(case)
+    _, rho = run.intermediates()
+    run.close()
+    dyn = rho[case.ref] < np.float32(case.tau)
+    assert dyn.any() and (~dyn).any()
+    assert np.array_equal(d1[dyn], d0[dyn]) and np.array_equal(q1[:, dyn], q0[:, dyn])
+    assert np.array_equal(rgb1[dyn], rgb0[dyn]) and np.array_equal(h1[dyn], h0[dyn])
+    assert np.array_equal(L1[dyn], L0[dyn]) and np.all(L1[~dyn] == 0)
+    assert np.array_equal(rgb1[~dyn], case.views[case.ref][~dyn].astype(np.float32) / np.float32(255))
+    assert not h1[~dyn].any()
+
+
+def test_window_covering_all_levels_is_the_plain_sweep():
+    """With 3 sigma wider than the level range the window holds every level:
+    same bits as the plain sweep (fast and exhaustive)."""
+    import paper_2003_11076_amd as LF
+    case = random_case(5, 6, 200, 24, storage="f16", seed=9)
+    case.sigma = np.float32(20.0)
+    _say("window wider than the level range vs plain sweep, fast and exhaustive")
+    for extra in (0, LF.LF_EXHAUSTIVE_SWEEP):
+        (a, La) = _run(case, extra)
+        (b, Lb) = _run(case, WINDOW | extra)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+        assert np.array_equal(La, Lb)
+
+
+def test_window_fast_sweep_matches_exhaustive():
+    import paper_2003_11076_amd as LF
+    case = random_case(7, 4, 300, 64, storage="bf16", seed=10)
+    _say("window: fast vs exhaustive sweep K=7 4x300 D=64 bf16")
+    (a, La) = _run(case, WINDOW | DYN)
+    (b, Lb) = _run(case, WINDOW | DYN | LF.LF_EXHAUSTIVE_SWEEP)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert np.array_equal(La, Lb)
+
+
+SERVER_CASES = [
+    dict(K=5, H=6, W=260, D=40, storage="f16", flags=WINDOW | DYN),
+    dict(K=7, H=4, W=140, D=24, storage="f32", flags=DYN, mode="enum_soft"),
+    dict(K=3, H=5, W=90, D=16, storage="bf16", flags=WINDOW, mode="hard"),
+]
+
+
+@pytest.mark.parametrize("kw", SERVER_CASES)
+def test_server_variants_equal_plain_context(kw):
+    from test_gpu_server import Server, _plain
+    kw = dict(kw)
+    flags = kw.pop("flags")
+    case = random_case(kw.pop("K"), kw.pop("H"), kw.pop("W"), kw.pop("D"), seed=12, **kw)
+    case.flags = flags
+    _say(f"server vs plain context with flags={flags:#x} K={case.K} {case.storage} {case.mode}")
+    with Server(n_iters=3) as srv:
+        fid, (rgb, d, q) = srv.submit(0, case)
+        srv.drain()
+        assert srv.done == {fid: 0}
+    prgb, pd, pq = _plain(case, 3)
+    assert np.array_equal(d, pd) and np.array_equal(q, pq) and np.array_equal(rgb, prgb)
