@@ -333,6 +333,13 @@ __device__ __forceinline__ float log_prior(const EmArgs &a, int j, float mu) {
     return kLn2 * __builtin_amdgcn_logf(a.gamma + g);
 }
 
+// Log prior as the M-step sweep scores it: with a search window (masked),
+// levels farther than win_half from mu are excluded (-inf).
+__device__ __forceinline__ float sweep_log_prior(const EmArgs &a, int j, float mu, bool masked) {
+    if (masked && fabsf(fmaf((float)j, a.d_step, a.d_min) - mu) > a.win_half) return -INFINITY;
+    return log_prior(a, j, mu);
+}
+
 // Per-lane state of one pixel across EM iterations.
 template <int K>
 struct Lane {
@@ -462,9 +469,11 @@ __device__ __forceinline__ void search_window(const EmArgs &a, float mu, int &wl
     }
 }
 
-// A working lane's search window and the union of its wave's (uniform).
-__device__ __forceinline__ void search_windows(const EmArgs &a, bool work, float mu, int &wlo, int &whi, int &slo,
-                                               int &shi) {
+// Union [slo, shi] of the search windows of the wave's working lanes
+// (uniform).  Within it the sweep excludes a lane's other levels through its
+// prior (sweep_log_prior).
+__device__ __forceinline__ void search_range(const EmArgs &a, bool work, float mu, int &slo, int &shi) {
+    int wlo, whi;
     search_window(a, mu, wlo, whi);
     slo = __builtin_amdgcn_readfirstlane(wave_min(work ? wlo : a.D));
     shi = __builtin_amdgcn_readfirstlane(wave_max(work ? whi : -1));
@@ -473,12 +482,12 @@ __device__ __forceinline__ void search_windows(const EmArgs &a, bool work, float
 // One EM iteration of one active lane: M-step sweep over all levels with the
 // current weights, then the E-step and the objective at the chosen level.
 
-// [jlo, jhi] is the wave's prior window, [wlo, whi] the lane's search window
-// and [slo, shi] the union of its wave's search windows.
+// [jlo, jhi] is the wave's prior window and [slo, shi] the union of its
+// lanes' search windows.
 template <int K, int ST, bool FRAC, bool EXH, bool SYM>
 __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, const Window (&w)[K], const EmArgs &a,
-                                             int x, int jlo, int jhi, int wlo, int whi, int slo, int shi, float Pc,
-                                             Lane<K> &s, bool with_obj) {
+                                             int x, int jlo, int jhi, int slo, int shi, float Pc, Lane<K> &s,
+                                             bool with_obj) {
     using R = typename Rec<ST>::T;
     // ---- M-step: weights from the previous E-step (or the start) ----
     float Q = 0.0f;
@@ -492,18 +501,19 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
     const float cw = empty ? 0.0f : a.beta_p;
     const float mu = s.mu;
     int best_j = s.best_j;
+    const bool masked = a.win_half > 0.0f;   // uniform: search window set
 
     if (EXH) {
+        // keeps the seed only when no level of the lane's window has a finite
+        // energy, i.e. when the window is empty and the seed is its fallback
         float best_E = INFINITY;
-        best_j = wlo;
         for (int j = slo; j <= shi; ++j) {
-            if (j < wlo || j > whi) continue;
             float2 f[K];
             float nn, mx, my;
             f[0] = s.f0;
 #pragma unroll
             for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, j, s.idx0[k], f[k], nn);
-            const float E = exact_energy<K>(f, wt, invW, cw, log_prior(a, j, mu), mx, my);
+            const float E = exact_energy<K>(f, wt, invW, cw, sweep_log_prior(a, j, mu, masked), mx, my);
             if (E < best_E) {
                 best_E = E;
                 best_j = j;
@@ -518,7 +528,7 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
             f[0] = s.f0;
 #pragma unroll
             for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, best_j, s.idx0[k], f[k], nn);
-            best_E = exact_energy<K>(f, wt, invW, cw, log_prior(a, best_j, mu), mx, my);
+            best_E = exact_energy<K>(f, wt, invW, cw, sweep_log_prior(a, best_j, mu, masked), mx, my);
         }
         const float A0x = wt[0] * s.f0.x, A0y = wt[0] * s.f0.y, S0 = wt[0] * s.n0;
         // candidate test  E^ - M <= E_best  with the margin folded in:
@@ -527,9 +537,8 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
         float bound = best_E + a.margin_c;
         // Scores G consecutive levels from j0, then re-evaluates the
         // candidates among them exactly, in increasing level order.
-        auto group = [&](auto Gc, auto Wc, int j0, bool inwin) {
+        auto group = [&](auto Gc, int j0, bool inwin) {
             constexpr int G = decltype(Gc)::value;
-            constexpr bool WIN = decltype(Wc)::value;
             float2 f[G][K];
             float lhs[G], P[G];
 #pragma unroll
@@ -557,14 +566,14 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
                     ay = fmaf(wt[k], f[i][k].y, ay);
                     S = fmaf(wt[k], n, S);
                 }
-                P[i] = inwin ? log_prior(a, j0 + i, mu) : Pc;
+                P[i] = inwin ? sweep_log_prior(a, j0 + i, mu, masked) : Pc;
                 lhs[i] = fmaf(-gam, fmaf(ax, ax, ay * ay), alpha * S);
             }
 #pragma unroll
             for (int i = 0; i < G; ++i) {
                 const int j = j0 + i;
                 // the current best level is already exact: skip it
-                if (lhs[i] <= bound + P[i] && j != best_j && (!WIN || (j >= wlo && j <= whi))) {
+                if (lhs[i] <= bound + P[i] && j != best_j) {
                     float mx, my;
                     const float E = exact_energy<K>(f[i], wt, invW, cw, P[i], mx, my);
                     if (E < best_E || (E == best_E && j < best_j)) {
@@ -576,20 +585,18 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
             }
         };
         constexpr int G = sweep_group<K>();
-        auto sweep = [&](auto Wc, int jb, int je, bool inwin) {
+        auto sweep = [&](int jb, int je, bool inwin) {
             int j = jb;
-            for (; j + G <= je; j += G) group(std::integral_constant<int, G>{}, Wc, j, inwin);
-            for (; j < je; ++j) group(std::integral_constant<int, 1>{}, Wc, j, inwin);
+            for (; j + G <= je; j += G) group(std::integral_constant<int, G>{}, j, inwin);
+            for (; j < je; ++j) group(std::integral_constant<int, 1>{}, j, inwin);
         };
-        // levels [lo, hi) below, inside and above the prior window
-        auto segments = [&](auto Wc, int lo, int hi) {
-            const int j1 = min(max(jlo, lo), hi), j2 = min(max(jhi + 1, j1), hi);
-            sweep(Wc, lo, j1, false);
-            sweep(Wc, j1, j2, true);
-            sweep(Wc, j2, hi, false);
-        };
-        if (a.win_half > 0.0f) segments(std::true_type{}, slo, shi + 1);
-        else segments(std::false_type{}, 0, a.D);
+        // levels [slo, shi] below, inside and above the prior window (a
+        // lane's search window lies inside its prior window)
+        const int lo = slo, hi = shi + 1;
+        const int j1 = min(max(jlo, lo), hi), j2 = min(max(jhi + 1, j1), hi);
+        sweep(lo, j1, false);
+        sweep(j1, j2, true);
+        sweep(j2, hi, false);
     }
     s.best_j = best_j;
 
@@ -687,14 +694,14 @@ __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
     }
 
     const float Pc = kLn2 * __builtin_amdgcn_logf(a.gamma);
-    int jlo, jhi, wlo, whi, slo, shi;
+    int jlo, jhi, slo, shi;
     prior_window(a, work, s.mu, jlo, jhi);
-    search_windows(a, work, s.mu, wlo, whi, slo, shi);
+    search_range(a, work, s.mu, slo, shi);
 
     const int block_id = blockIdx.y * gridDim.x + blockIdx.x;
     for (int it = 0; it < a.n_iters; ++it) {
         const bool with_obj = a.want_obj || it == a.n_iters - 1;
-        if (work) em_iteration<K, ST, FRAC, EXH, SYM>(win, w, a, x, jlo, jhi, wlo, whi, slo, shi, Pc, s, with_obj);
+        if (work) em_iteration<K, ST, FRAC, EXH, SYM>(win, w, a, x, jlo, jhi, slo, shi, Pc, s, with_obj);
         if (!with_obj) continue;
         // ---- FP64 block sum of the objective ----
         double sum = wave_sum(work ? (double)s.L : 0.0);

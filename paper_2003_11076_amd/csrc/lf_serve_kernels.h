@@ -123,12 +123,12 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
 
     // 4) EM iterations
     const float Pc = kLn2 * __builtin_amdgcn_logf(a.gamma);
-    int jlo, jhi, wlo, whi, slo, shi;
+    int jlo, jhi, slo, shi;
     prior_window(a, work, s.mu, jlo, jhi);
-    search_windows(a, work, s.mu, wlo, whi, slo, shi);
+    search_range(a, work, s.mu, slo, shi);
     if (work)
         for (int it = 0; it < a.n_iters; ++it)
-            em_iteration<K, ST, FRAC, false, SYM>(win, w, a, x, jlo, jhi, wlo, whi, slo, shi, Pc, s, false);
+            em_iteration<K, ST, FRAC, false, SYM>(win, w, a, x, jlo, jhi, slo, shi, Pc, s, false);
 
     // 5) outputs: weights, level, refocus of the static rays
     if (active) {
