@@ -12,6 +12,7 @@ Every function follows the paper (Kaveti, Katt and Singh, 2020):
                   Sec. III-D (segmentation posterior, Eq. 7)
   refocus      -> Eq. 2 (static rays only) and Sec. IV-B (no static ray: keep the pixel)
   median3      -> Sec. III-E (median filter against the refocus' specular noise)
+  segmentation_maps -> Sec. III-D (updated segmentation, shown per view in its own grid)
 """
 from __future__ import annotations
 
@@ -93,6 +94,7 @@ def lib():
         L.lfo_reconstruct.restype = i32
         L.lfo_threads.restype = i32
         L.lfo_median3.argtypes = [P, dp, dp, i32, i32]
+        L.lfo_segmentation_maps.argtypes = [P, i32p, dp, u8, i32, i32]
         _lib = L
     return _lib
 
@@ -183,6 +185,17 @@ def refocus(p: Params, views, d_idx, q, rows=None, rho=None):
                       _ptr(q, ctypes.c_double), _ptr(rho, ctypes.c_double), _ptr(rgb, ctypes.c_double),
                       _ptr(hole, ctypes.c_uint8), y0, y1)
     return rgb, hole
+
+
+def segmentation_maps(p: Params, d_idx, q, rows=None):
+    """Per-view labels uint8 [K][H][W] in each view's own grid: 1 static,
+    0 dynamic, 2 no reference ray lands there (nearest surface wins)."""
+    d, q = _c(d_idx, np.int32), _c(q, np.float64)
+    labels = np.full((p.K, p.H, p.W), 255, np.uint8)
+    y0, y1 = _rows(p, rows)
+    lib().lfo_segmentation_maps(ctypes.byref(p), _ptr(d, ctypes.c_int32), _ptr(q, ctypes.c_double),
+                                _ptr(labels, ctypes.c_uint8), y0, y1)
+    return labels
 
 
 def median3(p: Params, rgb, rows=None):

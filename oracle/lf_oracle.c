@@ -536,3 +536,41 @@ void lfo_median3(const lfo_params *p, const double *rgb, double *out, int32_t y0
                 out[((size_t)y * W + x) * 3 + c] = v[4];
             }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Per-view segmentation maps in each view's own pixel grid (the updated     */
+/* segmentation of Sec. III-D shown per view, as in the paper's figures).    */
+/* The ray of reference pixel (x, y) at its level d lands in view k at       */
+/* u = x - b_k d on row y, taken to the nearest pixel floor(u + 1/2).  Where */
+/* several rays land on one pixel the one with the largest disparity (the    */
+/* nearest surface) is seen; labels are 1 (static, q_k >= 1/2), 0 (dynamic)  */
+/* and 2 (no reference ray lands there).  labels is uint8 [K][H][W].         */
+/* ------------------------------------------------------------------------ */
+
+void lfo_segmentation_maps(const lfo_params *p, const int32_t *d_idx, const double *q, uint8_t *labels,
+                           int32_t y0, int32_t y1)
+{
+    const int K = p->K, H = p->H, W = p->W;
+#pragma omp parallel for schedule(static)
+    for (int y = y0; y < y1; ++y) {
+        int *winner = (int *)malloc(sizeof(int) * (size_t)W);
+        for (int k = 0; k < K; ++k) {
+            for (int u = 0; u < W; ++u) winner[u] = -1;
+            for (int x = 0; x < W; ++x) {
+                const int j = d_idx[(size_t)y * W + x];
+                const double u = (double)x - p->baselines[k] * (p->d_min + j * p->d_step);
+                const double ur = floor(u + 0.5);
+                if (ur < 0.0 || ur > W - 1) continue;
+                const int iu = (int)ur;
+                const int w = winner[iu];
+                if (w < 0 || j > d_idx[(size_t)y * W + w]) winner[iu] = x;
+            }
+            for (int u = 0; u < W; ++u) {
+                uint8_t *l = labels + ((size_t)k * H + y) * W + u;
+                if (winner[u] < 0) *l = 2;
+                else *l = q[((size_t)k * H + y) * W + winner[u]] >= 0.5 ? 1 : 0;
+            }
+        }
+        free(winner);
+    }
+}

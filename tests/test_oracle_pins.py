@@ -612,3 +612,54 @@ def test_dynamic_prior_keeps_relative_accuracy_near_certainty():
     want = (1 - t) * 2.0 ** -20                          # interpolation of 1 - S_P between columns 1 and 2
     assert abs(pr.omr[1, 0, 2] - want) <= 1e-12 * want
     assert pr.omr[1, 0, 3] == 0.0 and pr[0][1, 0, 3] == 1.0   # exact certainty stays exact
+
+
+# ---------------------------------------------------------------- per-view segmentation maps
+
+def test_segmentation_reference_view_is_identity():
+    rng = np.random.default_rng(50)
+    K, H, W, D = 3, 4, 20, 8
+    p = _params(K, H, W, [-1.0, 0.0, 1.5], D, 100.0, ref=1)
+    d = rng.integers(0, D, (H, W)).astype(np.int32)
+    q = rng.uniform(0, 1, (K, H, W))
+    lab = O.segmentation_maps(p, d, q)
+    assert np.array_equal(lab[1], (q[1] >= 0.5).astype(np.uint8))
+
+
+def test_segmentation_constant_level_is_a_shift():
+    """All pixels at one level: view k's pixel u shows reference pixel
+    u + b_k d (integer shift), nothing beyond the frame edge."""
+    rng = np.random.default_rng(51)
+    K, H, W, D, j0 = 4, 3, 25, 6, 3
+    b = [-2.0, 0.0, 1.0, 3.0]
+    p = _params(K, H, W, b, D, 100.0, ref=1, d_min=0.0, d_step=1.0)
+    d = np.full((H, W), j0, np.int32)
+    q = rng.uniform(0, 1, (K, H, W))
+    lab = O.segmentation_maps(p, d, q)
+    for k in range(K):
+        s = int(b[k] * j0)
+        want = np.full((H, W), 2, np.uint8)
+        for u in range(W):
+            if 0 <= u + s < W:
+                want[:, u] = (q[k, :, u + s] >= 0.5)
+        assert np.array_equal(lab[k], want), k
+
+
+def test_segmentation_nearest_surface_wins_and_rounds_half_up():
+    K, H, W, D = 2, 1, 12, 4
+    p = _params(K, H, W, [0.0, 1.0], D, 100.0, ref=0)
+    d = np.zeros((H, W), np.int32)
+    d[0, 5], d[0, 4] = 2, 1             # both land on view-1 pixel 3: the larger disparity is seen
+    q = np.zeros((K, H, W))
+    q[1, 0, 5] = 1.0
+    lab = O.segmentation_maps(p, d, q)
+    assert lab[1, 0, 3] == 1
+    q[1, 0, 5], q[1, 0, 4] = 0.0, 1.0
+    assert O.segmentation_maps(p, d, q)[1, 0, 3] == 0
+    # half a pixel: u = x - 0.5 is taken to pixel x
+    p = _params(K, H, W, [0.0, 0.5], D, 100.0, ref=0)
+    d = np.ones((H, W), np.int32)
+    q = np.zeros((K, H, W))
+    q[1, 0, 7] = 0.75
+    lab = O.segmentation_maps(p, d, q)
+    assert lab[1, 0, 7] == 1 and lab[1, 0, 6] == 0 and (lab[1, 0] != 2).all()
