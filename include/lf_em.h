@@ -179,6 +179,20 @@ lf_status lf_em_iterate(lf_ctx *c, int32_t n_iters, double *objective);
 lf_status lf_refocus(lf_ctx *c, float *rgb, int32_t *d_idx, float *q, uint8_t *hole, int32_t median);
 
 /*
+ * lf_segmentation_maps -- the updated segmentation (Sec. III-D) of every view
+ * in the view's own pixel grid, from the current levels and weights.  The ray
+ * of reference pixel (x, y) lands in view k at u = x - baselines[k] * d, taken
+ * to the nearest pixel floor(u + 1/2) on row y; where several rays land on one
+ * pixel the one with the largest level (the nearest surface) is seen.
+ *   labels : uint8 [K][H][W] (device memory with LF_OUTPUTS_ON_DEVICE):
+ *            1 = static (q_k >= 0.5), 0 = dynamic, 2 = no reference ray
+ *            lands on the pixel.
+ * Errors: LF_EINVAL (NULL arguments, W > 65535, D > 32767), LF_ESTATE (no EM
+ * iteration since the last load), LF_EDEVICE.
+ */
+lf_status lf_segmentation_maps(lf_ctx *c, uint8_t *labels);
+
+/*
  * lf_em_state -- copy out the current state without refocusing.
  *   q      : float [K][H][W] current weights (q0 before the first iteration), or NULL.
  *   d_idx  : int32 [H][W] disparity levels of the last iteration, or NULL.

@@ -77,11 +77,13 @@ def lib():
         L.lf_em_iterate.argtypes = [vp, i32, vp]
         L.lf_refocus.argtypes = [vp, vp, vp, vp, vp, i32]
         L.lf_em_state.argtypes = [vp, vp, vp, vp]
+        L.lf_segmentation_maps.argtypes = [vp, vp]
         L.lf_em_intermediates.argtypes = [vp, vp, vp]
         L.lf_em_destroy.argtypes = [vp]
         L.lf_em_destroy.restype = None
         L.lf_last_error.restype = ctypes.c_char_p
-        for f in ("lf_em_init", "lf_em_load", "lf_em_iterate", "lf_refocus", "lf_em_state", "lf_em_intermediates"):
+        for f in ("lf_em_init", "lf_em_load", "lf_em_iterate", "lf_refocus", "lf_em_state", "lf_em_intermediates",
+                  "lf_segmentation_maps"):
             getattr(L, f).restype = i32
         _bind_server(L)
         _lib = L
@@ -166,6 +168,10 @@ def lf_refocus(ctx, rgb, d_idx=None, q=None, hole=None, median=0):
 
 def lf_em_state(ctx, q=None, d_idx=None, L_pix=None):
     return _check(lib().lf_em_state(ctx, addr(q), addr(d_idx), addr(L_pix)))
+
+
+def lf_segmentation_maps(ctx, labels):
+    return _check(lib().lf_segmentation_maps(ctx, addr(labels)))
 
 
 def lf_em_intermediates(ctx, feat=None, rho=None):

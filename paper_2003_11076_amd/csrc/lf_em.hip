@@ -313,6 +313,8 @@ struct lf_ctx {
     void *feat;
     float *rho, *omr, *q, *lpix, *rgb, *rgb_med;
     int32_t *d_idx;
+    int32_t *seg_keys;      // per-view segmentation: ray seen at each view pixel
+    uint8_t *seg_labels;    // per-view segmentation labels (host-output staging)
     uint8_t *hole;
     double *obj;
     uint32_t *bad;
@@ -361,6 +363,8 @@ static lf_status ctx_alloc(lf_ctx *c) {
         plan.add(&c->hole, HW);
     }
     plan.add(&c->rgb_med, HW * 12);
+    plan.add(&c->seg_keys, KHW * 4);
+    if (!dev_out) plan.add(&c->seg_labels, KHW);
     lf_status st = c->arena.allocate(plan);
     if (st != LF_OK) return st;
     LF_HIP(hipHostMalloc((void **)&c->h_obj, (size_t)kMaxItersPerLaunch * c->n_blocks * 8, hipHostMallocDefault),
@@ -565,6 +569,48 @@ lf_status lf_refocus(lf_ctx *c, float *rgb, int32_t *d_idx, float *q, uint8_t *h
     if (st == LF_OK && q) st = copy_out(c, q, c->q, HW * p.K * 4);
     if (st != LF_OK) return st;
     if (!dev_out) LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    return LF_OK;
+}
+
+lf_status lf_segmentation_maps(lf_ctx *c, uint8_t *labels) {
+    g_last_error.clear();
+    if (!c) return set_error(LF_EINVAL, "context is NULL");
+    if (!labels) return set_error(LF_EINVAL, "labels is required");
+    if (!c->loaded || c->iters == 0) return set_error(LF_ESTATE, "segmentation maps need at least one EM iteration");
+    const lf_params &p = c->p;
+    if (p.W > 65535 || p.D > 32767) return set_error(LF_EINVAL, "segmentation maps need W <= 65535 and D <= 32767");
+    const size_t KHW = (size_t)p.K * p.H * p.W;
+    const bool dev_out = p.flags & LF_OUTPUTS_ON_DEVICE;
+    SegArgs a{};
+    a.d_idx = c->d_idx;
+    a.q = c->q;
+    a.keys = c->seg_keys;
+    a.labels = dev_out ? labels : c->seg_labels;
+    a.K = p.K;
+    a.H = p.H;
+    a.W = p.W;
+    a.frac = c->g.frac;
+    a.dmin_i = c->g.dmin_i;
+    a.dstep_i = c->g.dstep_i;
+    a.d_min = p.d_min;
+    a.d_step = p.d_step;
+    for (int k = 0; k < p.K; ++k) {
+        a.bi[k] = c->g.bi[k];
+        a.b[k] = p.baselines[k];
+    }
+    hipLaunchKernelGGL(lf_fill_i32_kernel, dim3((unsigned)((KHW + 255) / 256)), dim3(256), 0, c->stream, c->seg_keys,
+                       KHW, -1);
+    LF_HIP(hipGetLastError(), "segmentation fill launch");
+    const dim3 grid((p.W + 255) / 256, p.H, p.K);
+    hipLaunchKernelGGL(lf_seg_scatter_kernel, grid, dim3(256), 0, c->stream, a);
+    LF_HIP(hipGetLastError(), "segmentation scatter launch");
+    hipLaunchKernelGGL(lf_seg_resolve_kernel, grid, dim3(256), 0, c->stream, a);
+    LF_HIP(hipGetLastError(), "segmentation resolve launch");
+    if (!dev_out) {
+        lf_status st = copy_out(c, labels, c->seg_labels, KHW);
+        if (st != LF_OK) return st;
+        LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    }
     return LF_OK;
 }
 

@@ -5,6 +5,7 @@
 //                          (Sec. III-B, III-F)
 //   lf_refocus_kernel      mean of the static rays (Eq. 2)
 //   lf_median3_kernel      3x3 per-channel median of the refocused image (Sec. III-E)
+//   lf_seg_*_kernel        per-view segmentation maps in each view's own grid (Sec. III-D)
 // Included by one translation unit only.
 #pragma once
 
@@ -184,6 +185,64 @@ __global__ __launch_bounds__(256) void lf_median3_kernel(const float *__restrict
             for (int m = (i & 1); m + 1 < 9; m += 2) cswap(v[m], v[m + 1]);
         out[((size_t)y * W + x) * 3 + c] = v[4];
     }
+}
+
+
+// ---------------------------------------------------------------------------
+// Per-view segmentation maps (the updated segmentation of Sec. III-D, shown
+// in each view's own pixel grid).  The ray of reference pixel (x, y) at its
+// level lands in view k at u = x - b_k d, taken to the nearest pixel
+// floor(u + 1/2); the ray with the largest level (the nearest surface) is
+// the one seen.  keys [K][H][W] hold (level << 16 | x) of the ray seen, -1
+// for none: an atomic max picks it independently of the order of arrival.
+// Labels: 1 static (q >= 1/2), 0 dynamic, 2 no reference ray.
+// ---------------------------------------------------------------------------
+struct SegArgs {
+    const int32_t *d_idx;
+    const float *q;        // [K][H][W], array view order
+    int32_t *keys;         // [K][H][W]
+    uint8_t *labels;       // [K][H][W]
+    int K, H, W, frac;
+    int dmin_i, dstep_i;
+    float d_min, d_step;
+    int bi[kMaxViews];
+    float b[kMaxViews];
+};
+
+__global__ __launch_bounds__(256) void lf_fill_i32_kernel(int32_t *p, size_t n, int32_t v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// grid (ceil(W/256), H, K)
+__global__ __launch_bounds__(256) void lf_seg_scatter_kernel(SegArgs a) {
+    const int k = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.W) return;
+    const int j = a.d_idx[(size_t)y * a.W + x];
+    int u;
+    if (!a.frac) {
+        u = x - a.bi[k] * (a.dmin_i + j * a.dstep_i);
+    } else {
+        int i0;
+        float t;
+        footprint(x, a.b[k], fmaf((float)j, a.d_step, a.d_min), i0, t);
+        u = i0 + (t >= 0.5f ? 1 : 0);
+    }
+    if (u < 0 || u >= a.W) return;
+    atomicMax(&a.keys[((size_t)k * a.H + y) * a.W + u], (j << 16) | x);
+}
+
+// grid (ceil(W/256), H, K)
+__global__ __launch_bounds__(256) void lf_seg_resolve_kernel(SegArgs a) {
+    const int k = blockIdx.z, y = blockIdx.y;
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= a.W) return;
+    const size_t row = ((size_t)k * a.H + y) * a.W;
+    const int32_t key = a.keys[row + u];
+    uint8_t l = 2;
+    if (key >= 0) l = a.q[row + (key & 0xffff)] >= 0.5f ? 1 : 0;
+    a.labels[row + u] = l;
 }
 
 }  // namespace lfem
