@@ -13,6 +13,8 @@ Every function follows the paper (Kaveti, Katt and Singh, 2020):
   refocus      -> Eq. 2 (static rays only) and Sec. IV-B (no static ray: keep the pixel)
   median3      -> Sec. III-E (median filter against the refocus' specular noise)
   segmentation_maps -> Sec. III-D (updated segmentation, shown per view in its own grid)
+  support_points, raster_prior -> Sec. III-C (disparity prior: support points, dynamic filtering,
+                  transfer from the other views, triangulation and interpolation)
 """
 from __future__ import annotations
 
@@ -59,6 +61,26 @@ def make_params(K, H, W, ref, baselines, d_min, d_step, D, beta, lam=float("nan"
     return p
 
 
+class SupportParams(ctypes.Structure):
+    """Support-point matching and filtering parameters (prior construction)."""
+    _fields_ = [
+        ("step", ctypes.c_int32), ("radius", ctypes.c_int32), ("texture_min", ctypes.c_int32),
+        ("ratio_num", ctypes.c_int32), ("ratio_den", ctypes.c_int32),
+        ("incon_radius", ctypes.c_int32), ("incon_levels", ctypes.c_int32), ("incon_min", ctypes.c_int32),
+        ("static_min", ctypes.c_int32),
+    ]
+
+
+def make_support_params(step=5, radius=2, texture_min=2000, ratio_num=85, ratio_den=100, incon_radius=10,
+                        incon_levels=2, incon_min=3, static_min=20) -> SupportParams:
+    sp = SupportParams()
+    sp.step, sp.radius, sp.texture_min = step, radius, texture_min
+    sp.ratio_num, sp.ratio_den = ratio_num, ratio_den
+    sp.incon_radius, sp.incon_levels, sp.incon_min = incon_radius, incon_levels, incon_min
+    sp.static_min = static_min
+    return sp
+
+
 def build(force: bool = False) -> str:
     """Compile lf_oracle.c with gcc (no HIP).  Returns the library path."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -95,6 +117,9 @@ def lib():
         L.lfo_threads.restype = i32
         L.lfo_median3.argtypes = [P, dp, dp, i32, i32]
         L.lfo_segmentation_maps.argtypes = [P, i32p, dp, u8, i32, i32]
+        L.lfo_support_points.argtypes = [P, ctypes.POINTER(SupportParams), u8, fp, i32p, i32]
+        L.lfo_support_points.restype = i32
+        L.lfo_raster_prior.argtypes = [P, i32p, i32, i32p, i32, fp]
         _lib = L
     return _lib
 
@@ -196,6 +221,29 @@ def segmentation_maps(p: Params, d_idx, q, rows=None):
     lib().lfo_segmentation_maps(ctypes.byref(p), _ptr(d, ctypes.c_int32), _ptr(q, ctypes.c_double),
                                 _ptr(labels, ctypes.c_uint8), y0, y1)
     return labels
+
+
+def support_points(p: Params, sp: SupportParams, views, S_P) -> np.ndarray:
+    """Support points int32 [n][4] = (u, y, level, view), sorted by (y, u)."""
+    v, s = _c(views, np.uint8), _c(S_P, np.float32)
+    nx = max(0, (p.W - sp.step // 2 + sp.step - 1) // sp.step)
+    ny = max(0, (p.H - sp.step // 2 + sp.step - 1) // sp.step)
+    cap = nx * ny * p.K + 1
+    out = np.zeros((cap, 4), np.int32)
+    n = lib().lfo_support_points(ctypes.byref(p), ctypes.byref(sp), _ptr(v, ctypes.c_uint8), _ptr(s, ctypes.c_float),
+                                 _ptr(out, ctypes.c_int32), cap)
+    if n < 0:
+        raise ValueError("bad support parameters")
+    return out[:n].copy()
+
+
+def raster_prior(p: Params, points, tris) -> np.ndarray:
+    """mu_T float32 [H][W] from support points and a triangulation of them."""
+    pts, tr = _c(points, np.int32), _c(np.asarray(tris, np.int32).reshape(-1, 3), np.int32)
+    mu = np.zeros((p.H, p.W), np.float32)
+    lib().lfo_raster_prior(ctypes.byref(p), _ptr(pts, ctypes.c_int32), len(pts), _ptr(tr, ctypes.c_int32), len(tr),
+                           _ptr(mu, ctypes.c_float))
+    return mu
 
 
 def median3(p: Params, rgb, rows=None):

@@ -574,3 +574,262 @@ void lfo_segmentation_maps(const lfo_params *p, const int32_t *d_idx, const doub
         free(winner);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Disparity prior construction (Sec. III-C, disparity prior): support       */
+/* points matched along the epipolar line over the full disparity range,     */
+/* those on dynamic objects dropped, support points of the other views       */
+/* transferred into the reference where it is occluded by a dynamic object,  */
+/* duplicates and inconsistent points removed; then the prior mu_T is the    */
+/* piecewise-linear interpolation over a triangulation of the points.        */
+/*                                                                            */
+/* Readings (the paper follows ELAS and gives no numbers):                    */
+/*  - matching uses the integer Sobel responses (Gx, Gy) of L = R+G+B and    */
+/*    the sum of absolute differences over a (2r+1)^2 window, summed over    */
+/*    the views matched against, borders replicated; integer geometry only   */
+/*    (integer baselines and levels);                                         */
+/*  - a candidate is kept when its window has texture (sum of |Gx| + |Gy|    */
+/*    >= texture_min) and its best cost is unique: best * den < second *     */
+/*    num, the second best taken over levels at least 2 away; ties of the    */
+/*    best go to the lowest level;                                            */
+/*  - the views on either side of the matched view are summed apart and the */
+/*    smaller of the two sums is the cost (one side usually sees past an     */
+/*    occluder); a view at the end of the array has one side;                */
+/*  - reference pass: grid points of the reference matched against every     */
+/*    other view, kept where the point and at least static_min pixels of its */
+/*    window are static in the reference (S_P >= tau);                       */
+/*  - transfer pass: grid points of each other view a matched against its    */
+/*    non-reference neighbours a-1, a+1, static in view a as above, moved to */
+/*    reference column u = x + b_a d and kept where the reference is         */
+/*    dynamic there (S_P_ref < tau, the occluded part); of several points    */
+/*    landing on one reference pixel the one of the lowest view (then the    */
+/*    lowest x) is kept;                                                      */
+/*  - consistency: a point is kept when at least incon_min other points lie  */
+/*    within incon_radius pixels (Chebyshev) with levels within              */
+/*    incon_levels;                                                           */
+/*  - points are reported sorted by (y, u).                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t step, radius, texture_min, ratio_num, ratio_den;
+    int32_t incon_radius, incon_levels, incon_min, static_min;
+} lfo_support_params;
+
+/* Integer Sobel responses of view k, [H][W][2]. */
+static void sobel_int(const lfo_params *p, const uint8_t *views, int k, int32_t *g)
+{
+    const int H = p->H, W = p->W;
+    const uint8_t *v = views + (size_t)k * H * W * 3;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int L[3][3];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) L[r][c] = (int)intensity(v, H, W, x + c - 1, y + r - 1);
+            g[((size_t)y * W + x) * 2 + 0] = (L[0][2] - L[0][0]) + 2 * (L[1][2] - L[1][0]) + (L[2][2] - L[2][0]);
+            g[((size_t)y * W + x) * 2 + 1] = (L[2][0] - L[0][0]) + 2 * (L[2][1] - L[0][1]) + (L[2][2] - L[0][2]);
+        }
+}
+
+/* Whether the grid point (x, y) is static in view a by the prior threshold
+ * (S_P >= tau) and at least static_min pixels of its matching window are. */
+static int window_static(const lfo_params *p, const lfo_support_params *sp, const float *S_P, int a, int x, int y)
+{
+    const int H = p->H, W = p->W, r = sp->radius;
+    const float tau = (float)p->tau;
+    if (!(S_P[((size_t)a * H + y) * W + x] >= tau)) return 0;
+    int n = 0;
+    for (int dy = -r; dy <= r; ++dy)
+        for (int dx = -r; dx <= r; ++dx)
+            n += S_P[((size_t)a * H + clampi(y + dy, 0, H - 1)) * W + clampi(x + dx, 0, W - 1)] >= tau;
+    return n >= sp->static_min;
+}
+
+/* Level of the unique best match of grid point (x, y) of view a against the
+ * views in vs (n_vs of them), or -1. */
+static int match_point(const lfo_params *p, const lfo_support_params *sp, int32_t *const *G, int a, const int *vs,
+                       int n_vs, int x, int y)
+{
+    const int H = p->H, W = p->W, D = p->D, r = sp->radius;
+    long texture = 0;
+    for (int dy = -r; dy <= r; ++dy)
+        for (int dx = -r; dx <= r; ++dx) {
+            const int32_t *ga = G[a] + ((size_t)clampi(y + dy, 0, H - 1) * W + clampi(x + dx, 0, W - 1)) * 2;
+            texture += labs((long)ga[0]) + labs((long)ga[1]);
+        }
+    if (texture < sp->texture_min) return -1;
+    long *cost = (long *)malloc(sizeof(long) * (size_t)D);
+    for (int j = 0; j < D; ++j) {
+        const double d = p->d_min + j * p->d_step;
+        /* the views on either side of view a are summed apart and the
+         * smaller sum is the cost: one side usually sees past an occluder */
+        long side[2] = {0, 0};
+        int used[2] = {0, 0};
+        for (int i = 0; i < n_vs; ++i) {
+            const int v = vs[i];
+            const int sd = p->baselines[v] > p->baselines[a];
+            used[sd] = 1;
+            const int shift = (int)lround((p->baselines[v] - p->baselines[a]) * d);
+            for (int dy = -r; dy <= r; ++dy) {
+                const int yy = clampi(y + dy, 0, H - 1);
+                for (int dx = -r; dx <= r; ++dx) {
+                    const int32_t *ga = G[a] + ((size_t)yy * W + clampi(x + dx, 0, W - 1)) * 2;
+                    const int32_t *gv = G[v] + ((size_t)yy * W + clampi(x + dx - shift, 0, W - 1)) * 2;
+                    side[sd] += labs((long)ga[0] - gv[0]) + labs((long)ga[1] - gv[1]);
+                }
+            }
+        }
+        cost[j] = (used[0] && used[1]) ? (side[0] < side[1] ? side[0] : side[1]) : side[0] + side[1];
+    }
+    int best = 0;
+    for (int j = 1; j < D; ++j)
+        if (cost[j] < cost[best]) best = j;
+    long second = -1;
+    for (int j = 0; j < D; ++j)
+        if (abs(j - best) >= 2 && (second < 0 || cost[j] < second)) second = cost[j];
+    const int ok = second >= 0 ? cost[best] * sp->ratio_den < second * sp->ratio_num : 1;
+    free(cost);
+    return ok ? best : -1;
+}
+
+static int cmp_points(const void *pa, const void *pb)
+{
+    const int32_t *a = (const int32_t *)pa, *b = (const int32_t *)pb;
+    if (a[1] != b[1]) return a[1] < b[1] ? -1 : 1;   /* y */
+    if (a[0] != b[0]) return a[0] < b[0] ? -1 : 1;   /* u */
+    return 0;
+}
+
+/* points: int32 [max_points][4] = (u, y, level, view).  Returns the number of
+ * points kept (at most max_points are written), or -1 on a bad argument. */
+int32_t lfo_support_points(const lfo_params *p, const lfo_support_params *sp, const uint8_t *views, const float *S_P,
+                           int32_t *points, int32_t max_points)
+{
+    const int K = p->K, H = p->H, W = p->W, s = sp->step;
+    if (s < 1 || sp->radius < 0) return -1;
+    int32_t **G = (int32_t **)malloc(sizeof(int32_t *) * (size_t)K);
+    for (int k = 0; k < K; ++k) {
+        G[k] = (int32_t *)malloc(sizeof(int32_t) * (size_t)H * W * 2);
+        sobel_int(p, views, k, G[k]);
+    }
+    const float tau = (float)p->tau;
+    const int nx = (W - s / 2 + s - 1) / s, ny = (H - s / 2 + s - 1) / s;
+    /* candidates: reference pass, then transfer pass view by view */
+    size_t cap = (size_t)nx * ny * K + 1, n = 0;
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * 4 * cap);
+    int32_t *level = (int32_t *)malloc(sizeof(int32_t) * (size_t)nx * ny);
+    {
+        int vs[LFO_MAX_VIEWS], n_vs = 0;
+        for (int k = 0; k < K; ++k)
+            if (k != p->ref) vs[n_vs++] = k;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int iy = 0; iy < ny; ++iy)
+            for (int ix = 0; ix < nx; ++ix) {
+                const int x = s / 2 + ix * s, y = s / 2 + iy * s;
+                int j = -1;
+                if (window_static(p, sp, S_P, p->ref, x, y)) j = match_point(p, sp, G, p->ref, vs, n_vs, x, y);
+                level[(size_t)iy * nx + ix] = j;
+            }
+        for (int iy = 0; iy < ny; ++iy)
+            for (int ix = 0; ix < nx; ++ix) {
+                const int j = level[(size_t)iy * nx + ix];
+                if (j < 0) continue;
+                int32_t *c = cand + 4 * n++;
+                c[0] = s / 2 + ix * s; c[1] = s / 2 + iy * s; c[2] = j; c[3] = p->ref;
+            }
+    }
+    const size_t n_ref = n;
+    uint8_t *taken = (uint8_t *)calloc((size_t)H * W, 1);
+    for (int a = 0; a < K; ++a) {
+        if (a == p->ref) continue;
+        int vs[2], n_vs = 0;
+        if (a - 1 >= 0 && a - 1 != p->ref) vs[n_vs++] = a - 1;
+        if (a + 1 < K && a + 1 != p->ref) vs[n_vs++] = a + 1;
+        if (n_vs == 0) continue;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int iy = 0; iy < ny; ++iy)
+            for (int ix = 0; ix < nx; ++ix) {
+                const int x = s / 2 + ix * s, y = s / 2 + iy * s;
+                int j = -1;
+                if (window_static(p, sp, S_P, a, x, y)) j = match_point(p, sp, G, a, vs, n_vs, x, y);
+                level[(size_t)iy * nx + ix] = j;
+            }
+        for (int iy = 0; iy < ny; ++iy)
+            for (int ix = 0; ix < nx; ++ix) {
+                const int j = level[(size_t)iy * nx + ix];
+                if (j < 0) continue;
+                const int x = s / 2 + ix * s, y = s / 2 + iy * s;
+                const int u = x + (int)lround(p->baselines[a] * (p->d_min + j * p->d_step));
+                if (u < 0 || u >= W) continue;
+                if (!(S_P[((size_t)p->ref * H + y) * W + u] < tau)) continue;
+                if (taken[(size_t)y * W + u]) continue;
+                taken[(size_t)y * W + u] = 1;
+                int32_t *c = cand + 4 * n++;
+                c[0] = u; c[1] = y; c[2] = j; c[3] = a;
+            }
+    }
+    (void)n_ref;
+    /* consistency with the neighbours */
+    int32_t kept = 0;
+    uint8_t *keep = (uint8_t *)calloc(n + 1, 1);
+#pragma omp parallel for schedule(static)
+    for (size_t i = 0; i < n; ++i) {
+        int cnt = 0;
+        for (size_t m = 0; m < n; ++m) {
+            if (m == i) continue;
+            if (abs(cand[4 * m] - cand[4 * i]) <= sp->incon_radius &&
+                abs(cand[4 * m + 1] - cand[4 * i + 1]) <= sp->incon_radius &&
+                abs(cand[4 * m + 2] - cand[4 * i + 2]) <= sp->incon_levels)
+                ++cnt;
+        }
+        keep[i] = cnt >= sp->incon_min;
+    }
+    int32_t *out = (int32_t *)malloc(sizeof(int32_t) * 4 * (n + 1));
+    for (size_t i = 0; i < n; ++i)
+        if (keep[i]) { memcpy(out + 4 * kept, cand + 4 * i, sizeof(int32_t) * 4); ++kept; }
+    qsort(out, (size_t)kept, sizeof(int32_t) * 4, cmp_points);
+    memcpy(points, out, sizeof(int32_t) * 4 * (size_t)(kept < max_points ? kept : max_points));
+    free(out); free(keep); free(taken); free(level); free(cand);
+    for (int k = 0; k < K; ++k) free(G[k]);
+    free(G);
+    return kept;
+}
+
+/* mu_T from support points and a triangulation of them: in a triangle the   */
+/* disparity is the barycentric interpolation of its corners' levels (exact  */
+/* integer areas; the first triangle containing the pixel, edges included);  */
+/* outside every triangle, the disparity of the nearest point (lowest index  */
+/* on ties); with no point at all, the middle of the level range.  points    */
+/* int32 [n][4] as above, tris int32 [n_tri][3].                             */
+void lfo_raster_prior(const lfo_params *p, const int32_t *points, int32_t n, const int32_t *tris, int32_t n_tri,
+                      float *mu_T)
+{
+    const int H = p->H, W = p->W;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            double mu = NAN;
+            for (int t = 0; t < n_tri && isnan(mu); ++t) {
+                const int32_t *a = points + 4 * tris[3 * t], *b = points + 4 * tris[3 * t + 1],
+                              *c = points + 4 * tris[3 * t + 2];
+                const long A = (long)(b[0] - a[0]) * (c[1] - a[1]) - (long)(b[1] - a[1]) * (c[0] - a[0]);
+                if (A == 0) continue;
+                const long wa = (long)(b[0] - x) * (c[1] - y) - (long)(b[1] - y) * (c[0] - x);
+                const long wb = (long)(c[0] - x) * (a[1] - y) - (long)(c[1] - y) * (a[0] - x);
+                const long wc = (long)(a[0] - x) * (b[1] - y) - (long)(a[1] - y) * (b[0] - x);
+                const int inside = A > 0 ? (wa >= 0 && wb >= 0 && wc >= 0) : (wa <= 0 && wb <= 0 && wc <= 0);
+                if (!inside) continue;
+                const double da = p->d_min + a[2] * p->d_step, db = p->d_min + b[2] * p->d_step,
+                             dc = p->d_min + c[2] * p->d_step;
+                mu = ((double)wa * da + (double)wb * db + (double)wc * dc) / (double)A;
+            }
+            if (isnan(mu) && n == 0) mu = p->d_min + 0.5 * (p->D - 1) * p->d_step;   /* no point at all */
+            if (isnan(mu)) {
+                long best = -1;
+                for (int i = 0; i < n; ++i) {
+                    const long dx = points[4 * i] - x, dy = points[4 * i + 1] - y, d2 = dx * dx + dy * dy;
+                    if (best < 0 || d2 < best) { best = d2; mu = p->d_min + points[4 * i + 2] * p->d_step; }
+                }
+            }
+            mu_T[(size_t)y * W + x] = (float)mu;
+        }
+}

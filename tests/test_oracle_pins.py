@@ -663,3 +663,132 @@ def test_segmentation_nearest_surface_wins_and_rounds_half_up():
     q[1, 0, 7] = 0.75
     lab = O.segmentation_maps(p, d, q)
     assert lab[1, 0, 7] == 1 and lab[1, 0, 6] == 0 and (lab[1, 0] != 2).all()
+
+
+# ---------------------------------------------------------------- disparity prior construction
+
+def _plane_views(K, H, W, b, d0, rng, period=None):
+    """Views of one fronto-parallel textured plane at integer disparity d0:
+    view k pixel x shows texture column x + b_k d0 (same row)."""
+    pad = int(max(abs(v) for v in b) * d0) + 2
+    if period:
+        base = rng.integers(0, 256, size=(H, period, 3))
+        tex = np.tile(base, (1, (W + 2 * pad) // period + 2, 1))[:, :W + 2 * pad]
+    else:
+        tex = rng.integers(0, 256, size=(H, W + 2 * pad, 3))
+    views = np.zeros((K, H, W, 3), np.uint8)
+    for k in range(K):
+        s = int(b[k] * d0)
+        views[k] = tex[:, pad + s:pad + s + W]
+    return views
+
+
+def test_support_points_recover_a_plane():
+    rng = np.random.default_rng(60)
+    K, H, W, D, d0 = 5, 40, 80, 16, 5
+    b = [-2.0, -1.0, 0.0, 1.0, 2.0]
+    views = _plane_views(K, H, W, b, d0, rng)
+    p = _params(K, H, W, b, D, 100.0, ref=2)
+    pts = O.support_points(p, O.make_support_params(), views, np.ones((K, H, W), np.float32))
+    xs, ys = np.arange(2, W, 5), np.arange(2, H, 5)
+    assert len(pts) == len(xs) * len(ys)                 # every grid point, all from the reference
+    assert np.all(pts[:, 2] == d0) and np.all(pts[:, 3] == 2)
+    assert np.array_equal(pts[:, :2], np.array([(x, y) for y in ys for x in xs]))
+
+
+def test_support_points_fill_the_occluded_part_from_other_views():
+    """A dynamic square in the reference only: no reference point inside it,
+    points transferred from the other views at the plane's level instead."""
+    rng = np.random.default_rng(61)
+    K, H, W, D, d0 = 5, 40, 90, 16, 4
+    b = [-2.0, -1.0, 0.0, 1.0, 2.0]
+    views = _plane_views(K, H, W, b, d0, rng)
+    views[2, 10:30, 30:60] = rng.integers(0, 256, size=(20, 30, 3))
+    S_P = np.ones((K, H, W), np.float32)
+    S_P[2, 10:30, 30:60] = 0.0
+    p = _params(K, H, W, b, D, 100.0, ref=2)
+    pts = O.support_points(p, O.make_support_params(), views, S_P)
+    inside = (pts[:, 1] >= 10) & (pts[:, 1] < 30) & (pts[:, 0] >= 30) & (pts[:, 0] < 60)
+    assert inside.sum() > 20
+    assert np.all(pts[inside, 3] != 2) and np.all(pts[~inside, 3] == 2)
+    assert np.all(pts[:, 2] == d0)
+    # a transferred point came from a grid point of its view: x_a = u - b_a d0
+    xa = pts[inside, 0] - np.array(b)[pts[inside, 3]].astype(int) * d0
+    assert np.all((xa - 2) % 5 == 0)
+    # one point per reference pixel, sorted by (y, u)
+    key = pts[:, 1].astype(np.int64) * W + pts[:, 0]
+    assert np.all(np.diff(key) > 0)
+
+
+def test_support_points_need_texture_uniqueness_and_neighbours():
+    rng = np.random.default_rng(62)
+    K, H, W, D = 3, 30, 60, 12
+    b = [-1.0, 0.0, 1.0]
+    p = _params(K, H, W, b, D, 100.0, ref=1)
+    ones = np.ones((K, H, W), np.float32)
+    flat = np.full((K, H, W, 3), 128, np.uint8)
+    assert len(O.support_points(p, O.make_support_params(), flat, ones)) == 0          # no texture
+    periodic = _plane_views(K, H, W, b, 3, rng, period=4)                               # ambiguous along x
+    assert len(O.support_points(p, O.make_support_params(), periodic, ones)) == 0
+    plane = _plane_views(K, H, W, b, 3, rng)
+    assert len(O.support_points(p, O.make_support_params(), plane, ones)) > 0
+    lonely = O.make_support_params(incon_min=10 ** 6)                                   # nobody agrees
+    assert len(O.support_points(p, lonely, plane, ones)) == 0
+    dynamic = ones.copy()
+    dynamic[1] = 0.0                                                                    # reference all dynamic,
+    dynamic[0] = 0.0                                                                    # and the only other view
+    assert len(O.support_points(p, O.make_support_params(), plane, dynamic)) == 0       # with a neighbour too
+
+
+def test_raster_prior_is_scipy_linear_interpolation():
+    from scipy.interpolate import LinearNDInterpolator
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(63)
+    H, W, D = 50, 70, 40
+    n = 60
+    u = rng.choice(W, n, replace=True)
+    y = rng.choice(H, n, replace=True)
+    uy = np.unique(np.stack([u, y], 1), axis=0)
+    lev = rng.integers(0, D, len(uy))
+    pts = np.zeros((len(uy), 4), np.int32)
+    pts[:, 0], pts[:, 1], pts[:, 2] = uy[:, 0], uy[:, 1], lev
+    p = _params(3, H, W, [-1, 0, 1], D, 100.0, ref=1, d_min=-2.0, d_step=0.5)
+    tri = Delaunay(pts[:, :2].astype(float))
+    mu = O.raster_prior(p, pts, tri.simplices)
+    gy, gx = np.mgrid[0:H, 0:W]
+    dval = -2.0 + 0.5 * pts[:, 2]
+    lin = LinearNDInterpolator(tri, dval)(gx, gy)
+    inside = ~np.isnan(lin)
+    np.testing.assert_allclose(mu[inside], lin[inside], rtol=0, atol=1e-5)
+    d2 = (gx[..., None] - pts[:, 0]) ** 2 + (gy[..., None] - pts[:, 1]) ** 2
+    near = dval[np.argmin(d2, axis=-1)]
+    assert np.array_equal(mu[~inside], near[~inside].astype(np.float32))
+
+
+def test_support_points_rules_in_detail():
+    rng = np.random.default_rng(64)
+    K, H, W, D, d0 = 3, 30, 70, 12, 3
+    b = [-1.0, 0.0, 1.0]
+    p = _params(K, H, W, b, D, 100.0, ref=1)
+    ones = np.ones((K, H, W), np.float32)
+    plane = _plane_views(K, H, W, b, d0, rng)
+    # texture below the threshold: unique matches, but no point
+    faint = (plane // 64 + 126).astype(np.uint8)
+    sp = O.make_support_params(texture_min=10 ** 6)
+    assert len(O.support_points(p, O.make_support_params(texture_min=0), faint, ones)) > 0
+    assert len(O.support_points(p, sp, faint, ones)) == 0
+    # a dynamic grid point is dropped even when the rest of its window is static
+    holes = ones.copy()
+    holes[1, 2::5, 2::5] = 0.0
+    assert len(O.support_points(p, O.make_support_params(), plane, holes)) == 0
+    # smooth noisy texture: the neighbouring levels of the best one are not
+    # its competitors (with them, most of these points would be rejected)
+    from scipy.ndimage import gaussian_filter
+    r2 = np.random.default_rng(65)
+    smooth = gaussian_filter(r2.uniform(0, 255, size=(H, W + 20, 3)), sigma=(0, 4, 0))
+    views = np.zeros((K, H, W, 3), np.uint8)
+    for k in range(K):
+        s = int(b[k] * d0)
+        views[k] = np.clip(smooth[:, 10 + s:10 + s + W] + r2.normal(0, 5.0, (H, W, 3)), 0, 255).astype(np.uint8)
+    pts = O.support_points(p, O.make_support_params(texture_min=0, incon_min=0), views, ones)
+    assert len(pts) >= 45 and np.median(pts[:, 2]) == d0
