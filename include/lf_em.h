@@ -224,6 +224,71 @@ const char *lf_last_error(void);
 /* Frame server: continuous batching of frames from many camera streams.     */
 /* ------------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------------ */
+/* Disparity prior construction (Sec. III-C, disparity prior)                */
+/* ------------------------------------------------------------------------ */
+
+/* Support-point parameters (the paper follows ELAS and states no numbers;
+ * the defaults below are this library's readings). */
+typedef struct {
+    int32_t step;          /* grid spacing of candidate points, pixels (5)         */
+    int32_t radius;        /* matching window (2r+1)^2, r in [0,7] (2)              */
+    int32_t texture_min;   /* min sum of |Gx|+|Gy| over the window (2000)           */
+    int32_t ratio_num, ratio_den; /* unique iff best*den < second*num (85, 100)     */
+    int32_t incon_radius;  /* consistency neighbourhood, pixels (10)                */
+    int32_t incon_levels;  /* max level difference of a consistent neighbour (2)    */
+    int32_t incon_min;     /* min consistent neighbours to keep a point (3)         */
+    int32_t static_min;    /* min static pixels (S_P >= tau_init) in the window (20) */
+} lf_support_params;
+
+/*
+ * lf_build_prior -- build the dense prior disparity mu_T from the views and
+ * S_P (Sec. III-C): support points are matched along the epipolar line over
+ * all levels (sum of absolute differences of the integer Sobel responses of
+ * R+G+B over the window; the views left and right of the matched view are
+ * summed apart and the smaller sum counts), kept when static (the point and
+ * static_min window pixels have S_P >= tau_init), textured and unique (the
+ * second best taken over levels at least 2 away).  Grid points of the
+ * reference are matched against all other views; grid points of every other
+ * view a against its non-reference neighbours a-1, a+1, and moved to the
+ * reference column x + baselines[a] * d where the reference is dynamic
+ * (S_P_ref < tau_init), one per reference pixel (lowest view, then lowest x).
+ * Points with fewer than incon_min neighbours (within incon_radius pixels and
+ * incon_levels levels) are dropped, the rest sorted by (y, u), and the four
+ * image corners added at the level of their nearest point.  mu_T is the
+ * piecewise-linear interpolation of the levels' disparities over a Delaunay
+ * triangulation of the points (the lowest-index triangle holding a pixel,
+ * edges included); with no point, the middle of the level range.
+ *   p      : parameters as lf_em_init; integer baselines and levels only,
+ *            H, W <= 16384; flags LF_INPUTS_ON_DEVICE / LF_OUTPUTS_ON_DEVICE
+ *            place views, S_P / mu_T.
+ *   views  : uint8 [K][H][W][3]; S_P float [K][H][W] in [0,1].
+ *   mu_T   : float [H][W], written.
+ *   points : host int32 [max_points][4] = (u, y, level, view; view -1 for a
+ *            corner) or NULL; n_points (nullable) receives the total count.
+ *   tris   : host int32 [max_tris][3] counter-clockwise point indices or
+ *            NULL; n_tris (nullable) receives the total count.
+ *   hip_stream : stream for the device work (NULL: the null stream).
+ * Allocates and frees temporary device memory; synchronises the stream.
+ * Errors: LF_EINVAL (as lf_em_init, plus fractional geometry, bad support
+ * parameters, frames above 16384), LF_ENOMEM, LF_EDEVICE.
+ */
+/*
+ * lf_triangulate -- the Delaunay triangulation lf_build_prior uses, on the
+ * host: incremental insertion in the given order with exact integer
+ * predicates (a point on a circumcircle does not count as inside; points
+ * already present are skipped).
+ *   xy     : int32 [n][2] points, coordinates in [0, 16383].
+ *   tris   : int32 [max_tris][3] counter-clockwise indices or NULL;
+ *            n_tris (nullable) receives the count.
+ * No device work.  Errors: LF_EINVAL.
+ */
+lf_status lf_triangulate(const int32_t *xy, int32_t n, int32_t *tris, int32_t max_tris, int32_t *n_tris);
+
+lf_status lf_build_prior(const lf_params *p, const lf_support_params *sp, const uint8_t *views, const float *S_P,
+                         float *mu_T, int32_t *points, int32_t max_points, int32_t *n_points, int32_t *tris,
+                         int32_t max_tris, int32_t *n_tris, void *hip_stream);
+
 typedef struct lf_server lf_server;   /* opaque */
 
 /* Called once per submitted frame from the server's service thread, after

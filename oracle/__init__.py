@@ -120,6 +120,8 @@ def lib():
         L.lfo_support_points.argtypes = [P, ctypes.POINTER(SupportParams), u8, fp, i32p, i32]
         L.lfo_support_points.restype = i32
         L.lfo_raster_prior.argtypes = [P, i32p, i32, i32p, i32, fp]
+        L.lfo_prior_corners.argtypes = [P, i32p, i32]
+        L.lfo_prior_corners.restype = i32
         _lib = L
     return _lib
 
@@ -235,6 +237,15 @@ def support_points(p: Params, sp: SupportParams, views, S_P) -> np.ndarray:
     if n < 0:
         raise ValueError("bad support parameters")
     return out[:n].copy()
+
+
+def prior_corners(p: Params, points) -> np.ndarray:
+    """points plus the four image corners (view -1) at the level of the
+    nearest support point, corners already present skipped."""
+    pts = np.zeros((len(points) + 4, 4), np.int32)
+    pts[:len(points)] = points
+    n = lib().lfo_prior_corners(ctypes.byref(p), _ptr(pts, ctypes.c_int32), len(points))
+    return pts[:n].copy()
 
 
 def raster_prior(p: Params, points, tris) -> np.ndarray:

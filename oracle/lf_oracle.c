@@ -833,3 +833,30 @@ void lfo_raster_prior(const lfo_params *p, const int32_t *points, int32_t n, con
             mu_T[(size_t)y * W + x] = (float)mu;
         }
 }
+
+/* The four image corners as extra points (as ELAS does), each with the level
+ * of the nearest support point (squared distance, lowest index on ties), so
+ * that the triangulation covers the whole frame; a corner already holding a
+ * point is not added.  points int32 [n + 4][4] (room for four more); view
+ * = -1 marks a corner.  Returns the new count (n when n == 0). */
+int32_t lfo_prior_corners(const lfo_params *p, int32_t *points, int32_t n)
+{
+    const int cx[4] = {0, p->W - 1, 0, p->W - 1}, cy[4] = {0, 0, p->H - 1, p->H - 1};
+    int32_t m = n;
+    if (n == 0) return 0;
+    for (int c = 0; c < 4; ++c) {
+        int dup = 0;
+        for (int i = 0; i < m; ++i)
+            if (points[4 * i] == cx[c] && points[4 * i + 1] == cy[c]) dup = 1;
+        if (dup) continue;
+        long best = -1;
+        int lev = 0;
+        for (int i = 0; i < n; ++i) {
+            const long dx = points[4 * i] - cx[c], dy = points[4 * i + 1] - cy[c], d2 = dx * dx + dy * dy;
+            if (best < 0 || d2 < best) { best = d2; lev = points[4 * i + 2]; }
+        }
+        int32_t *q = points + 4 * m++;
+        q[0] = cx[c]; q[1] = cy[c]; q[2] = lev; q[3] = -1;
+    }
+    return m;
+}

@@ -14,6 +14,8 @@ import ctypes
 import math
 import os
 
+import numpy as np
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblfem.so")
 
@@ -86,6 +88,7 @@ def lib():
                   "lf_segmentation_maps"):
             getattr(L, f).restype = i32
         _bind_server(L)
+        _bind_prior(L)
         _lib = L
     return _lib
 
@@ -101,6 +104,54 @@ class lf_server_stats_t(ctypes.Structure):
 
 
 lf_done_fn = ctypes.CFUNCTYPE(None, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p)
+
+
+class lf_support_params(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int32), ("radius", ctypes.c_int32), ("texture_min", ctypes.c_int32),
+        ("ratio_num", ctypes.c_int32), ("ratio_den", ctypes.c_int32), ("incon_radius", ctypes.c_int32),
+        ("incon_levels", ctypes.c_int32), ("incon_min", ctypes.c_int32), ("static_min", ctypes.c_int32),
+    ]
+
+
+def make_support_params(step=5, radius=2, texture_min=2000, ratio_num=85, ratio_den=100, incon_radius=10,
+                        incon_levels=2, incon_min=3, static_min=20) -> lf_support_params:
+    sp = lf_support_params()
+    sp.step, sp.radius, sp.texture_min, sp.ratio_num, sp.ratio_den = step, radius, texture_min, ratio_num, ratio_den
+    sp.incon_radius, sp.incon_levels, sp.incon_min, sp.static_min = incon_radius, incon_levels, incon_min, static_min
+    return sp
+
+
+def _bind_prior(L):
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    L.lf_triangulate.argtypes = [vp, i32, vp, i32, i32p]
+    L.lf_triangulate.restype = i32
+    L.lf_build_prior.argtypes = [ctypes.POINTER(lf_params), ctypes.POINTER(lf_support_params), vp, vp, vp, vp, i32,
+                                 i32p, vp, i32, i32p, vp]
+    L.lf_build_prior.restype = i32
+
+
+def lf_triangulate(xy):
+    """Delaunay triangles int32 [T][3] of int32 points [n][2] (host only)."""
+    xy = np.ascontiguousarray(xy, np.int32).reshape(-1, 2)
+    n_t = ctypes.c_int32(0)
+    _check(lib().lf_triangulate(addr(xy), len(xy), None, 0, ctypes.byref(n_t)))
+    tris = np.zeros((max(n_t.value, 1), 3), np.int32)
+    _check(lib().lf_triangulate(addr(xy), len(xy), addr(tris), n_t.value, ctypes.byref(n_t)))
+    return tris[:n_t.value]
+
+
+def lf_build_prior(p, sp, views, S_P, mu_T, max_points=0, max_tris=0, hip_stream=None):
+    """Builds mu_T (written into mu_T); returns (points [n][4], tris [T][3]),
+    each cut to max_points / max_tris rows (0: none returned)."""
+    n_p, n_t = ctypes.c_int32(0), ctypes.c_int32(0)
+    pts = np.zeros((max(max_points, 1), 4), np.int32)
+    tris = np.zeros((max(max_tris, 1), 3), np.int32)
+    _check(lib().lf_build_prior(ctypes.byref(p), ctypes.byref(sp), addr(views), addr(S_P), addr(mu_T),
+                                addr(pts) if max_points else None, max_points, ctypes.byref(n_p),
+                                addr(tris) if max_tris else None, max_tris, ctypes.byref(n_t), hip_stream))
+    return pts[:min(n_p.value, max_points)], tris[:min(n_t.value, max_tris)], n_p.value, n_t.value
 
 
 def _bind_server(L):

@@ -1,0 +1,638 @@
+// Construction of the disparity prior mu_T (Sec. III-C, disparity prior):
+// support points matched along the epipolar line over the full disparity
+// range, those on dynamic objects dropped, support points of the other views
+// transferred into the part of the reference occluded by dynamic objects,
+// duplicates and inconsistent points removed, and mu_T interpolated
+// piecewise-linearly over a Delaunay triangulation of the points.
+//
+// Device: integer Sobel responses, the matching of every grid point of every
+// pass (one lane per point, all levels), and the raster of the triangulation.
+// Host (native C++): assembling, filtering and sorting the points, and the
+// triangulation (incremental Delaunay with exact integer predicates).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "lf_em.h"
+#include "lf_internal.h"
+
+namespace lfem {
+
+#define LF_HIP(call, what)                                 \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_error(e_, what);  \
+    } while (0)
+
+__device__ __forceinline__ int pclamp(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+// Integer Sobel responses (Gx, Gy) of L = R+G+B, replicated border.
+// grid (ceil(W/256), H, K); g is [K][H][W].
+__global__ __launch_bounds__(256) void lf_sobel_i16_kernel(const uint8_t *__restrict__ views, short2 *__restrict__ g,
+                                                           int H, int W) {
+    const int k = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= W) return;
+    const uint8_t *v = views + (size_t)k * H * W * 3;
+    int L[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int yy = pclamp(y + r - 1, 0, H - 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const uint8_t *px = v + ((size_t)yy * W + pclamp(x + c - 1, 0, W - 1)) * 3;
+            L[r][c] = (int)px[0] + (int)px[1] + (int)px[2];
+        }
+    }
+    const int gx = (L[0][2] - L[0][0]) + 2 * (L[1][2] - L[1][0]) + (L[2][2] - L[2][0]);
+    const int gy = (L[2][0] - L[0][0]) + 2 * (L[2][1] - L[0][1]) + (L[2][2] - L[0][2]);
+    g[((size_t)k * H + y) * W + x] = make_short2((short)gx, (short)gy);
+}
+
+// One matching pass: grid points of view a against the views vs[].
+struct MatchArgs {
+    const short2 *g;     // [K][H][W]
+    const float *S_P;    // [K][H][W]
+    int32_t *level;      // [ny][nx] level of the unique best match, or -1
+    int H, W, D, a, n_vs, nx, ny;
+    int step, radius, texture_min, ratio_num, ratio_den, static_min;
+    int dmin_i, dstep_i;
+    float tau;
+    int vs[LF_MAX_VIEWS];
+    int db[LF_MAX_VIEWS];     // integer baseline of vs[i] minus that of a
+    int side[LF_MAX_VIEWS];   // 1 when vs[i] lies right of a (larger baseline)
+    int two_sides;            // views on both sides: the cost is the smaller side sum
+};
+
+// grid (ceil(nx*ny/128)), block 128; one lane per grid point.
+__global__ __launch_bounds__(128) void lf_support_match_kernel(MatchArgs m) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.nx * m.ny) return;
+    const int ix = i % m.nx, iy = i / m.nx;
+    const int x = m.step / 2 + ix * m.step, y = m.step / 2 + iy * m.step;
+    const int H = m.H, W = m.W, r = m.radius;
+    const size_t HW = (size_t)H * W;
+    int j_out = -1;
+    // static point with enough static pixels in its window
+    const float *sp = m.S_P + (size_t)m.a * HW;
+    bool ok = sp[(size_t)y * W + x] >= m.tau;
+    if (ok) {
+        int n_static = 0;
+        for (int dy = -r; dy <= r; ++dy)
+            for (int dx = -r; dx <= r; ++dx)
+                n_static += sp[(size_t)pclamp(y + dy, 0, H - 1) * W + pclamp(x + dx, 0, W - 1)] >= m.tau;
+        ok = n_static >= m.static_min;
+    }
+    const short2 *ga = m.g + (size_t)m.a * HW;
+    if (ok) {
+        long texture = 0;
+        for (int dy = -r; dy <= r; ++dy)
+            for (int dx = -r; dx <= r; ++dx) {
+                const short2 v = ga[(size_t)pclamp(y + dy, 0, H - 1) * W + pclamp(x + dx, 0, W - 1)];
+                texture += abs((int)v.x) + abs((int)v.y);
+            }
+        ok = texture >= m.texture_min;
+    }
+    if (ok) {
+        // the four lowest (cost, level) pairs in lexicographic order: the
+        // best, at most two levels next to it, and the best level further away
+        long tc[4] = {LONG_MAX, LONG_MAX, LONG_MAX, LONG_MAX};
+        int tj[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+        for (int j = 0; j < m.D; ++j) {
+            const int d = m.dmin_i + j * m.dstep_i;
+            long s[2] = {0, 0};
+            for (int t = 0; t < m.n_vs; ++t) {
+                const short2 *gv = m.g + (size_t)m.vs[t] * HW;
+                const int shift = m.db[t] * d;
+                long c = 0;
+                for (int dy = -r; dy <= r; ++dy) {
+                    const size_t row = (size_t)pclamp(y + dy, 0, H - 1) * W;
+                    for (int dx = -r; dx <= r; ++dx) {
+                        const short2 A = ga[row + pclamp(x + dx, 0, W - 1)];
+                        const short2 B = gv[row + pclamp(x + dx - shift, 0, W - 1)];
+                        c += abs((int)A.x - (int)B.x) + abs((int)A.y - (int)B.y);
+                    }
+                }
+                s[m.side[t]] += c;
+            }
+            const long cost = m.two_sides ? min(s[0], s[1]) : s[0] + s[1];
+            // insert (cost, j); j increases, so a tie in cost keeps the earlier level first
+            int pos = 4;
+            while (pos > 0 && cost < tc[pos - 1]) --pos;
+            if (pos < 4) {
+                for (int q = 3; q > pos; --q) {
+                    tc[q] = tc[q - 1];
+                    tj[q] = tj[q - 1];
+                }
+                tc[pos] = cost;
+                tj[pos] = j;
+            }
+        }
+        const int best = tj[0];
+        long second = -1;
+        for (int q = 1; q < 4; ++q)
+            if (tj[q] != INT_MAX && abs(tj[q] - best) >= 2) {
+                second = tc[q];
+                break;
+            }
+        const bool unique = second >= 0 ? tc[0] * m.ratio_den < second * m.ratio_num : true;
+        if (unique) j_out = best;
+    }
+    m.level[i] = j_out;
+}
+
+// Raster of the triangulation: the lowest-index triangle containing each
+// pixel (edges included), found with an atomic min so the result does not
+// depend on the order of arrival.  grid (n_tri), block 256.
+__global__ __launch_bounds__(256) void lf_prior_cover_kernel(const int4 *__restrict__ pts, const int3 *__restrict__ tris,
+                                                             int n_tri, int32_t *__restrict__ owner, int H, int W) {
+    const int t = blockIdx.x;
+    if (t >= n_tri) return;
+    const int3 tr = tris[t];
+    const int4 a = pts[tr.x], b = pts[tr.y], c = pts[tr.z];
+    const long A = (long)(b.x - a.x) * (c.y - a.y) - (long)(b.y - a.y) * (c.x - a.x);
+    if (A == 0) return;
+    const int x0 = max(min(a.x, min(b.x, c.x)), 0), x1 = min(max(a.x, max(b.x, c.x)), W - 1);
+    const int y0 = max(min(a.y, min(b.y, c.y)), 0), y1 = min(max(a.y, max(b.y, c.y)), H - 1);
+    const int bw = x1 - x0 + 1;
+    const long n = (long)bw * (y1 - y0 + 1);
+    for (long i = threadIdx.x; i < n; i += blockDim.x) {
+        const int x = x0 + (int)(i % bw), y = y0 + (int)(i / bw);
+        const long wa = (long)(b.x - x) * (c.y - y) - (long)(b.y - y) * (c.x - x);
+        const long wb = (long)(c.x - x) * (a.y - y) - (long)(c.y - y) * (a.x - x);
+        const long wc = (long)(a.x - x) * (b.y - y) - (long)(a.y - y) * (b.x - x);
+        const bool inside = A > 0 ? (wa >= 0 && wb >= 0 && wc >= 0) : (wa <= 0 && wb <= 0 && wc <= 0);
+        if (inside) atomicMin(&owner[(size_t)y * W + x], t);
+    }
+}
+
+// mu_T of every pixel: barycentric interpolation in its triangle, in double
+// with the interpolation written out in a fixed order (no contraction), or
+// the level of the nearest point when no triangle covers it.  grid
+// (ceil(W/256), H).
+__global__ __launch_bounds__(256) void lf_prior_interp_kernel(const int4 *__restrict__ pts, int n_pts,
+                                                              const int3 *__restrict__ tris,
+                                                              const int32_t *__restrict__ owner, float *__restrict__ mu,
+                                                              int H, int W, int D, double d_min, double d_step) {
+#pragma clang fp contract(off)
+    const int y = blockIdx.y;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= W) return;
+    const int t = owner[(size_t)y * W + x];
+    double v;
+    if (t != INT_MAX) {
+        const int3 tr = tris[t];
+        const int4 a = pts[tr.x], b = pts[tr.y], c = pts[tr.z];
+        const long A = (long)(b.x - a.x) * (c.y - a.y) - (long)(b.y - a.y) * (c.x - a.x);
+        const long wa = (long)(b.x - x) * (c.y - y) - (long)(b.y - y) * (c.x - x);
+        const long wb = (long)(c.x - x) * (a.y - y) - (long)(c.y - y) * (a.x - x);
+        const long wc = (long)(a.x - x) * (b.y - y) - (long)(a.y - y) * (b.x - x);
+        const double da = d_min + a.z * d_step, db = d_min + b.z * d_step, dc = d_min + c.z * d_step;
+        const double s1 = (double)wa * da;
+        const double s2 = (double)wb * db;
+        const double s3 = (double)wc * dc;
+        v = ((s1 + s2) + s3) / (double)A;
+    } else if (n_pts == 0) {
+        v = d_min + 0.5 * (D - 1) * d_step;
+    } else {
+        long best = -1;
+        int lev = 0;
+        for (int i = 0; i < n_pts; ++i) {
+            const long dx = pts[i].x - x, dy = pts[i].y - y, d2 = dx * dx + dy * dy;
+            if (best < 0 || d2 < best) {
+                best = d2;
+                lev = pts[i].z;
+            }
+        }
+        v = d_min + lev * d_step;
+    }
+    mu[(size_t)y * W + x] = (float)v;
+}
+
+__global__ __launch_bounds__(256) void lf_prior_fill_kernel(int32_t *p, size_t n, int32_t v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Delaunay triangulation (incremental, Bowyer-Watson) with exact predicates on
+// integer coordinates.  Three far vertices enclose the frame; triangles that
+// use them are dropped at the end.  For frames up to 16384 pixels on a side
+// the far vertices are far enough that every edge of the convex hull of the
+// points is an edge of the result.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct P2 {
+    long x, y;
+};
+
+inline long orient(const P2 &a, const P2 &b, const P2 &c) {
+    return (b.x - a.x) * (c.y - a.y) - (b.y - a.y) * (c.x - a.x);
+}
+
+// > 0 when d lies strictly inside the circle through a, b, c (counter-clockwise)
+inline int incircle(const P2 &a, const P2 &b, const P2 &c, const P2 &d) {
+    const __int128 adx = a.x - d.x, ady = a.y - d.y, bdx = b.x - d.x, bdy = b.y - d.y, cdx = c.x - d.x,
+                   cdy = c.y - d.y;
+    const __int128 det = (adx * adx + ady * ady) * (bdx * cdy - bdy * cdx) -
+                         (bdx * bdx + bdy * bdy) * (adx * cdy - ady * cdx) +
+                         (cdx * cdx + cdy * cdy) * (adx * bdy - ady * bdx);
+    return det > 0 ? 1 : (det < 0 ? -1 : 0);
+}
+
+struct Tri {
+    int v[3];   // counter-clockwise
+    int n[3];   // neighbour across the edge opposite v[i], -1 outside
+    bool alive;
+};
+
+class Delaunay {
+  public:
+    std::vector<P2> P;
+    std::vector<Tri> T;
+    int n_real = 0;
+
+    void run(const std::vector<P2> &pts) {
+        n_real = (int)pts.size();
+        P = pts;
+        const long L = 1L << 26;
+        P.push_back({-L, -L});
+        P.push_back({3 * L, -L});
+        P.push_back({-L, 3 * L});
+        T.clear();
+        T.push_back({{n_real, n_real + 1, n_real + 2}, {-1, -1, -1}, true});
+        int last = 0;
+        std::vector<int> bad, stack;
+        std::vector<char> mark;
+        for (int i = 0; i < n_real; ++i) {
+            const int t0 = locate(P[i], last);
+            if (t0 < 0) continue;   // a duplicate point
+            // cavity: triangles whose circumcircle strictly holds the point
+            bad.clear();
+            stack.assign(1, t0);
+            mark.resize(T.size(), 0);
+            mark[t0] = 1;
+            while (!stack.empty()) {
+                const int t = stack.back();
+                stack.pop_back();
+                bad.push_back(t);
+                for (int e = 0; e < 3; ++e) {
+                    const int nb = T[t].n[e];
+                    if (nb < 0 || mark[nb]) continue;
+                    const Tri &u = T[nb];
+                    if (incircle(P[u.v[0]], P[u.v[1]], P[u.v[2]], P[i]) > 0) {
+                        mark[nb] = 1;
+                        stack.push_back(nb);
+                    }
+                }
+            }
+            // boundary edges of the cavity, each with its outer neighbour
+            struct Edge {
+                int a, b, outer;
+            };
+            std::vector<Edge> edges;
+            for (int t : bad)
+                for (int e = 0; e < 3; ++e) {
+                    const int nb = T[t].n[e];
+                    if (nb >= 0 && mark[nb]) continue;
+                    edges.push_back({T[t].v[(e + 1) % 3], T[t].v[(e + 2) % 3], nb});
+                }
+            for (int t : bad) {
+                T[t].alive = false;
+                mark[t] = 0;
+            }
+            // fan of new triangles (a, b, i); each edge a->b is counter-clockwise
+            // seen from inside the cavity, so (a, b, i) is counter-clockwise
+            const int base = (int)T.size();
+            for (size_t k = 0; k < edges.size(); ++k) {
+                const Edge &E = edges[k];
+                T.push_back({{E.a, E.b, i}, {-1, -1, E.outer}, true});
+                if (E.outer >= 0)
+                    for (int e = 0; e < 3; ++e) {
+                        Tri &o = T[E.outer];
+                        if (o.v[(e + 1) % 3] == E.b && o.v[(e + 2) % 3] == E.a) o.n[e] = base + (int)k;
+                    }
+            }
+            // link the fan: triangle (a, b, i) meets (b, c, i) across edge b-i
+            // (opposite a) and (z, a, i) across edge i-a (opposite b)
+            std::vector<std::pair<int, int>> by_a(edges.size()), by_b(edges.size());
+            for (size_t k = 0; k < edges.size(); ++k) {
+                by_a[k] = {edges[k].a, base + (int)k};
+                by_b[k] = {edges[k].b, base + (int)k};
+            }
+            std::sort(by_a.begin(), by_a.end());
+            for (size_t k = 0; k < edges.size(); ++k) {
+                Tri &t = T[base + (int)k];
+                auto it = std::lower_bound(by_a.begin(), by_a.end(), std::make_pair(t.v[1], INT_MIN));
+                if (it != by_a.end() && it->first == t.v[1]) {
+                    t.n[0] = it->second;              // the triangle starting at b
+                    T[it->second].n[1] = base + (int)k;   // it meets this one across i-b
+                }
+            }
+            last = base;
+            mark.resize(T.size(), 0);
+        }
+    }
+
+    // triangles of real points only, counter-clockwise
+    std::vector<int> triangles() const {
+        std::vector<int> out;
+        for (const Tri &t : T)
+            if (t.alive && t.v[0] < n_real && t.v[1] < n_real && t.v[2] < n_real) {
+                out.push_back(t.v[0]);
+                out.push_back(t.v[1]);
+                out.push_back(t.v[2]);
+            }
+        return out;
+    }
+
+  private:
+    // a live triangle holding p (edges included), walking from `start`; -1
+    // when p is already a vertex
+    int locate(const P2 &p, int start) {
+        int t = start;
+        if (!T[t].alive) t = last_alive();
+        for (size_t steps = 0; steps < 4 * T.size() + 16; ++steps) {
+            const Tri &u = T[t];
+            int next = -1;
+            for (int e = 0; e < 3 && next < 0; ++e) {
+                const P2 &a = P[u.v[(e + 1) % 3]], &b = P[u.v[(e + 2) % 3]];
+                if (orient(a, b, p) < 0) next = u.n[e];
+            }
+            if (next < 0) return is_vertex(u, p) ? -1 : t;
+            t = next;
+        }
+        // the walk did not settle: search every live triangle
+        for (size_t k = 0; k < T.size(); ++k) {
+            const Tri &u = T[k];
+            if (!u.alive) continue;
+            if (orient(P[u.v[0]], P[u.v[1]], p) >= 0 && orient(P[u.v[1]], P[u.v[2]], p) >= 0 &&
+                orient(P[u.v[2]], P[u.v[0]], p) >= 0)
+                return is_vertex(u, p) ? -1 : (int)k;
+        }
+        return -1;
+    }
+    bool is_vertex(const Tri &u, const P2 &p) const {
+        for (int e = 0; e < 3; ++e)
+            if (P[u.v[e]].x == p.x && P[u.v[e]].y == p.y) return true;
+        return false;
+    }
+    int last_alive() const {
+        for (int k = (int)T.size() - 1; k >= 0; --k)
+            if (T[k].alive) return k;
+        return 0;
+    }
+};
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+}  // namespace lfem
+
+using namespace lfem;
+
+extern "C" lf_status lf_triangulate(const int32_t *xy, int32_t n, int32_t *tris, int32_t max_tris, int32_t *n_tris) {
+    if (n < 0 || (n > 0 && !xy) || max_tris < 0) return set_error(LF_EINVAL, "bad arguments");
+    for (int32_t i = 0; i < n; ++i)
+        if (xy[2 * i] < 0 || xy[2 * i] > 16383 || xy[2 * i + 1] < 0 || xy[2 * i + 1] > 16383)
+            return set_error(LF_EINVAL, "point %d outside [0, 16383]^2", i);
+    std::vector<P2> pp(n);
+    for (int32_t i = 0; i < n; ++i) pp[i] = {xy[2 * i], xy[2 * i + 1]};
+    Delaunay dt;
+    dt.run(pp);
+    const std::vector<int> tv = dt.triangles();
+    const int n_tri = (int)(tv.size() / 3);
+    if (n_tris) *n_tris = n_tri;
+    if (tris)
+        for (int t = 0; t < std::min(n_tri, max_tris); ++t)
+            for (int e = 0; e < 3; ++e) tris[3 * t + e] = tv[3 * t + e];
+    return LF_OK;
+}
+
+extern "C" lf_status lf_build_prior(const lf_params *p, const lf_support_params *sp, const uint8_t *views,
+                                    const float *S_P, float *mu_T, int32_t *points, int32_t max_points,
+                                    int32_t *n_points, int32_t *tris, int32_t max_tris, int32_t *n_tris,
+                                    void *hip_stream) {
+    if (!p || !sp) return set_error(LF_EINVAL, "params and support params are required");
+    lf_status st = validate_params(p);
+    if (st != LF_OK) return st;
+    if (!views || !S_P || !mu_T) return set_error(LF_EINVAL, "views, S_P and mu_T are required");
+    if (p->W > 16384 || p->H > 16384) return set_error(LF_EINVAL, "the prior is built for frames up to 16384 pixels");
+    if (sp->step < 1 || sp->radius < 0 || sp->radius > 7 || sp->ratio_den <= 0 || sp->ratio_num < 0 ||
+        sp->incon_radius < 0 || sp->incon_levels < 0 || sp->texture_min < 0)
+        return set_error(LF_EINVAL, "support params out of range");
+    const Geometry g = make_geometry(p);
+    if (g.frac) return set_error(LF_EINVAL, "the prior is built for integer baselines and levels only");
+    const bool dev_in = p->flags & LF_INPUTS_ON_DEVICE;
+    const bool dev_out = p->flags & LF_OUTPUTS_ON_DEVICE;
+    const int K = p->K, H = p->H, W = p->W;
+    const size_t HW = (size_t)H * W, KHW = HW * K;
+    if (!dev_in) {
+        for (size_t i = 0; i < KHW; ++i)
+            if (!(S_P[i] >= 0.0f && S_P[i] <= 1.0f)) return set_error(LF_EINVAL, "S_P[%zu] outside [0,1]", i);
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int step = sp->step;
+    const int nx = (W - step / 2 + step - 1) / step, ny = (H - step / 2 + step - 1) / step;
+    const size_t n_grid = (size_t)std::max(nx, 0) * std::max(ny, 0);
+
+    // device buffers: inputs (when on the host), Sobel responses, levels
+    DevBuf b_views, b_sp, b_g, b_lev;
+    const uint8_t *d_views = views;
+    const float *d_sp = S_P;
+    if (!dev_in) {
+        LF_HIP(hipMalloc(&b_views.p, KHW * 3), "allocation");
+        LF_HIP(hipMalloc(&b_sp.p, KHW * 4), "allocation");
+        LF_HIP(hipMemcpyAsync(b_views.p, views, KHW * 3, hipMemcpyHostToDevice, s), "copy");
+        LF_HIP(hipMemcpyAsync(b_sp.p, S_P, KHW * 4, hipMemcpyHostToDevice, s), "copy");
+        d_views = (const uint8_t *)b_views.p;
+        d_sp = (const float *)b_sp.p;
+    }
+    LF_HIP(hipMalloc(&b_g.p, KHW * sizeof(short2)), "allocation");
+    LF_HIP(hipMalloc(&b_lev.p, std::max<size_t>(n_grid, 1) * K * 4), "allocation");
+    hipLaunchKernelGGL(lf_sobel_i16_kernel, dim3((W + 255) / 256, H, K), dim3(256), 0, s, d_views, (short2 *)b_g.p, H,
+                       W);
+    LF_HIP(hipGetLastError(), "sobel launch");
+
+    // passes: the reference against every other view, then each other view
+    // against its non-reference neighbours
+    std::vector<int> pass_view;
+    for (int a = -1; a < K; ++a) {
+        const int va = a < 0 ? p->ref : a;
+        if (a >= 0 && a == p->ref) continue;
+        MatchArgs m{};
+        m.g = (const short2 *)b_g.p;
+        m.S_P = d_sp;
+        m.level = (int32_t *)b_lev.p + pass_view.size() * n_grid;
+        m.H = H;
+        m.W = W;
+        m.D = p->D;
+        m.a = va;
+        m.nx = nx;
+        m.ny = ny;
+        m.step = step;
+        m.radius = sp->radius;
+        m.texture_min = sp->texture_min;
+        m.ratio_num = sp->ratio_num;
+        m.ratio_den = sp->ratio_den;
+        m.static_min = sp->static_min;
+        m.dmin_i = g.dmin_i;
+        m.dstep_i = g.dstep_i;
+        m.tau = p->tau_init;
+        if (a < 0) {
+            for (int k = 0; k < K; ++k)
+                if (k != p->ref) m.vs[m.n_vs++] = k;
+        } else {
+            if (a - 1 >= 0 && a - 1 != p->ref) m.vs[m.n_vs++] = a - 1;
+            if (a + 1 < K && a + 1 != p->ref) m.vs[m.n_vs++] = a + 1;
+            if (m.n_vs == 0) continue;
+        }
+        int used[2] = {0, 0};
+        for (int t = 0; t < m.n_vs; ++t) {
+            m.db[t] = g.bi[m.vs[t]] - g.bi[va];
+            m.side[t] = p->baselines[m.vs[t]] > p->baselines[va] ? 1 : 0;
+            used[m.side[t]] = 1;
+        }
+        m.two_sides = used[0] && used[1];
+        pass_view.push_back(va);
+        if (n_grid > 0) {
+            hipLaunchKernelGGL(lf_support_match_kernel, dim3((unsigned)((n_grid + 127) / 128)), dim3(128), 0, s, m);
+            LF_HIP(hipGetLastError(), "support match launch");
+        }
+    }
+    std::vector<int32_t> lev(pass_view.size() * n_grid);
+    std::vector<float> sp_ref(HW);
+    if (!lev.empty())
+        LF_HIP(hipMemcpyAsync(lev.data(), b_lev.p, lev.size() * 4, hipMemcpyDeviceToHost, s), "copy");
+    LF_HIP(hipMemcpyAsync(sp_ref.data(), d_sp + (size_t)p->ref * HW, HW * 4, hipMemcpyDeviceToHost, s), "copy");
+    LF_HIP(hipStreamSynchronize(s), "synchronize");
+
+    // candidates: reference points, then transferred points (lowest view,
+    // then grid order, wins a reference pixel)
+    std::vector<int4> cand;
+    std::vector<char> taken(HW, 0);
+    const float tau = p->tau_init;
+    for (size_t ps = 0; ps < pass_view.size(); ++ps) {
+        const int a = pass_view[ps];
+        for (int iy = 0; iy < ny; ++iy)
+            for (int ix = 0; ix < nx; ++ix) {
+                const int j = lev[ps * n_grid + (size_t)iy * nx + ix];
+                if (j < 0) continue;
+                const int x = step / 2 + ix * step, y = step / 2 + iy * step;
+                if (ps == 0) {
+                    cand.push_back(make_int4(x, y, j, a));
+                    continue;
+                }
+                const int u = x + g.bi[a] * (g.dmin_i + j * g.dstep_i);
+                if (u < 0 || u >= W) continue;
+                if (!(sp_ref[(size_t)y * W + u] < tau)) continue;
+                if (taken[(size_t)y * W + u]) continue;
+                taken[(size_t)y * W + u] = 1;
+                cand.push_back(make_int4(u, y, j, a));
+            }
+    }
+    // consistency: enough neighbours within the radius with close levels
+    // (bins of the radius' size; the 3x3 bins around a point hold them all)
+    const int R = sp->incon_radius, bs = std::max(R, 1);
+    const int bx = W / bs + 1, by = H / bs + 1;
+    std::vector<std::vector<int>> bins((size_t)bx * by);
+    for (size_t i = 0; i < cand.size(); ++i) bins[(size_t)(cand[i].y / bs) * bx + cand[i].x / bs].push_back((int)i);
+    std::vector<int4> pts;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        const int4 c = cand[i];
+        int cnt = 0;
+        for (int yy = c.y / bs - 1; yy <= c.y / bs + 1; ++yy)
+            for (int xx = c.x / bs - 1; xx <= c.x / bs + 1; ++xx) {
+                if (yy < 0 || yy >= by || xx < 0 || xx >= bx) continue;
+                for (int o : bins[(size_t)yy * bx + xx]) {
+                    if (o == (int)i) continue;
+                    const int4 d = cand[o];
+                    if (std::abs(d.x - c.x) <= R && std::abs(d.y - c.y) <= R && std::abs(d.z - c.z) <= sp->incon_levels)
+                        ++cnt;
+                }
+            }
+        if (cnt >= sp->incon_min) pts.push_back(c);
+    }
+    std::sort(pts.begin(), pts.end(), [](const int4 &a, const int4 &b) { return a.y != b.y ? a.y < b.y : a.x < b.x; });
+    // the image corners at the level of the nearest point
+    if (!pts.empty()) {
+        const size_t n0 = pts.size();
+        const int cx[4] = {0, W - 1, 0, W - 1}, cy[4] = {0, 0, H - 1, H - 1};
+        for (int c = 0; c < 4; ++c) {
+            bool dup = false;
+            for (const int4 &q : pts) dup |= (q.x == cx[c] && q.y == cy[c]);
+            if (dup) continue;
+            long best = -1;
+            int lv = 0;
+            for (size_t i = 0; i < n0; ++i) {
+                const long dx = pts[i].x - cx[c], dy = pts[i].y - cy[c], d2 = dx * dx + dy * dy;
+                if (best < 0 || d2 < best) {
+                    best = d2;
+                    lv = pts[i].z;
+                }
+            }
+            pts.push_back(make_int4(cx[c], cy[c], lv, -1));
+        }
+    }
+    // triangulation
+    std::vector<P2> pp(pts.size());
+    for (size_t i = 0; i < pts.size(); ++i) pp[i] = {pts[i].x, pts[i].y};
+    Delaunay dt;
+    dt.run(pp);
+    const std::vector<int> tv = dt.triangles();
+    const int n_tri = (int)(tv.size() / 3);
+
+    // raster on the device
+    DevBuf b_pts, b_tri, b_owner, b_mu;
+    const int n_pts = (int)pts.size();
+    LF_HIP(hipMalloc(&b_pts.p, std::max(n_pts, 1) * sizeof(int4)), "allocation");
+    LF_HIP(hipMalloc(&b_tri.p, std::max(n_tri, 1) * sizeof(int3)), "allocation");
+    LF_HIP(hipMalloc(&b_owner.p, HW * 4), "allocation");
+    float *d_mu = mu_T;
+    if (!dev_out) {
+        LF_HIP(hipMalloc(&b_mu.p, HW * 4), "allocation");
+        d_mu = (float *)b_mu.p;
+    }
+    std::vector<int3> t3(n_tri);
+    for (int t = 0; t < n_tri; ++t) t3[t] = make_int3(tv[3 * t], tv[3 * t + 1], tv[3 * t + 2]);
+    if (n_pts) LF_HIP(hipMemcpyAsync(b_pts.p, pts.data(), n_pts * sizeof(int4), hipMemcpyHostToDevice, s), "copy");
+    if (n_tri) LF_HIP(hipMemcpyAsync(b_tri.p, t3.data(), n_tri * sizeof(int3), hipMemcpyHostToDevice, s), "copy");
+    hipLaunchKernelGGL(lf_prior_fill_kernel, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s, (int32_t *)b_owner.p,
+                       HW, INT_MAX);
+    LF_HIP(hipGetLastError(), "fill launch");
+    if (n_tri) {
+        hipLaunchKernelGGL(lf_prior_cover_kernel, dim3(n_tri), dim3(256), 0, s, (const int4 *)b_pts.p,
+                           (const int3 *)b_tri.p, n_tri, (int32_t *)b_owner.p, H, W);
+        LF_HIP(hipGetLastError(), "cover launch");
+    }
+    hipLaunchKernelGGL(lf_prior_interp_kernel, dim3((W + 255) / 256, H), dim3(256), 0, s, (const int4 *)b_pts.p, n_pts,
+                       (const int3 *)b_tri.p, (const int32_t *)b_owner.p, d_mu, H, W, p->D, (double)p->d_min,
+                       (double)p->d_step);
+    LF_HIP(hipGetLastError(), "interpolation launch");
+    if (!dev_out) LF_HIP(hipMemcpyAsync(mu_T, d_mu, HW * 4, hipMemcpyDeviceToHost, s), "copy");
+    LF_HIP(hipStreamSynchronize(s), "synchronize");
+    if (n_points) *n_points = n_pts;
+    if (n_tris) *n_tris = n_tri;
+    if (points)
+        for (int i = 0; i < std::min(n_pts, max_points); ++i) {
+            points[4 * i] = pts[i].x;
+            points[4 * i + 1] = pts[i].y;
+            points[4 * i + 2] = pts[i].z;
+            points[4 * i + 3] = pts[i].w;
+        }
+    if (tris)
+        for (int t = 0; t < std::min(n_tri, max_tris); ++t)
+            for (int e = 0; e < 3; ++e) tris[3 * t + e] = tv[3 * t + e];
+    return LF_OK;
+}

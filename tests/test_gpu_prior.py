@@ -1,0 +1,73 @@
+"""Construction of the disparity prior on the GPU (lf_build_prior, Sec. III-C)
+against the oracle: the support points (integer work: exact), the corners,
+a valid Delaunay triangulation of them (several are correct where points are
+cocircular, so the GPU's own is checked by definition), and mu_T against the
+oracle's raster of that triangulation."""
+import sys
+
+import numpy as np
+import pytest
+
+import lf_scenes as S
+import oracle as O
+from lfcase import f32
+from test_triangulation import _check_delaunay, _hull
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _run(spec, fr, check_all_circles):
+    import torch
+    import paper_2003_11076_amd as LF
+    K, H, W = spec.K, spec.H, spec.W
+    p = LF.make_params(K, H, W, spec.ref, spec.baselines, spec.d_min, spec.d_step, spec.D, fr.beta,
+                       tau_init=spec.tau)
+    sp = LF.make_support_params()
+    mu = np.zeros((H, W), np.float32)
+    cap_p, cap_t = ((W // 5 + 1) * (H // 5 + 1) * K + 8), 4 * (W // 5 + 1) * (H // 5 + 1) * K + 16
+    pts, tris, n_p, n_t = LF.lf_build_prior(p, sp, fr.views, fr.S_P, mu, cap_p, cap_t,
+                                            hip_stream=torch.cuda.current_stream().cuda_stream)
+    assert len(pts) == n_p and len(tris) == n_t
+    op = O.make_params(K, H, W, spec.ref, [f32(b) for b in spec.baselines], f32(spec.d_min), f32(spec.d_step),
+                       spec.D, f32(fr.beta), tau=f32(spec.tau))
+    ref = O.prior_corners(op, O.support_points(op, O.make_support_params(), fr.views, fr.S_P))
+    assert np.array_equal(pts, ref)
+    if check_all_circles:
+        _check_delaunay(pts[:, :2], tris)
+    else:
+        _, h, area2 = _hull(pts[:, :2].tolist())
+        assert n_t == 2 * len(pts) - h - 2
+        a, b, c = pts[tris[:, 0], :2].astype(np.int64), pts[tris[:, 1], :2].astype(np.int64), pts[tris[:, 2], :2].astype(np.int64)
+        o = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0])
+        assert np.all(o > 0) and o.sum() == area2
+    mu_o = O.raster_prior(op, pts, tris)
+    assert np.array_equal(mu, mu_o)
+    return pts, mu
+
+
+def test_prior_config1():
+    fr = S.make_frame(S.config_spec(1))
+    _say("build prior config1 160x120 K=5 D=32")
+    pts, mu = _run(fr.spec, fr, True)
+    assert np.abs(mu - fr.disp_bg).max() == 0.0          # one plane: recovered exactly
+
+
+def test_prior_config2():
+    fr = S.make_frame(S.config_spec(2))
+    _say("build prior config2 640x480 K=5 D=64")
+    pts, mu = _run(fr.spec, fr, False)
+    err = np.abs(mu - fr.disp_bg)
+    assert np.percentile(err, 50) < 1.0                  # sanity against the scene's truth
+
+
+def test_prior_small_asymmetric():
+    spec = S.config_spec(1, H=60, W=100, baselines=(0.0, 1.0, 2.0, 3.0, 4.0), ref=0, dyn_kind="ellipse",
+                         dyn_cover=(0.05, 0.4))
+    fr = S.make_frame(spec)
+    _say("build prior 100x60 K=5 reference at the end of the array")
+    _run(spec, fr, True)

@@ -792,3 +792,13 @@ def test_support_points_rules_in_detail():
         views[k] = np.clip(smooth[:, 10 + s:10 + s + W] + r2.normal(0, 5.0, (H, W, 3)), 0, 255).astype(np.uint8)
     pts = O.support_points(p, O.make_support_params(texture_min=0, incon_min=0), views, ones)
     assert len(pts) >= 45 and np.median(pts[:, 2]) == d0
+
+
+def test_prior_corners_take_the_nearest_level():
+    p = _params(3, 20, 30, [-1, 0, 1], 10, 100.0, ref=1)
+    pts = np.array([[5, 5, 3, 1], [20, 10, 7, 0]], np.int32)
+    out = O.prior_corners(p, pts)
+    assert out.tolist()[2:] == [[0, 0, 3, -1], [29, 0, 7, -1], [0, 19, 3, -1], [29, 19, 7, -1]]
+    pts = np.array([[0, 0, 4, 1], [20, 10, 7, 0]], np.int32)        # a point on a corner already
+    assert len(O.prior_corners(p, pts)) == 5
+    assert len(O.prior_corners(p, np.zeros((0, 4), np.int32))) == 0
