@@ -32,6 +32,30 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector (256 CU x 2.4 GHz x 256 flop/clk)
 PEAK_HBM_GBS = 8000.0
 F_DESC = 2
+ROOT = os.path.dirname(os.path.abspath(__file__))
+# sources of the EM kernel: HBM traffic measured with rocprofv3 counters is
+# reported only while these are unchanged since the measurement
+EM_SOURCES = ("paper_2003_11076_amd/csrc/lf_em_kernels.h", "paper_2003_11076_amd/csrc/lf_em_f32.hip",
+              "paper_2003_11076_amd/csrc/lf_em_dispatch.h")
+
+
+def measured_traffic(workload):
+    """HBM bytes per EM launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of this workload (scaled by a plain copy's counters),
+    or None when there is none or the kernel changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"lf_em_kernel_{workload}.traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in EM_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest()[:16] != rec.get("src_hash"):
+        return None
+    return rec.get("traffic_bytes")
 
 
 def parse():
@@ -390,7 +414,7 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(spec.name) if storage == spec.storage and args.mode == "soft" else None,
             "kernel": "lf_em_kernel",
             "kernel_ms": em_avg_s * 1e3,
             "flops_per_unit": flops_per_unit,
