@@ -13,7 +13,13 @@ static EmKernel pick_em_k(bool frac, bool exh, bool sym) {
     if (exh)
         return frac ? (EmKernel)lf_em_kernel<K, ST, true, true, false> : (EmKernel)lf_em_kernel<K, ST, false, true, false>;
     if (frac) return (EmKernel)lf_em_kernel<K, ST, true, false, false>;
-    return sym ? (EmKernel)lf_em_kernel<K, ST, false, false, true> : (EmKernel)lf_em_kernel<K, ST, false, false, false>;
+    if constexpr (K <= 6) {
+        // the fast sweep of small view counts fits 128 VGPRs with a few spills
+        return sym ? (EmKernel)lf_em_kernel_w4<K, ST, false, false, true>
+                   : (EmKernel)lf_em_kernel_w4<K, ST, false, false, false>;
+    } else {
+        return sym ? (EmKernel)lf_em_kernel<K, ST, false, false, true> : (EmKernel)lf_em_kernel<K, ST, false, false, false>;
+    }
 }
 
 template <int ST>

@@ -306,8 +306,11 @@ __device__ __forceinline__ void fetch(const typename Rec<ST>::T *win, const Wind
 // spread, summed in kernel view order; shared by the exact re-evaluation and
 // the exhaustive sweep so both give the same bits.
 template <int K>
-__device__ __forceinline__ float exact_energy(const float2 (&f)[K], const float (&wt)[K], float invW, float cw,
-                                              float P, float &mx, float &my) {
+__device__ __forceinline__ float exact_energy(const float2 (&f)[K], const float (&q)[K], bool empty, float invW,
+                                              float cw, float P, float &mx, float &my) {
+    float wt[K];   // the weights, all 1 when none is positive
+#pragma unroll
+    for (int k = 0; k < K; ++k) wt[k] = empty ? 1.0f : q[k];
     float ax = 0.0f, ay = 0.0f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -494,7 +497,7 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
 #pragma unroll
     for (int k = 0; k < K; ++k) Q += s.q[k];
     const bool empty = !(Q > 0.0f);
-    float wt[K];
+    float wt[K];   // sweep weights (all 1 when none is positive)
 #pragma unroll
     for (int k = 0; k < K; ++k) wt[k] = empty ? 1.0f : s.q[k];
     const float invW = 1.0f / (empty ? (float)K : Q);
@@ -513,7 +516,7 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
             f[0] = s.f0;
 #pragma unroll
             for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, j, s.idx0[k], f[k], nn);
-            const float E = exact_energy<K>(f, wt, invW, cw, sweep_log_prior(a, j, mu, masked), mx, my);
+            const float E = exact_energy<K>(f, s.q, empty, invW, cw, sweep_log_prior(a, j, mu, masked), mx, my);
             if (E < best_E) {
                 best_E = E;
                 best_j = j;
@@ -528,13 +531,22 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
             f[0] = s.f0;
 #pragma unroll
             for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, best_j, s.idx0[k], f[k], nn);
-            best_E = exact_energy<K>(f, wt, invW, cw, sweep_log_prior(a, best_j, mu, masked), mx, my);
+            best_E = exact_energy<K>(f, s.q, empty, invW, cw, sweep_log_prior(a, best_j, mu, masked), mx, my);
         }
-        const float A0x = wt[0] * s.f0.x, A0y = wt[0] * s.f0.y, S0 = wt[0] * s.n0;
         // candidate test  E^ - M <= E_best  with the margin folded in:
-        //   cw (1 - margin_k) S - (cw / W) |A|^2  <=  E_best + margin_c + P_j
-        const float alpha = cw * (1.0f - a.margin_k), gam = cw * invW;
+        //   cw (1 - margin_k) S - (cw / W) |A|^2  <=  E_best + margin_c + P_j,
+        // evaluated with the weights pre-scaled by sg = sqrt(cw / W), so that
+        // |A'|^2 = (cw / W) |A|^2 and S' = sg S, as c3 S' - |A'|^2 with
+        // c3 = cw (1 - margin_k) / sg (the extra roundings stay well inside
+        // margin_k's slack)
+        const float sg = sqrtf(cw * invW);
+        const float c3 = sg > 0.0f ? cw * (1.0f - a.margin_k) / sg : 0.0f;
+        float ws[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) ws[k] = sg * wt[k];
+        const float A0x = ws[0] * s.f0.x, A0y = ws[0] * s.f0.y, S0 = ws[0] * s.n0;
         float bound = best_E + a.margin_c;
+        float bound_c = bound + Pc;   // the threshold where the prior is the constant ln gamma
         // Scores G consecutive levels from j0, then re-evaluates the
         // candidates among them exactly, in increasing level order.
         auto group = [&](auto Gc, int j0, bool inwin) {
@@ -562,24 +574,25 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
                         f[i][k] = rec_f<ST>(r);
                         n = rec_n<ST>(r);
                     }
-                    ax = fmaf(wt[k], f[i][k].x, ax);
-                    ay = fmaf(wt[k], f[i][k].y, ay);
-                    S = fmaf(wt[k], n, S);
+                    ax = fmaf(ws[k], f[i][k].x, ax);
+                    ay = fmaf(ws[k], f[i][k].y, ay);
+                    S = fmaf(ws[k], n, S);
                 }
                 P[i] = inwin ? sweep_log_prior(a, j0 + i, mu, masked) : Pc;
-                lhs[i] = fmaf(-gam, fmaf(ax, ax, ay * ay), alpha * S);
+                lhs[i] = fmaf(c3, S, -fmaf(ax, ax, ay * ay));
             }
 #pragma unroll
             for (int i = 0; i < G; ++i) {
                 const int j = j0 + i;
                 // the current best level is already exact: skip it
-                if (lhs[i] <= bound + P[i] && j != best_j) {
+                if (lhs[i] <= (inwin ? bound + P[i] : bound_c) && j != best_j) {
                     float mx, my;
-                    const float E = exact_energy<K>(f[i], wt, invW, cw, P[i], mx, my);
+                    const float E = exact_energy<K>(f[i], s.q, empty, invW, cw, P[i], mx, my);
                     if (E < best_E || (E == best_E && j < best_j)) {
                         best_E = E;
                         best_j = j;
                         bound = best_E + a.margin_c;
+                        bound_c = bound + Pc;
                     }
                 }
             }
@@ -606,7 +619,7 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
     f[0] = s.f0;
 #pragma unroll
     for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, best_j, s.idx0[k], f[k], nn);
-    (void)exact_energy<K>(f, wt, invW, cw, 0.0f, mx, my);
+    (void)exact_energy<K>(f, s.q, empty, invW, cw, 0.0f, mx, my);
     float L = 0.0f;
     if (with_obj) L = log_prior(a, best_j, mu);
     if (a.mode >= 2) {
@@ -636,13 +649,25 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
     s.L = L;
 }
 
-template <int K, int ST, bool FRAC, bool EXH, bool SYM>
-__global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
-    using R = typename Rec<ST>::T;
+// Descriptor pair of storage ST as a pair of record storage RS (RS == ST,
+// or FP32 values already known to be exact in binary16).
+template <int RS, int ST>
+__device__ __forceinline__ typename Pair<RS>::T to_record_pair(typename Pair<ST>::T v) {
+    if constexpr (RS == ST) return v;
+    else {
+        const float2 f = widen(v);
+        return make_pair<RS>(f.x, f.y);
+    }
+}
+
+__device__ __forceinline__ bool exact_in_half(float v) { return __half2float(__float2half_rn(v)) == v; }
+
+// The kernel body: descriptors of storage ST staged as records of storage RS.
+template <int K, int ST, int RS, bool FRAC, bool EXH, bool SYM>
+__device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw, double *red) {
+    using R = typename Rec<RS>::T;
     using P = typename Pair<ST>::T;
-    extern __shared__ __align__(16) unsigned char lds_raw[];
     R *win = reinterpret_cast<R *>(lds_raw);
-    __shared__ double red[8];
 
     const int y = blockIdx.y;
     const int x0 = blockIdx.x * a.tile;
@@ -662,7 +687,7 @@ __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
     for (int k = 0; k < K; ++k) {
         const P *row = feat + ((size_t)a.perm[k] * a.H + y) * a.W;
         for (int p = tid; p < w[k].len; p += blockDim.x)
-            win[win_index(w[k], p)] = make_rec<ST>(row[clampi(w[k].umin + p, 0, a.W - 1)]);
+            win[win_index(w[k], p)] = make_rec<RS>(to_record_pair<RS, ST>(row[clampi(w[k].umin + p, 0, a.W - 1)]));
     }
     __syncthreads();
 
@@ -687,7 +712,7 @@ __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
         s.best_j = (a.seed_from_d && work) ? a.d_idx[pix] : nearest_level(a, s.mu);
 #pragma unroll
         for (int k = 0; k < K; ++k) s.idx0[k] = FRAC ? 0 : lane_index0(w[k], a.bi[k], a.dmin_i, x);
-        fetch<K, ST, FRAC>(win, w[0], a, 0, x, 0, s.idx0[0], s.f0, s.n0);
+        fetch<K, RS, FRAC>(win, w[0], a, 0, x, 0, s.idx0[0], s.f0, s.n0);
     } else {
 #pragma unroll
         for (int k = 0; k < K; ++k) s.q[k] = s.la[k] = s.lb[k] = 0.0f;
@@ -701,7 +726,7 @@ __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
     const int block_id = blockIdx.y * gridDim.x + blockIdx.x;
     for (int it = 0; it < a.n_iters; ++it) {
         const bool with_obj = a.want_obj || it == a.n_iters - 1;
-        if (work) em_iteration<K, ST, FRAC, EXH, SYM>(win, w, a, x, jlo, jhi, slo, shi, Pc, s, with_obj);
+        if (work) em_iteration<K, RS, FRAC, EXH, SYM>(win, w, a, x, jlo, jhi, slo, shi, Pc, s, with_obj);
         if (!with_obj) continue;
         // ---- FP64 block sum of the objective ----
         double sum = wave_sum(work ? (double)s.L : 0.0);
@@ -721,6 +746,48 @@ __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
         a.d_idx[pix] = s.best_j;
         a.lpix[pix] = s.L;
     }
+}
+
+// EM kernel.  FP32 descriptors whose staged windows are all exact in
+// binary16 (|G| <= 2048 for the Sobel responses, the usual case) are staged
+// as binary16 records: the same values, read as 8 bytes instead of 12 per
+// record, and the same FP32 arithmetic, so the results are the same bits.
+template <int K, int ST, bool FRAC, bool EXH, bool SYM>
+__device__ __forceinline__ void em_entry(const EmArgs &a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ double red[8];
+    if constexpr (ST == 0) {
+        Window w[K];
+        int total;
+        view_windows<K, FRAC>(a, blockIdx.x * a.tile, w, total);
+        const float2 *feat = reinterpret_cast<const float2 *>(a.feat);
+        bool exact = true;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float2 *row = feat + ((size_t)a.perm[k] * a.H + blockIdx.y) * a.W;
+            for (int p = threadIdx.x; p < w[k].len; p += blockDim.x) {
+                const float2 v = row[clampi(w[k].umin + p, 0, a.W - 1)];
+                exact = exact && exact_in_half(v.x) && exact_in_half(v.y);
+            }
+        }
+        if (__syncthreads_and(exact)) em_body<K, 0, 1, FRAC, EXH, SYM>(a, lds_raw, red);
+        else em_body<K, 0, 0, FRAC, EXH, SYM>(a, lds_raw, red);
+    } else {
+        em_body<K, ST, ST, FRAC, EXH, SYM>(a, lds_raw, red);
+    }
+}
+
+template <int K, int ST, bool FRAC, bool EXH, bool SYM>
+__global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
+    em_entry<K, ST, FRAC, EXH, SYM>(a);
+}
+
+// The same kernel held to 128 VGPRs, four waves per SIMD: for small view
+// counts this costs a few spills outside the sweep and gains a wave of
+// latency hiding (the sweep alternates LDS reads and FMAs).
+template <int K, int ST, bool FRAC, bool EXH, bool SYM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void lf_em_kernel_w4(EmArgs a) {
+    em_entry<K, ST, FRAC, EXH, SYM>(a);
 }
 
 }  // namespace lfem
