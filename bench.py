@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the frame-server legs")
+    ap.add_argument("--no-variants", action="store_true", help="skip the variant legs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM traffic counters)")
     return ap.parse_args()
@@ -78,6 +79,36 @@ def parse():
 def log(args, msg):
     if not args.quiet:
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def variant_legs(LF, torch, spec, frame, storage, views, sp, mu, stream, reps=20):
+    """EM launch time of the same frame with the paper's speed levers and
+    E-step forms: the search window around mu_T, dynamic reference pixels
+    only, both, and the enumeration E-step."""
+    K, H, W, D, I = spec.K, spec.H, spec.W, spec.D, spec.n_iters
+    legs = [("window_3sigma", "soft", LF.LF_PRIOR_WINDOW), ("dynamic_only", "soft", LF.LF_DYNAMIC_ONLY),
+            ("window_and_dynamic_only", "soft", LF.LF_PRIOR_WINDOW | LF.LF_DYNAMIC_ONLY),
+            ("enumeration_soft", "enum_soft", 0), ("enumeration_hard", "enum_hard", 0)]
+    out = {}
+    dev_flags = LF.LF_INPUTS_ON_DEVICE | LF.LF_OUTPUTS_ON_DEVICE
+    for name, mode, flags in legs:
+        p = LF.make_params(K, H, W, spec.ref, spec.baselines, spec.d_min, spec.d_step, D, frame.beta,
+                           gamma=spec.gamma, sigma=spec.sigma, tau_init=spec.tau, storage=storage, mode=mode,
+                           flags=dev_flags | flags)
+        ctx = LF.lf_em_init(p, views, sp, mu, hip_stream=stream.cuda_stream)
+        ts = []
+        for r in range(reps + 3):
+            LF.lf_em_load(ctx, views, sp, mu)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            LF.lf_em_iterate(ctx, I)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if r >= 3:
+                ts.append(e0.elapsed_time(e1))
+        LF.lf_em_destroy(ctx)
+        out[name] = {"em_ms": float(np.median(ts)), "mode": mode}
+    return out
 
 
 def cpu_baseline(spec, frame, storage, mode, budget_s):
@@ -422,6 +453,10 @@ def main():
             "algorithmic_hbm_GBps": em_bytes / em_avg_s / 1e9,
         },
     }
+    if not args.no_variants:
+        log(args, "timing the variants (search window, dynamic-only, enumeration)")
+        out["variants"] = variant_legs(LF, torch, spec, frame, storage, views, sp, mu, stream)
+        out["variants"]["plain_em_ms"] = em_avg_s * 1e3
     if serve:
         log(args, "serving the same workload through the FP16 frame server")
         out["serving_same_workload"] = serve_same_workload(args, LF, frame, spec)
