@@ -193,6 +193,9 @@ hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *m
     return hipGetLastError();
 }
 
+// LDS a dynamic-only launch adds after the windows: 256 lane slots and 4 counts
+static constexpr size_t kSlotsBytes = 260 * 4;
+
 EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
     EmArgs a{};
     // kernel view order: the reference first, then the others in array order
@@ -210,6 +213,10 @@ EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
         const double c2 = 1.4426950408889634 / (2.0 * (double)p->sigma * p->sigma);
         const double e = 28.0 - std::log2((double)p->gamma);
         a.prior_T = e > 0.0 ? (float)std::sqrt(e / c2) : -1.0f;
+        // ln(gamma + g) <= ln(1 + gamma) for g <= 1; the slack covers the
+        // rounding of gamma + g and the hardware logarithm
+        const double hi = std::log1p((double)p->gamma);
+        a.prior_hi = (float)(hi + 1e-5 * std::max(1.0, std::fabs(hi)));
     }
     // bound of |one-pass energy - two-pass energy| in FP32 (see the kernel):
     // beta' * (16K + 64) u * S + 64 u (|ln gamma| + 1), u = 2^-24
@@ -243,6 +250,10 @@ EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
 hipError_t launch_em(const lf_params *p, const Geometry &g, EmArgs a, int tile, size_t lds, hipStream_t s) {
     EmKernel kern = pick_em(p->K, p->storage, g.frac, (p->flags & LF_EXHAUSTIVE_SWEEP) != 0, g.sym);
     a.tile = tile;
+    if (a.dyn_only) {
+        a.lds_slots = (int)((lds + 15) / 16 * 16);
+        lds = (size_t)a.lds_slots + kSlotsBytes;
+    }
     dim3 block(tile), grid((p->W + tile - 1) / tile, p->H);
     a.n_blocks = grid.x * grid.y;
     hipLaunchKernelGGL(kern, grid, block, lds, s, a);
@@ -279,16 +290,37 @@ hipError_t launch_median3(const lf_params *p, const float *in, float *out, hipSt
     return hipGetLastError();
 }
 
-int choose_tile(const lf_params *p, const Geometry &g, size_t lds_limit, size_t *lds_out) {
-    int tile = p->W >= 128 ? 128 : 64;
-    for (;;) {
-        const size_t lds = em_window_pairs(p, g, tile) * rec_bytes(p->storage);
-        if (lds <= lds_limit || tile == 64) {
-            *lds_out = lds;
-            return lds <= lds_limit ? tile : 0;
+// Row-tile width of the EM kernel: the width (a multiple of the 64-lane
+// wave, up to 256) with the best product of waves resident per SIMD (capped
+// at 4; bounded by the kernel's VGPRs and the CU's LDS) and lanes doing
+// work (W over W rounded up to whole tiles); ties go to the narrower tile.
+// Returns 0 when not even 64 columns fit the block LDS limit.
+int choose_tile(const lf_params *p, const Geometry &g, size_t lds_limit, size_t lds_per_cu, int vgprs,
+                size_t *lds_out) {
+    const int waves_simd_vgpr = vgprs > 0 ? 512 / ((vgprs + 7) / 8 * 8) : 4;
+    int best = 0;
+    double best_score = -1.0;
+    *lds_out = em_window_pairs(p, g, 64) * rec_bytes(p->storage);
+    for (int tile = 64; tile <= 256; tile += 64) {
+        if (tile > 64 && tile - 64 >= p->W) break;   // wider than the frame
+        const size_t lds = em_window_pairs(p, g, tile) * rec_bytes(p->storage) + 64 +
+                           ((p->flags & LF_DYNAMIC_ONLY) ? kSlotsBytes + 16 : 0);
+        if (lds > lds_limit) continue;
+        const int wb = tile / 64;
+        const int blocks_lds = (int)(lds_per_cu / lds);
+        const int blocks_vgpr = 4 * std::max(waves_simd_vgpr, 1) / wb;
+        const int blocks = std::min(blocks_lds, blocks_vgpr);
+        if (blocks < 1) continue;
+        const double per_simd = std::min(blocks * wb / 4.0, 4.0);
+        const double used = (double)p->W / (double)(((p->W + tile - 1) / tile) * tile);
+        const double score = per_simd * used;
+        if (score > best_score + 1e-9) {
+            best_score = score;
+            best = tile;
+            *lds_out = em_window_pairs(p, g, tile) * rec_bytes(p->storage);
         }
-        tile /= 2;
     }
+    return best;
 }
 
 }  // namespace lfem
@@ -339,7 +371,21 @@ static lf_status ctx_alloc(lf_ctx *c) {
         LF_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device), "device attribute");
         lds_limit = (size_t)v;
     }
-    c->tile = choose_tile(&p, c->g, lds_limit, &c->lds);
+    size_t lds_cu = 0;
+    {
+        int v = 0;
+        LF_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device),
+               "device attribute");
+        lds_cu = v > 0 ? (size_t)v : lds_limit;
+    }
+    int vgprs = 0;
+    {
+        EmKernel kern = pick_em(p.K, p.storage, c->g.frac, (p.flags & LF_EXHAUSTIVE_SWEEP) != 0, c->g.sym);
+        hipFuncAttributes fa;
+        if (kern && hipFuncGetAttributes(&fa, (const void *)kern) == hipSuccess) vgprs = fa.numRegs;
+        (void)hipGetLastError();
+    }
+    c->tile = choose_tile(&p, c->g, lds_limit, lds_cu, vgprs, &c->lds);
     if (!c->tile)
         return set_error(LF_EINVAL, "disparity halo needs %zu bytes of LDS per block, more than %zu", c->lds, lds_limit);
     c->n_blocks = ((p.W + c->tile - 1) / c->tile) * p.H;

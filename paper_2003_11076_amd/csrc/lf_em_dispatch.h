@@ -13,10 +13,18 @@ static EmKernel pick_em_k(bool frac, bool exh, bool sym) {
     if (exh)
         return frac ? (EmKernel)lf_em_kernel<K, ST, true, true, false> : (EmKernel)lf_em_kernel<K, ST, false, true, false>;
     if (frac) return (EmKernel)lf_em_kernel<K, ST, true, false, false>;
-    if constexpr (K <= 6) {
-        // the fast sweep of small view counts fits 128 VGPRs with a few spills
+    // Occupancy per view count: the fast sweep of few views fits 96 or 128
+    // VGPRs with a few spills outside the sweep (five or four waves per SIMD)
+    if constexpr (K <= 5) {
+        return sym ? (EmKernel)lf_em_kernel_w5<K, ST, false, false, true>
+                   : (EmKernel)lf_em_kernel_w5<K, ST, false, false, false>;
+    } else if constexpr (K <= 6) {
         return sym ? (EmKernel)lf_em_kernel_w4<K, ST, false, false, true>
                    : (EmKernel)lf_em_kernel_w4<K, ST, false, false, false>;
+    } else if constexpr (K <= 9) {
+        // three waves per SIMD, with a tile wide enough for the LDS to hold them
+        return sym ? (EmKernel)lf_em_kernel_w3<K, ST, false, false, true>
+                   : (EmKernel)lf_em_kernel_w3<K, ST, false, false, false>;
     } else {
         return sym ? (EmKernel)lf_em_kernel<K, ST, false, false, true> : (EmKernel)lf_em_kernel<K, ST, false, false, false>;
     }

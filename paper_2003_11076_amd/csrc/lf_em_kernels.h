@@ -172,10 +172,12 @@ struct EmArgs {
     float c_exp2;         // log2(e) / (2 sigma^2)
     float c_exp;          // 1 / (2 sigma^2)
     float prior_T;        // |d - mu| beyond which gamma + g == gamma in FP32
+    float prior_hi;       // upper bound of the log prior as evaluated: ln(1 + gamma) plus slack
     float margin_k;       // one-pass error bound, in units of beta' * S
     float margin_c;       // absolute slack of the bound
     float win_half;       // > 0: the M-step searches only |d - mu| <= win_half
     int dyn_only;         // 1: only pixels with rho_ref < tau are reconstructed
+    int lds_slots;        // dynamic-only: byte offset of 260 ints of LDS after the windows
     float tau;            // first-iteration threshold (dynamic-only test)
     int perm[kMaxViews];  // kernel view order -> array view index (perm[0] = reference)
     int bi[kMaxViews];    // integer baselines, kernel order (integer-shift path)
@@ -546,13 +548,14 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
         for (int k = 0; k < K; ++k) ws[k] = sg * wt[k];
         const float A0x = ws[0] * s.f0.x, A0y = ws[0] * s.f0.y, S0 = ws[0] * s.n0;
         float bound = best_E + a.margin_c;
-        float bound_c = bound + Pc;   // the threshold where the prior is the constant ln gamma
+        float bound_c = bound + Pc;            // threshold where the prior is the constant ln gamma
+        float bound_hi = bound + a.prior_hi;   // threshold with the prior's upper bound
         // Scores G consecutive levels from j0, then re-evaluates the
         // candidates among them exactly, in increasing level order.
         auto group = [&](auto Gc, int j0, bool inwin) {
             constexpr int G = decltype(Gc)::value;
             float2 f[G][K];
-            float lhs[G], P[G];
+            float lhs[G];
 #pragma unroll
             for (int i = 0; i < G; ++i) {
                 f[i][0] = s.f0;
@@ -578,21 +581,35 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
                     ay = fmaf(ws[k], f[i][k].y, ay);
                     S = fmaf(ws[k], n, S);
                 }
-                P[i] = inwin ? sweep_log_prior(a, j0 + i, mu, masked) : Pc;
                 lhs[i] = fmaf(c3, S, -fmaf(ax, ax, ay * ay));
             }
 #pragma unroll
             for (int i = 0; i < G; ++i) {
                 const int j = j0 + i;
-                // the current best level is already exact: skip it
-                if (lhs[i] <= (inwin ? bound + P[i] : bound_c) && j != best_j) {
+                // Inside the prior window the prior is evaluated only for
+                // levels that pass the test with its upper bound P_hi (few:
+                // the seed is close to the optimum); the current best level
+                // is already exact and is skipped.
+                float Pj = Pc;
+                bool cand;
+                if (inwin) {
+                    cand = false;
+                    if (lhs[i] <= bound_hi) {
+                        Pj = sweep_log_prior(a, j, mu, masked);
+                        cand = lhs[i] <= bound + Pj;
+                    }
+                } else {
+                    cand = lhs[i] <= bound_c;
+                }
+                if (cand && j != best_j) {
                     float mx, my;
-                    const float E = exact_energy<K>(f[i], s.q, empty, invW, cw, P[i], mx, my);
+                    const float E = exact_energy<K>(f[i], s.q, empty, invW, cw, Pj, mx, my);
                     if (E < best_E || (E == best_E && j < best_j)) {
                         best_E = E;
                         best_j = j;
                         bound = best_E + a.margin_c;
                         bound_c = bound + Pc;
+                        bound_hi = bound + a.prior_hi;
                     }
                 }
             }
@@ -672,10 +689,7 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
     const int y = blockIdx.y;
     const int x0 = blockIdx.x * a.tile;
     const int tid = threadIdx.x;
-    const int x = x0 + tid;
-    const bool active = x < a.W;
     const size_t HW = (size_t)a.H * a.W;
-    const size_t pix = (size_t)y * a.W + x;
 
     Window w[K];
     int total;
@@ -689,7 +703,42 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
         for (int p = tid; p < w[k].len; p += blockDim.x)
             win[win_index(w[k], p)] = make_rec<RS>(to_record_pair<RS, ST>(row[clampi(w[k].umin + p, 0, a.W - 1)]));
     }
-    __syncthreads();
+
+    // Column of the tile this lane works on: its own, or with dynamic-only
+    // the tile's dynamic reference pixels packed into the first lanes (so
+    // that waves of static pixels have nothing to do).
+    int xc = tid;
+    if (a.dyn_only) {
+        const int xo = x0 + tid;
+        bool mine = false;
+        if (xo < a.W) {
+            const size_t po = (size_t)y * a.W + xo;
+            mine = a.rho[(size_t)a.perm[0] * HW + po] < a.tau;
+            if (!mine && a.n_iters > 0) {   // static reference ray: not reconstructed
+                a.d_idx[po] = nearest_level(a, a.mu_T[po]);
+                a.lpix[po] = 0.0f;
+            }
+        }
+        int *slots = reinterpret_cast<int *>(lds_raw + a.lds_slots);
+        int *counts = slots + 256;
+        const unsigned long long m = __ballot(mine);
+        const int lane = tid & 63, wv = tid >> 6;
+        if (lane == 0) counts[wv] = __popcll(m);
+        __syncthreads();
+        int base = 0, n = 0;
+        for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) {
+            if (i < wv) base += counts[i];
+            n += counts[i];
+        }
+        if (mine) slots[base + __popcll(m & ((1ull << lane) - 1ull))] = tid;
+        __syncthreads();
+        xc = tid < n ? slots[tid] : -1;
+    } else {
+        __syncthreads();
+    }
+    const int x = x0 + xc;
+    const bool active = xc >= 0 && x < a.W;
+    const size_t pix = (size_t)y * a.W + (active ? x : 0);
 
     Lane<K> s;
     s.mu = 0.0f;
@@ -707,7 +756,6 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
             s.q[k] = a.q[i];
             s.la[k] = (r > 0.0f ? logf(r) : -INFINITY) + a.lambda;   // ln rho + lambda
             s.lb[k] = (om > 0.0f ? logf(om) : -INFINITY);            // ln(1 - rho)
-            if (k == 0 && a.dyn_only) work = r < a.tau;                // kernel view 0 is the reference
         }
         s.best_j = (a.seed_from_d && work) ? a.d_idx[pix] : nearest_level(a, s.mu);
 #pragma unroll
@@ -779,6 +827,18 @@ __device__ __forceinline__ void em_entry(const EmArgs &a) {
 
 template <int K, int ST, bool FRAC, bool EXH, bool SYM>
 __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
+    em_entry<K, ST, FRAC, EXH, SYM>(a);
+}
+
+// The same kernel held to 168 VGPRs, three waves per SIMD (views 7 to 9).
+template <int K, int ST, bool FRAC, bool EXH, bool SYM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void lf_em_kernel_w3(EmArgs a) {
+    em_entry<K, ST, FRAC, EXH, SYM>(a);
+}
+
+// The same kernel held to 96 VGPRs, five waves per SIMD (up to 5 views).
+template <int K, int ST, bool FRAC, bool EXH, bool SYM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void lf_em_kernel_w5(EmArgs a) {
     em_entry<K, ST, FRAC, EXH, SYM>(a);
 }
 

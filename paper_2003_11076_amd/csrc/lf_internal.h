@@ -71,7 +71,8 @@ Geometry make_geometry(const lf_params *p);
 size_t em_window_pairs(const lf_params *p, const Geometry &g, int tile);
 size_t pair_bytes(int storage);
 size_t rec_bytes(int storage);
-int choose_tile(const lf_params *p, const Geometry &g, size_t lds_limit, size_t *lds_out);
+int choose_tile(const lf_params *p, const Geometry &g, size_t lds_limit, size_t lds_per_cu, int vgprs,
+                size_t *lds_out);
 
 hipError_t launch_descriptors(const lf_params *p, const uint8_t *views, void *feat, hipStream_t s);
 hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *mu_T, const float *q_warm,

@@ -233,3 +233,24 @@ def test_fast_sweep_matches_exhaustive_config1(config1):
         run.close()
     for x, y in zip(out[0], out[1]):
         assert np.array_equal(x, y)
+
+
+def test_config3_fp16_error_against_unquantised_oracle():
+    """Reported, not a parity bound: FP16 storage end to end (10 free-running
+    iterations) against the FP64 oracle on unrounded inputs, rows 472..488."""
+    fr = S.make_frame(S.config_spec(3))
+    case = Case.from_frame(fr, storage="f16")
+    _say("config3 fp16 end to end vs the unquantised FP64 oracle, rows 472..488")
+    run = GpuRun(case)
+    run.iterate(10)
+    rgb, d, q, hole = run.refocus()
+    run.close()
+    ref = O.reconstruct(Case.from_frame(fr, storage="f32").oracle_params(),
+                        case.views, case.S_P, case.mu_T, 10, rows=(472, 488))
+    y = slice(472, 488)
+    agree = float((d[y] == ref["d_idx"][y]).mean())
+    qerr = np.abs(q[:, y].astype(np.float64) - ref["q"][:, y])
+    rerr = np.abs(rgb[y].astype(np.float64) - ref["rgb"][y])
+    print(f"[report] d agreement {agree:.5f}  q max {qerr.max():.3g} p99.9 {np.percentile(qerr, 99.9):.3g}  "
+          f"rgb max {rerr.max():.3g} mean {rerr.mean():.3g}", flush=True)
+    assert agree > 0.98
