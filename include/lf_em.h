@@ -86,6 +86,14 @@ typedef int32_t lf_status;
  *   objective, and its refocused colour is its reference colour (hole = 0). */
 #define LF_PRIOR_WINDOW       0x8u
 #define LF_DYNAMIC_ONLY       0x10u
+/* LF_DEFERRED_CHECK (with LF_INPUTS_ON_DEVICE): lf_em_load / lf_em_init
+ * return without waiting for the device-side value check of the inputs, so
+ * frames can be queued back to back.  Invalid values are counted on the
+ * device (the count stays set across frames) and reported as LF_EINVAL by
+ * the next call that waits for the stream (lf_em_check, lf_em_iterate with
+ * an objective, or an output copied to the host), which also unloads the
+ * frame; results of frames with invalid inputs are meaningless. */
+#define LF_DEFERRED_CHECK     0x20u
 
 typedef struct {
     int32_t K, H, W;            /* views, rows, columns; 2 <= K <= 16                 */
@@ -103,7 +111,7 @@ typedef struct {
     int32_t mode;               /* LF_SOFT, LF_HARD, LF_ENUM_SOFT, LF_ENUM_HARD        */
     uint32_t flags;             /* LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE |       */
                                 /* LF_EXHAUSTIVE_SWEEP | LF_PRIOR_WINDOW |            */
-                                /* LF_DYNAMIC_ONLY                                    */
+                                /* LF_DYNAMIC_ONLY | LF_DEFERRED_CHECK                */
 } lf_params;
 
 typedef struct lf_ctx lf_ctx;   /* opaque; owns all device buffers of one frame shape */
@@ -191,6 +199,14 @@ lf_status lf_refocus(lf_ctx *c, float *rgb, int32_t *d_idx, float *q, uint8_t *h
  * iteration since the last load), LF_EDEVICE.
  */
 lf_status lf_segmentation_maps(lf_ctx *c, uint8_t *labels);
+
+/*
+ * lf_em_check -- wait for all work queued on the context's stream and report
+ * a deferred input check (LF_DEFERRED_CHECK): LF_EINVAL when any frame loaded
+ * since the last report had invalid values (the frame is then unloaded).
+ * Errors: LF_EINVAL, LF_EDEVICE.
+ */
+lf_status lf_em_check(lf_ctx *c);
 
 /*
  * lf_em_state -- copy out the current state without refocusing.

@@ -27,7 +27,7 @@ LF_SOFT, LF_HARD, LF_ENUM_SOFT, LF_ENUM_HARD = 0, 1, 2, 3
 LF_ENUM_MAX_VIEWS = 12
 MODES = {"soft": LF_SOFT, "hard": LF_HARD, "enum_soft": LF_ENUM_SOFT, "enum_hard": LF_ENUM_HARD}
 LF_INPUTS_ON_DEVICE, LF_OUTPUTS_ON_DEVICE, LF_EXHAUSTIVE_SWEEP = 0x1, 0x2, 0x4
-LF_PRIOR_WINDOW, LF_DYNAMIC_ONLY = 0x8, 0x10
+LF_PRIOR_WINDOW, LF_DYNAMIC_ONLY, LF_DEFERRED_CHECK = 0x8, 0x10, 0x20
 STORAGE = {"f32": LF_F32, "f16": LF_F16, "bf16": LF_BF16}
 
 
@@ -80,12 +80,13 @@ def lib():
         L.lf_refocus.argtypes = [vp, vp, vp, vp, vp, i32]
         L.lf_em_state.argtypes = [vp, vp, vp, vp]
         L.lf_segmentation_maps.argtypes = [vp, vp]
+        L.lf_em_check.argtypes = [vp]
         L.lf_em_intermediates.argtypes = [vp, vp, vp]
         L.lf_em_destroy.argtypes = [vp]
         L.lf_em_destroy.restype = None
         L.lf_last_error.restype = ctypes.c_char_p
         for f in ("lf_em_init", "lf_em_load", "lf_em_iterate", "lf_refocus", "lf_em_state", "lf_em_intermediates",
-                  "lf_segmentation_maps"):
+                  "lf_segmentation_maps", "lf_em_check"):
             getattr(L, f).restype = i32
         _bind_server(L)
         _bind_prior(L)
@@ -219,6 +220,10 @@ def lf_refocus(ctx, rgb, d_idx=None, q=None, hole=None, median=0):
 
 def lf_em_state(ctx, q=None, d_idx=None, L_pix=None):
     return _check(lib().lf_em_state(ctx, addr(q), addr(d_idx), addr(L_pix)))
+
+
+def lf_em_check(ctx):
+    return _check(lib().lf_em_check(ctx))
 
 
 def lf_segmentation_maps(ctx, labels):

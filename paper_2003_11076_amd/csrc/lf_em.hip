@@ -72,7 +72,7 @@ lf_status validate_params(const lf_params *p) {
     if (p->mode >= LF_ENUM_SOFT && p->K > LF_ENUM_MAX_VIEWS)
         return set_error(LF_EINVAL, "K=%d above %d in an enumeration mode", p->K, LF_ENUM_MAX_VIEWS);
     if (p->flags & ~(LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE | LF_EXHAUSTIVE_SWEEP | LF_PRIOR_WINDOW |
-                     LF_DYNAMIC_ONLY))
+                     LF_DYNAMIC_ONLY | LF_DEFERRED_CHECK))
         return set_error(LF_EINVAL, "unknown flags");
     return LF_OK;
 }
@@ -352,6 +352,7 @@ struct lf_ctx {
     uint32_t *bad;
     double *h_obj;          // pinned
     uint32_t *h_bad;        // pinned
+    bool check_pending;     // deferred value check of device inputs not yet read
     int tile, n_blocks;
     size_t lds;
     bool loaded;
@@ -440,16 +441,21 @@ static lf_status ctx_load(lf_ctx *c, const uint8_t *views, const float *S_P, con
         qw = q_warm ? c->qw_own : nullptr;
     } else {
         c->views = views;
-        LF_HIP(hipMemsetAsync(c->bad, 0, 4, c->stream), "clear counter");
+        // with a deferred check the counter stays set until it is reported
+        if (!(p.flags & LF_DEFERRED_CHECK)) LF_HIP(hipMemsetAsync(c->bad, 0, 4, c->stream), "clear counter");
     }
     LF_HIP(launch_descriptors(&p, c->views, c->feat, c->stream), "descriptor launch");
     LF_HIP(launch_ray_prior(&p, sp, mu, qw, c->rho, c->omr, c->q, c->bad, dev_in ? 1 : 0, c->stream),
            "ray prior launch");
     if (dev_in) {
         LF_HIP(hipMemcpyAsync(c->h_bad, c->bad, 4, hipMemcpyDeviceToHost, c->stream), "copy counter");
-        LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
-        if (*c->h_bad) return set_error(LF_EINVAL, "%u input values invalid (S_P outside [0,1], mu_T not finite "
-                                                  "or q_warm outside [0,1])", *c->h_bad);
+        if (p.flags & LF_DEFERRED_CHECK) {
+            c->check_pending = true;   // read by the next call that waits for the stream
+        } else {
+            LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+            if (*c->h_bad) return set_error(LF_EINVAL, "%u input values invalid (S_P outside [0,1], mu_T not finite "
+                                                      "or q_warm outside [0,1])", *c->h_bad);
+        }
     } else {
         // host inputs were copied asynchronously from caller memory: finish the
         // copies before returning so the caller may free its buffers
@@ -525,6 +531,8 @@ lf_status lf_em_init(lf_ctx **out, const lf_params *p, const uint8_t *views, con
     c->stream = (hipStream_t)hip_stream;   // NULL: the device's null stream
     c->own_stream = false;
     st = ctx_alloc(c);
+    if (st == LF_OK && hipMemsetAsync(c->bad, 0, 4, c->stream) != hipSuccess)
+        st = set_error(LF_EDEVICE, "clear counter");
     if (st == LF_OK) st = ctx_load(c, views, S_P, mu_T, q_warm);
     if (st != LF_OK) {
         std::string msg = g_last_error;
@@ -540,6 +548,21 @@ lf_status lf_em_load(lf_ctx *c, const uint8_t *views, const float *S_P, const fl
     g_last_error.clear();
     if (!c) return set_error(LF_EINVAL, "context is NULL");
     return ctx_load(c, views, S_P, mu_T, q_warm);
+}
+
+// After the stream has been synchronised: report a pending deferred value
+// check of device inputs (and clear the sticky counter).
+static lf_status deferred_check(lf_ctx *c) {
+    if (!c->check_pending) return LF_OK;
+    c->check_pending = false;
+    const uint32_t bad = *c->h_bad;
+    if (!bad) return LF_OK;
+    *c->h_bad = 0;
+    LF_HIP(hipMemsetAsync(c->bad, 0, 4, c->stream), "clear counter");
+    LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    c->loaded = false;
+    return set_error(LF_EINVAL, "%u input values invalid in frames loaded since the last check (S_P outside [0,1], "
+                                "mu_T not finite or q_warm outside [0,1])", bad);
 }
 
 lf_status lf_em_iterate(lf_ctx *c, int32_t n_iters, double *objective) {
@@ -567,6 +590,8 @@ lf_status lf_em_iterate(lf_ctx *c, int32_t n_iters, double *objective) {
             LF_HIP(hipMemcpyAsync(c->h_obj, c->obj, (size_t)n * c->n_blocks * 8, hipMemcpyDeviceToHost, c->stream),
                    "copy objective");
             LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+            lf_status st = deferred_check(c);
+            if (st != LF_OK) return st;
             for (int t = 0; t < n; ++t) {
                 double s = 0.0;
                 const double *row = c->h_obj + (size_t)t * c->n_blocks;
@@ -578,6 +603,13 @@ lf_status lf_em_iterate(lf_ctx *c, int32_t n_iters, double *objective) {
     }
     c->iters += n_iters;
     return LF_OK;
+}
+
+lf_status lf_em_check(lf_ctx *c) {
+    g_last_error.clear();
+    if (!c) return set_error(LF_EINVAL, "context is NULL");
+    LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    return deferred_check(c);
 }
 
 static lf_status copy_out(lf_ctx *c, void *dst, const void *src, size_t bytes) {
@@ -614,7 +646,10 @@ lf_status lf_refocus(lf_ctx *c, float *rgb, int32_t *d_idx, float *q, uint8_t *h
     if (st == LF_OK && d_idx) st = copy_out(c, d_idx, c->d_idx, HW * 4);
     if (st == LF_OK && q) st = copy_out(c, q, c->q, HW * p.K * 4);
     if (st != LF_OK) return st;
-    if (!dev_out) LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    if (!dev_out) {
+        LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+        return deferred_check(c);
+    }
     return LF_OK;
 }
 
@@ -656,6 +691,7 @@ lf_status lf_segmentation_maps(lf_ctx *c, uint8_t *labels) {
         lf_status st = copy_out(c, labels, c->seg_labels, KHW);
         if (st != LF_OK) return st;
         LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+        return deferred_check(c);
     }
     return LF_OK;
 }
@@ -671,7 +707,10 @@ lf_status lf_em_state(lf_ctx *c, float *q, int32_t *d_idx, float *L_pix) {
     if (st == LF_OK && d_idx) st = copy_out(c, d_idx, c->d_idx, HW * 4);
     if (st == LF_OK && L_pix) st = copy_out(c, L_pix, c->lpix, HW * 4);
     if (st != LF_OK) return st;
-    if (!(c->p.flags & LF_OUTPUTS_ON_DEVICE)) LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    if (!(c->p.flags & LF_OUTPUTS_ON_DEVICE)) {
+        LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+        return deferred_check(c);
+    }
     return LF_OK;
 }
 
@@ -684,7 +723,10 @@ lf_status lf_em_intermediates(lf_ctx *c, void *feat, float *rho) {
     if (feat) st = copy_out(c, feat, c->feat, KHW * pair_bytes(c->p.storage));
     if (st == LF_OK && rho) st = copy_out(c, rho, c->rho, KHW * 4);
     if (st != LF_OK) return st;
-    if (!(c->p.flags & LF_OUTPUTS_ON_DEVICE)) LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    if (!(c->p.flags & LF_OUTPUTS_ON_DEVICE)) {
+        LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+        return deferred_check(c);
+    }
     return LF_OK;
 }
 

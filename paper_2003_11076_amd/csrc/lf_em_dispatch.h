@@ -14,8 +14,9 @@ static EmKernel pick_em_k(bool frac, bool exh, bool sym) {
         return frac ? (EmKernel)lf_em_kernel<K, ST, true, true, false> : (EmKernel)lf_em_kernel<K, ST, false, true, false>;
     if (frac) return (EmKernel)lf_em_kernel<K, ST, true, false, false>;
     // Occupancy per view count: the fast sweep of few views fits 96 or 128
-    // VGPRs with a few spills outside the sweep (five or four waves per SIMD)
-    if constexpr (K <= 5) {
+    // VGPRs with a few spills outside the sweep (five or four waves per SIMD;
+    // FP32 descriptors carry two record paths and stay at four)
+    if constexpr (K <= 5 && ST != 0) {
         return sym ? (EmKernel)lf_em_kernel_w5<K, ST, false, false, true>
                    : (EmKernel)lf_em_kernel_w5<K, ST, false, false, false>;
     } else if constexpr (K <= 6) {

@@ -705,8 +705,9 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
     }
 
     // Column of the tile this lane works on: its own, or with dynamic-only
-    // the tile's dynamic reference pixels packed into the first lanes (so
-    // that waves of static pixels have nothing to do).
+    // the tile's dynamic reference pixels, packed into the first lanes when
+    // that frees at least half of the busy waves (waves left without work
+    // skip the iterations).
     int xc = tid;
     if (a.dyn_only) {
         const int xo = x0 + tid;
@@ -730,9 +731,14 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
             if (i < wv) base += counts[i];
             n += counts[i];
         }
-        if (mine) slots[base + __popcll(m & ((1ull << lane) - 1ull))] = tid;
+        // pack only when it at least halves the busy waves: packed lanes read
+        // scattered columns of the windows, which costs LDS bank conflicts
+        int busy = 0;
+        for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) busy += counts[i] > 0;
+        const bool pack = 2 * ((n + 63) / 64) <= busy;
+        if (pack && mine) slots[base + __popcll(m & ((1ull << lane) - 1ull))] = tid;
         __syncthreads();
-        xc = tid < n ? slots[tid] : -1;
+        xc = pack ? (tid < n ? slots[tid] : -1) : (mine ? tid : -1);
     } else {
         __syncthreads();
     }

@@ -69,7 +69,7 @@ def _params(**over):
     (dict(mode=-1), "mode"),
     (dict(K=13, ref=6, baselines=list(range(-6, 7)), mode=2), "enumeration"),
     (dict(K=13, ref=6, baselines=list(range(-6, 7)), mode=3), "enumeration"),
-    (dict(flags=0x20), "flags"),
+    (dict(flags=0x40), "flags"),
     (dict(H=0), "H="),
     (dict(baselines=[-1, 0, float("inf")]), "baselines[2]"),
 ])

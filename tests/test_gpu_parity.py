@@ -166,6 +166,44 @@ def test_device_value_validation(config1):
     assert e.value.status == LF.LF_EINVAL
 
 
+def test_deferred_value_check(config1):
+    """LF_DEFERRED_CHECK: loads return at once; an invalid value is reported
+    by the next call that waits for the stream, once, and valid frames that
+    follow load and check clean."""
+    import torch
+    import paper_2003_11076_amd as LF
+    case = Case.from_frame(config1, storage="f32")
+    _say("deferred device-side input check")
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    tv = torch.from_numpy(case.views).to(dev)
+    good = torch.from_numpy(case.S_P).to(dev)
+    sp = case.S_P.copy()
+    sp[2, 9, 11] = 1.5
+    bad = torch.from_numpy(sp).to(dev)
+    tm = torch.from_numpy(case.mu_T).to(dev)
+    flags = LF.LF_INPUTS_ON_DEVICE | LF.LF_DEFERRED_CHECK
+    ctx = LF.lf_em_init(case.api_params(flags), tv, good, tm, hip_stream=stream)
+    try:
+        LF.lf_em_check(ctx)                                  # clean start
+        LF.lf_em_load(ctx, tv, bad, tm)                      # returns without waiting
+        LF.lf_em_iterate(ctx, 1)
+        with pytest.raises(LF.LFError) as e:
+            LF.lf_em_check(ctx)
+        assert e.value.status == LF.LF_EINVAL
+        with pytest.raises(LF.LFError) as e:                 # the frame was unloaded
+            LF.lf_em_iterate(ctx, 1)
+        assert e.value.status == LF.LF_ESTATE
+        LF.lf_em_load(ctx, tv, good, tm)
+        LF.lf_em_iterate(ctx, 2)
+        LF.lf_em_check(ctx)                                  # reported once, then clean
+        q = np.zeros((case.K, case.H, case.W), np.float32)
+        LF.lf_em_state(ctx, q)
+        assert np.all((q >= 0) & (q <= 1))
+    finally:
+        LF.lf_em_destroy(ctx)
+
+
 def test_state_calls_out_of_order(config1):
     import paper_2003_11076_amd as LF
     case = Case.from_frame(config1, storage="f32")
