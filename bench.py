@@ -1,6 +1,6 @@
 """Benchmark of the EM plane sweep on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2] [--storage f32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload plain] [--storage f32]
 
 One step is one frame through the whole method, with inputs already resident
 in HBM: lf_em_load (descriptors, ray prior, first weights, device-side input
@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 5])
+    ap.add_argument("--workload", default="plain", choices=["small", "plain", "precision", "large"])
     ap.add_argument("--storage", default=None, choices=["f32", "f16", "bf16"])
     ap.add_argument("--mode", default="soft", choices=["soft", "hard"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -349,11 +349,11 @@ def main():
     import lf_scenes as S
     import paper_2003_11076_amd as LF
 
-    spec = S.config_spec(args.config)
+    spec = S.workload_spec(args.workload)
     storage = args.storage or spec.storage
     log(args, f"generating {spec.name} ({spec.W}x{spec.H}, K={spec.K}, D={spec.D}, I={spec.n_iters})")
     frame = S.make_frame(spec)
-    serve = not args.no_serving and args.config == 2
+    serve = not args.no_serving and args.workload == "plain"
     mix_frames = serving_frames(S, lambda m: log(args, m)) if serve else None
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

@@ -25,7 +25,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "Frame", "SceneSpec", "make_frame", "config_spec", "CONFIG_NAMES",
+    "Frame", "SceneSpec", "make_frame", "workload_spec", "WORKLOAD_NAMES", "WORKLOADS",
     "serving_stream_spec", "rng_for",
 ]
 
@@ -440,48 +440,52 @@ def make_frame(spec: SceneSpec) -> Frame:
 
 
 # ---------------------------------------------------------------------------
-# The five workload configurations
+# The workloads: four single-frame scenes and the serving stream mix
 # ---------------------------------------------------------------------------
 
-CONFIG_NAMES = {
-    1: "plain-em-fp64-160x120-k5-d32-i5",
-    2: "plain-em-fp32-640x480-k5-d64-i10",
-    3: "precision-fp16-1280x960-k5-d128-i10",
-    4: "serving-mix-fp16-i8",
-    5: "large-bf16-1920x1080-k9-d192-i12",
+WORKLOAD_NAMES = {
+    "small": "plain-em-fp64-160x120-k5-d32-i5",
+    "plain": "plain-em-fp32-640x480-k5-d64-i10",
+    "precision": "precision-fp16-1280x960-k5-d128-i10",
+    "serving": "serving-mix-fp16-i8",
+    "large": "large-bf16-1920x1080-k9-d192-i12",
 }
+WORKLOADS = ("small", "plain", "precision", "large")   # single-frame scenes
+# seed bases of the scenes (every draw of a scene is seeded from its base)
+_SEED_BASE = {"small": 1000, "plain": 2000, "precision": 3000, "large": 5000}
 
 
 def _sym(K):
     return tuple(float(k - (K - 1) // 2) for k in range(K))
 
 
-def config_spec(c: int, **over) -> SceneSpec:
-    """SceneSpec of workload configuration c (1, 2, 3 or 5; 4 is a stream mix)."""
-    base = 1000 * c
-    if c == 1:
-        s = SceneSpec(CONFIG_NAMES[1], K=5, H=120, W=160, baselines=_sym(5), ref=2, D=32,
+def workload_spec(name: str, **over) -> SceneSpec:
+    """SceneSpec of a single-frame workload: "small", "plain", "precision" or
+    "large" (the serving mix is serving_stream_spec)."""
+    if name not in WORKLOADS:
+        raise ValueError(f"{name!r} is not a single-frame workload ({', '.join(WORKLOADS)})")
+    base = _SEED_BASE[name]
+    if name == "small":
+        s = SceneSpec(WORKLOAD_NAMES["small"], K=5, H=120, W=160, baselines=_sym(5), ref=2, D=32,
                       n_iters=5, texture="iid", n_planes=1, bg_disp=(6, 6), dyn_kind="rect",
                       n_dyn=1, dyn_disp=(20, 20), dyn_cover=(0.15, 0.15), noise_sigma=0.0,
                       sp_model="gauss", n_T=30, seed=base, beta=2133.0)
-    elif c == 2:
-        s = SceneSpec(CONFIG_NAMES[2], K=5, H=480, W=640, baselines=_sym(5), ref=2, D=64,
+    elif name == "plain":
+        s = SceneSpec(WORKLOAD_NAMES["plain"], K=5, H=480, W=640, baselines=_sym(5), ref=2, D=64,
                       n_iters=10, texture="perlin", n_planes=4, slanted=True, bg_disp=(2, 20),
                       dyn_kind="ellipse", n_dyn=3, dyn_disp=(25, 50), dyn_cover=(0.20, 0.40),
                       noise_sigma=2.0 / 255.0, sp_model="blurflip", n_T=200, seed=base)
-    elif c == 3:
-        s = SceneSpec(CONFIG_NAMES[3], K=5, H=960, W=1280, baselines=_sym(5), ref=2, D=128,
+    elif name == "precision":
+        s = SceneSpec(WORKLOAD_NAMES["precision"], K=5, H=960, W=1280, baselines=_sym(5), ref=2, D=128,
                       n_iters=10, storage="f16", texture="iid", n_planes=6, bg_disp=(2, 40),
                       dyn_kind="mixed", n_dyn=5, dyn_disp=(50, 120), dyn_cover=(0.34, 0.36),
                       noise_sigma=0.0, sp_model="gauss", n_T=1920, seed=base, beta=2133.0)
-    elif c == 5:
-        s = SceneSpec(CONFIG_NAMES[5], K=9, H=1080, W=1920, baselines=_sym(9), ref=4, D=192,
+    elif name == "large":
+        s = SceneSpec(WORKLOAD_NAMES["large"], K=9, H=1080, W=1920, baselines=_sym(9), ref=4, D=192,
                       n_iters=12, storage="bf16", texture="perlin", n_planes=6, slanted=True,
                       bg_disp=(4, 60), dyn_kind="mixed", n_dyn=5, dyn_disp=(70, 180),
                       dyn_cover=(0.49, 0.51), noise_sigma=2.0 / 255.0, sp_model="blurflip",
                       n_T=1350, seed=base)
-    else:
-        raise ValueError(f"config {c} is not a single-frame configuration")
     for k, v in over.items():
         setattr(s, k, v)
     return s

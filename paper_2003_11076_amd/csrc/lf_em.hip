@@ -156,7 +156,7 @@ EmKernel pick_em(int K, int st, bool frac, bool exh, bool sym) {
 // Launch helpers shared by the plain context and the server.
 // ---------------------------------------------------------------------------
 hipError_t launch_descriptors(const lf_params *p, const uint8_t *views, void *feat, hipStream_t s) {
-    dim3 block(256), grid((p->W + 255) / 256, p->H, p->K);
+    dim3 block(256), grid((p->W + 255) / 256, (p->H + kDescRows - 1) / kDescRows, p->K);
     switch (p->storage) {
         case LF_F32:
             hipLaunchKernelGGL(lf_descriptors_kernel<0>, grid, block, 0, s, views, (float2 *)feat, p->H, p->W);

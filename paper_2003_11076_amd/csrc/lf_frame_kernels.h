@@ -14,31 +14,36 @@
 namespace lfem {
 
 // ---------------------------------------------------------------------------
-// Descriptors.  grid (ceil(W/blockDim), H, K).
+// Descriptors.  grid (ceil(W/256), ceil(H/kDescRows), K), block 256: each
+// block stages the intensity sums L = R+G+B of its kDescRows rows plus one
+// row and one column of border on each side (replicated) in LDS, then every
+// lane takes the 3x3 Sobel responses of its column down the rows.
 // ---------------------------------------------------------------------------
+constexpr int kDescRows = 8;
+
 template <int ST>
 __global__ __launch_bounds__(256) void lf_descriptors_kernel(const uint8_t *__restrict__ views,
                                                              typename Pair<ST>::T *__restrict__ feat,
                                                              int H, int W) {
-    const int k = blockIdx.z, y = blockIdx.y;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= W) return;
+    __shared__ int16_t L[kDescRows + 2][256 + 2];
+    const int k = blockIdx.z, y0 = blockIdx.y * kDescRows, x0 = blockIdx.x * 256, tid = threadIdx.x;
     const uint8_t *v = views + (size_t)k * H * W * 3;
-    int L[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        const int yy = clampi(y + r - 1, 0, H - 1);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int xx = clampi(x + c - 1, 0, W - 1);
-            const uint8_t *px = v + ((size_t)yy * W + xx) * 3;
-            L[r][c] = (int)px[0] + (int)px[1] + (int)px[2];
-        }
+    for (int i = tid; i < (kDescRows + 2) * 258; i += 256) {
+        const int r = i / 258, c = i - r * 258;
+        const int yy = clampi(y0 + r - 1, 0, H - 1), xx = clampi(x0 + c - 1, 0, W - 1);
+        const uint8_t *px = v + ((size_t)yy * W + xx) * 3;
+        L[r][c] = (int16_t)((int)px[0] + (int)px[1] + (int)px[2]);
     }
-    const int gx = (L[0][2] - L[0][0]) + 2 * (L[1][2] - L[1][0]) + (L[2][2] - L[2][0]);
-    const int gy = (L[2][0] - L[0][0]) + 2 * (L[2][1] - L[0][1]) + (L[2][2] - L[0][2]);
+    __syncthreads();
+    const int x = x0 + tid;
+    if (x >= W) return;
     const float s = 1.0f / 4096.0f;  // exact: |G| <= 3060
-    feat[((size_t)k * H + y) * W + x] = make_pair<ST>((float)gx * s, (float)gy * s);
+    for (int r = 0; r < kDescRows && y0 + r < H; ++r) {
+        const int16_t *a = L[r] + tid, *b = L[r + 1] + tid, *c = L[r + 2] + tid;
+        const int gx = (a[2] - a[0]) + 2 * (b[2] - b[0]) + (c[2] - c[0]);
+        const int gy = (c[0] - a[0]) + 2 * (c[1] - a[1]) + (c[2] - a[2]);
+        feat[((size_t)k * H + y0 + r) * W + x] = make_pair<ST>((float)gx * s, (float)gy * s);
+    }
 }
 
 // ---------------------------------------------------------------------------

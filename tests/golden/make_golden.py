@@ -21,10 +21,10 @@ import lf_scenes as S  # noqa: E402
 import oracle as O  # noqa: E402
 
 CASES = [
-    # (name, scene configuration, overrides, storage, mode, EM iterations)
-    ("small-fp32-soft", 1, {}, "f32", "soft", 5),
-    ("small-fp16-hard", 1, {"H": 40, "dyn_kind": "ellipse", "dyn_cover": (0.05, 0.4)}, "f16", "hard", 4),
-    ("small-bf16-soft-perlin", 1, {"H": 48, "texture": "perlin", "sp_model": "blurflip", "seed": 1777, "dyn_kind": "ellipse", "dyn_cover": (0.05, 0.4)}, "bf16",
+    # (name, workload, overrides, storage, mode, EM iterations)
+    ("small-fp32-soft", "small", {}, "f32", "soft", 5),
+    ("small-fp16-hard", "small", {"H": 40, "dyn_kind": "ellipse", "dyn_cover": (0.05, 0.4)}, "f16", "hard", 4),
+    ("small-bf16-soft-perlin", "small", {"H": 48, "texture": "perlin", "sp_model": "blurflip", "seed": 1777, "dyn_kind": "ellipse", "dyn_cover": (0.05, 0.4)}, "bf16",
      "soft", 3),
 ]
 
@@ -33,14 +33,14 @@ def _digest(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()[:16]
 
 
-def summarize(name, c, over, storage, mode, n_iters):
-    spec = S.config_spec(c, **over)
+def summarize(name, workload, over, storage, mode, n_iters):
+    spec = S.workload_spec(workload, **over)
     fr = S.make_frame(spec)
     p = O.make_params(spec.K, spec.H, spec.W, spec.ref, spec.baselines, spec.d_min, spec.d_step, spec.D,
                       fr.beta, gamma=spec.gamma, sigma=spec.sigma, tau=spec.tau, storage=storage, mode=mode)
     r = O.reconstruct(p, fr.views, fr.S_P, fr.mu_T, n_iters)
     return {
-        "name": name, "config": c, "overrides": over, "storage": storage, "mode": mode, "n_iters": n_iters,
+        "name": name, "workload": workload, "overrides": over, "storage": storage, "mode": mode, "n_iters": n_iters,
         "inputs_sha256_16": _digest(fr.views) + _digest(fr.S_P) + _digest(fr.mu_T),
         "beta": float(fr.beta),
         "d_idx_histogram": np.bincount(r["d_idx"].ravel(), minlength=spec.D).tolist(),

@@ -20,9 +20,9 @@ def _say(msg):
 
 
 @pytest.mark.parametrize("mode", ["enum_soft", "enum_hard"])
-def test_config1_enumeration_teacher_forced(mode):
-    case = Case.from_frame(S.make_frame(S.config_spec(1)), storage="f32", mode=mode)
-    _say(f"config1 160x120 K=5 D=32 fp32 {mode} teacher-forced x3")
+def test_small_scene_enumeration_teacher_forced(mode):
+    case = Case.from_frame(S.make_frame(S.workload_spec("small")), storage="f32", mode=mode)
+    _say(f"small_frame 160x120 K=5 D=32 fp32 {mode} teacher-forced x3")
     teacher_forced(case, 3)
 
 
@@ -47,9 +47,9 @@ def test_small_enumeration_teacher_forced(K, H, W, D, b, dmin, dstep, st, mode):
     teacher_forced(case, 2)
 
 
-def test_config5_enumeration_sampled_rows():
-    case = Case.from_frame(S.make_frame(S.config_spec(5)), storage="bf16", mode="enum_soft")
-    _say("config5 1920x1080 K=9 D=192 bf16 enum_soft teacher-forced x2, rows 536..539")
+def test_large_enumeration_sampled_rows():
+    case = Case.from_frame(S.make_frame(S.workload_spec("large")), storage="bf16", mode="enum_soft")
+    _say("large 1920x1080 K=9 D=192 bf16 enum_soft teacher-forced x2, rows 536..539")
     teacher_forced(case, 2, rows=(536, 539))
 
 

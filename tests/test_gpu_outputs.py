@@ -41,7 +41,7 @@ def _half_pixel_exempt(case, d_idx):
 
 
 CASES = [
-    ("config1", None),
+    ("small_frame", None),
     ("small", dict(K=4, H=5, W=150, D=20, baselines=[-1.5, 0, 0.5, 2.25], d_min=-1.0, d_step=0.5, storage="f32")),
     ("small", dict(K=7, H=3, W=300, D=40, storage="bf16")),
     ("small", dict(K=3, H=4, W=90, D=16, storage="f16", baselines=[0, 1, 3])),
@@ -51,7 +51,7 @@ CASES = [
 @pytest.mark.parametrize("name,kw", CASES)
 def test_per_iteration_refocus_and_segmentation(name, kw):
     if kw is None:
-        case = Case.from_frame(S.make_frame(S.config_spec(1)), storage="f32")
+        case = Case.from_frame(S.make_frame(S.workload_spec("small")), storage="f32")
     else:
         kw = dict(kw)
         case = random_case(kw.pop("K"), kw.pop("H"), kw.pop("W"), kw.pop("D"), seed=31, **kw)

@@ -21,14 +21,14 @@ def _say(msg):
 
 
 @pytest.fixture(scope="module")
-def config1():
-    return S.make_frame(S.config_spec(1))
+def small_frame():
+    return S.make_frame(S.workload_spec("small"))
 
 
 @pytest.mark.parametrize("mode", ["soft", "hard"])
-def test_config1_teacher_forced(config1, mode):
-    case = Case.from_frame(config1, storage="f32", mode=mode)
-    _say(f"config1 160x120 K=5 D=32 fp32 {mode} teacher-forced x5")
+def test_small_teacher_forced(small_frame, mode):
+    case = Case.from_frame(small_frame, storage="f32", mode=mode)
+    _say(f"small_frame 160x120 K=5 D=32 fp32 {mode} teacher-forced x5")
     stats = teacher_forced(case, 5)
     assert sum(s.get("near_ties", 0) for s in stats[:-1]) < 0.01 * case.H * case.W * 5
 
@@ -56,30 +56,30 @@ def test_small_cases_teacher_forced(K, H, W, D, b, dmin, dstep, st, mode):
     teacher_forced(case, 3)
 
 
-def test_config2_full_size_fp32():
-    fr = S.make_frame(S.config_spec(2))
+def test_plain_full_size_fp32():
+    fr = S.make_frame(S.workload_spec("plain"))
     case = Case.from_frame(fr, storage="f32")
-    _say("config2 640x480 K=5 D=64 fp32 soft teacher-forced x10 (full frame)")
+    _say("plain 640x480 K=5 D=64 fp32 soft teacher-forced x10 (full frame)")
     teacher_forced(case, 10)
 
 
-def test_config3_fp16_sampled_rows():
-    fr = S.make_frame(S.config_spec(3))
+def test_precision_fp16_sampled_rows():
+    fr = S.make_frame(S.workload_spec("precision"))
     case = Case.from_frame(fr, storage="f16")
-    _say("config3 1280x960 K=5 D=128 fp16 teacher-forced x10, rows 472..488")
+    _say("precision 1280x960 K=5 D=128 fp16 teacher-forced x10, rows 472..488")
     teacher_forced(case, 10, rows=(472, 488))
 
 
-def test_config5_bf16_sampled_rows():
-    fr = S.make_frame(S.config_spec(5))
+def test_large_bf16_sampled_rows():
+    fr = S.make_frame(S.workload_spec("large"))
     case = Case.from_frame(fr, storage="bf16")
-    _say("config5 1920x1080 K=9 D=192 bf16 teacher-forced x12, rows 530..542")
+    _say("large 1920x1080 K=9 D=192 bf16 teacher-forced x12, rows 530..542")
     teacher_forced(case, 12, rows=(530, 542))
 
 
-def test_resume_is_bitwise(config1):
-    case = Case.from_frame(config1, storage="f32")
-    _say("config1 resume: iterate(3)+iterate(2) vs iterate(5)")
+def test_resume_is_bitwise(small_frame):
+    case = Case.from_frame(small_frame, storage="f32")
+    _say("small_frame resume: iterate(3)+iterate(2) vs iterate(5)")
     a = GpuRun(case)
     a.iterate(3)
     a.iterate(2)
@@ -92,9 +92,9 @@ def test_resume_is_bitwise(config1):
     assert np.array_equal(qa, qb) and np.array_equal(da, db) and np.array_equal(La, Lb)
 
 
-def test_host_and_device_inputs_agree(config1):
-    case = Case.from_frame(config1, storage="f16")
-    _say("config1 host vs device inputs, fp16")
+def test_host_and_device_inputs_agree(small_frame):
+    case = Case.from_frame(small_frame, storage="f16")
+    _say("small_frame host vs device inputs, fp16")
     a = GpuRun(case, device_inputs=True)
     a.iterate(4)
     ra = a.refocus()
@@ -107,9 +107,9 @@ def test_host_and_device_inputs_agree(config1):
         assert np.array_equal(x, y)
 
 
-def test_warm_start_uses_given_weights(config1):
-    case = Case.from_frame(config1, storage="f32")
-    _say("config1 warm start")
+def test_warm_start_uses_given_weights(small_frame):
+    case = Case.from_frame(small_frame, storage="f32")
+    _say("small_frame warm start")
     qw = np.random.default_rng(5).uniform(0, 1, (case.K, case.H, case.W)).astype(np.float32)
     run = GpuRun(case, q_warm=qw)
     q0, _, _ = run.state(with_d=False)
@@ -125,9 +125,9 @@ def test_warm_start_uses_given_weights(config1):
     assert np.all((d1 == ref["d_idx"]) | tie)
 
 
-def test_frame_objective_is_sum_of_pixels(config1):
-    case = Case.from_frame(config1, storage="f32")
-    _say("config1 frame objective")
+def test_frame_objective_is_sum_of_pixels(small_frame):
+    case = Case.from_frame(small_frame, storage="f32")
+    _say("small_frame frame objective")
     run = GpuRun(case)
     obj = run.iterate(3, objective=True)
     q, d, L = run.state()
@@ -136,9 +136,9 @@ def test_frame_objective_is_sum_of_pixels(config1):
     assert np.all(np.diff(obj) >= -1e-6 * np.abs(obj[1:]))
 
 
-def test_median_refocus(config1):
-    case = Case.from_frame(config1, storage="f32")
-    _say("config1 refocus with 3x3 median")
+def test_median_refocus(small_frame):
+    case = Case.from_frame(small_frame, storage="f32")
+    _say("small_frame refocus with 3x3 median")
     run = GpuRun(case)
     run.iterate(2)
     rgb0, d, q, hole = run.refocus(median=0)
@@ -149,10 +149,10 @@ def test_median_refocus(config1):
     assert np.array_equal(rgb3.astype(np.float64), want.astype(np.float32).astype(np.float64))
 
 
-def test_device_value_validation(config1):
+def test_device_value_validation(small_frame):
     import torch
     import paper_2003_11076_amd as LF
-    case = Case.from_frame(config1, storage="f32")
+    case = Case.from_frame(small_frame, storage="f32")
     _say("device-side S_P validation")
     sp = case.S_P.copy()
     sp[1, 5, 7] = np.nan
@@ -166,13 +166,13 @@ def test_device_value_validation(config1):
     assert e.value.status == LF.LF_EINVAL
 
 
-def test_deferred_value_check(config1):
+def test_deferred_value_check(small_frame):
     """LF_DEFERRED_CHECK: loads return at once; an invalid value is reported
     by the next call that waits for the stream, once, and valid frames that
     follow load and check clean."""
     import torch
     import paper_2003_11076_amd as LF
-    case = Case.from_frame(config1, storage="f32")
+    case = Case.from_frame(small_frame, storage="f32")
     _say("deferred device-side input check")
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream().cuda_stream
@@ -204,9 +204,9 @@ def test_deferred_value_check(config1):
         LF.lf_em_destroy(ctx)
 
 
-def test_state_calls_out_of_order(config1):
+def test_state_calls_out_of_order(small_frame):
     import paper_2003_11076_amd as LF
-    case = Case.from_frame(config1, storage="f32")
+    case = Case.from_frame(small_frame, storage="f32")
     _say("ESTATE paths")
     run = GpuRun(case)
     rgb = np.zeros((case.H, case.W, 3), np.float32)
@@ -219,9 +219,9 @@ def test_state_calls_out_of_order(config1):
     run.close()
 
 
-def test_free_running_agreement(config1):
-    case = Case.from_frame(config1, storage="f32")
-    _say("config1 free-running agreement")
+def test_free_running_agreement(small_frame):
+    case = Case.from_frame(small_frame, storage="f32")
+    _say("small_frame free-running agreement")
     run = GpuRun(case)
     run.iterate(case.n_iters)
     rgb, d, q, hole = run.refocus()
@@ -259,10 +259,10 @@ def test_fast_sweep_matches_exhaustive_bitwise(K, H, W, D, b, dmin, dstep, st, m
         assert np.array_equal(x, y)
 
 
-def test_fast_sweep_matches_exhaustive_config1(config1):
+def test_fast_sweep_matches_exhaustive_small(small_frame):
     import paper_2003_11076_amd as LF
-    case = Case.from_frame(config1, storage="f32")
-    _say("config1 fast vs exhaustive sweep, 5 iterations")
+    case = Case.from_frame(small_frame, storage="f32")
+    _say("small_frame fast vs exhaustive sweep, 5 iterations")
     out = []
     for flags in (0, LF.LF_EXHAUSTIVE_SWEEP):
         run = GpuRun(case, extra_flags=flags)
@@ -273,12 +273,12 @@ def test_fast_sweep_matches_exhaustive_config1(config1):
         assert np.array_equal(x, y)
 
 
-def test_config3_fp16_error_against_unquantised_oracle():
+def test_precision_fp16_error_against_unquantised_oracle():
     """Reported, not a parity bound: FP16 storage end to end (10 free-running
     iterations) against the FP64 oracle on unrounded inputs, rows 472..488."""
-    fr = S.make_frame(S.config_spec(3))
+    fr = S.make_frame(S.workload_spec("precision"))
     case = Case.from_frame(fr, storage="f16")
-    _say("config3 fp16 end to end vs the unquantised FP64 oracle, rows 472..488")
+    _say("precision fp16 end to end vs the unquantised FP64 oracle, rows 472..488")
     run = GpuRun(case)
     run.iterate(10)
     rgb, d, q, hole = run.refocus()

@@ -50,23 +50,23 @@ def _run(spec, fr, check_all_circles):
     return pts, mu
 
 
-def test_prior_config1():
-    fr = S.make_frame(S.config_spec(1))
-    _say("build prior config1 160x120 K=5 D=32")
+def test_prior_small():
+    fr = S.make_frame(S.workload_spec("small"))
+    _say("build prior small_frame 160x120 K=5 D=32")
     pts, mu = _run(fr.spec, fr, True)
     assert np.abs(mu - fr.disp_bg).max() == 0.0          # one plane: recovered exactly
 
 
-def test_prior_config2():
-    fr = S.make_frame(S.config_spec(2))
-    _say("build prior config2 640x480 K=5 D=64")
+def test_prior_plain():
+    fr = S.make_frame(S.workload_spec("plain"))
+    _say("build prior plain 640x480 K=5 D=64")
     pts, mu = _run(fr.spec, fr, False)
     err = np.abs(mu - fr.disp_bg)
     assert np.percentile(err, 50) < 1.0                  # sanity against the scene's truth
 
 
 def test_prior_small_asymmetric():
-    spec = S.config_spec(1, H=60, W=100, baselines=(0.0, 1.0, 2.0, 3.0, 4.0), ref=0, dyn_kind="ellipse",
+    spec = S.workload_spec("small", H=60, W=100, baselines=(0.0, 1.0, 2.0, 3.0, 4.0), ref=0, dyn_kind="ellipse",
                          dyn_cover=(0.05, 0.4))
     fr = S.make_frame(spec)
     _say("build prior 100x60 K=5 reference at the end of the array")

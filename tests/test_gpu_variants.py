@@ -22,9 +22,9 @@ def _say(msg):
 
 @pytest.mark.parametrize("flags", [WINDOW, DYN, WINDOW | DYN])
 @pytest.mark.parametrize("mode", ["soft", "hard"])
-def test_config1_variants_teacher_forced(flags, mode):
-    case = Case.from_frame(S.make_frame(S.config_spec(1)), storage="f32", mode=mode, flags=flags)
-    _say(f"config1 160x120 K=5 D=32 fp32 {mode} flags={flags:#x} teacher-forced x3")
+def test_small_scene_variants_teacher_forced(flags, mode):
+    case = Case.from_frame(S.make_frame(S.workload_spec("small")), storage="f32", mode=mode, flags=flags)
+    _say(f"small_frame 160x120 K=5 D=32 fp32 {mode} flags={flags:#x} teacher-forced x3")
     teacher_forced(case, 3)
 
 
@@ -47,9 +47,9 @@ def test_small_variants_teacher_forced(K, H, W, D, b, dmin, dstep, st, flags):
     teacher_forced(case, 3)
 
 
-def test_config5_window_sampled_rows():
-    case = Case.from_frame(S.make_frame(S.config_spec(5)), storage="bf16", flags=WINDOW | DYN)
-    _say("config5 1920x1080 K=9 D=192 bf16 window+dynamic-only teacher-forced x4, rows 530..538")
+def test_large_window_sampled_rows():
+    case = Case.from_frame(S.make_frame(S.workload_spec("large")), storage="bf16", flags=WINDOW | DYN)
+    _say("large 1920x1080 K=9 D=192 bf16 window+dynamic-only teacher-forced x4, rows 530..538")
     teacher_forced(case, 4, rows=(530, 538))
 
 
@@ -63,8 +63,8 @@ def _run(case, flags, n=3):
 
 
 def test_dynamic_only_equals_plain_on_dynamic_pixels():
-    case = Case.from_frame(S.make_frame(S.config_spec(1)), storage="f32")
-    _say("config1 dynamic-only vs plain, bitwise on the dynamic reference pixels")
+    case = Case.from_frame(S.make_frame(S.workload_spec("small")), storage="f32")
+    _say("small_frame dynamic-only vs plain, bitwise on the dynamic reference pixels")
     (rgb0, d0, q0, h0), L0 = _run(case, 0)
     (rgb1, d1, q1, h1), L1 = _run(case, DYN)
     run = GpuRun(case)

@@ -11,7 +11,7 @@ from lfcase import Case
 
 
 def test_reconstruction_shows_the_background_behind_the_object():
-    fr = S.make_frame(S.config_spec(1))
+    fr = S.make_frame(S.workload_spec("small"))
     c = Case.from_frame(fr, storage="f32")
     r = O.reconstruct(c.oracle_params(), c.views, c.S_P, c.mu_T, fr.spec.n_iters)
     # footprints beyond the frame edge are clamped: leave that band out
