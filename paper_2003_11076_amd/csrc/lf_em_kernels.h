@@ -502,7 +502,9 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
     float wt[K];   // sweep weights (all 1 when none is positive)
 #pragma unroll
     for (int k = 0; k < K; ++k) wt[k] = empty ? 1.0f : s.q[k];
-    const float invW = 1.0f / (empty ? (float)K : Q);
+    // hardware reciprocal (1 ulp): the exact energies of the fast and the
+    // exhaustive sweep both use this value
+    const float invW = __builtin_amdgcn_rcpf(empty ? (float)K : Q);
     const float cw = empty ? 0.0f : a.beta_p;
     const float mu = s.mu;
     int best_j = s.best_j;
@@ -541,8 +543,10 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
         // |A'|^2 = (cw / W) |A|^2 and S' = sg S, as c3 S' - |A'|^2 with
         // c3 = cw (1 - margin_k) / sg (the extra roundings stay well inside
         // margin_k's slack)
-        const float sg = sqrtf(cw * invW);
-        const float c3 = sg > 0.0f ? cw * (1.0f - a.margin_k) / sg : 0.0f;
+        // hardware square root and reciprocal: c3 * sg is cw (1 - margin_k)
+        // to a few ulps, far inside margin_k's slack
+        const float sg = __builtin_amdgcn_sqrtf(cw * invW);
+        const float c3 = sg > 0.0f ? cw * (1.0f - a.margin_k) * __builtin_amdgcn_rcpf(sg) : 0.0f;
         float ws[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) ws[k] = sg * wt[k];
