@@ -196,6 +196,7 @@ hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *m
 // LDS a dynamic-only launch adds after the windows: 256 lane slots and 4 counts
 static constexpr size_t kSlotsBytes = 260 * 4;
 
+
 EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
     EmArgs a{};
     // kernel view order: the reference first, then the others in array order
@@ -244,6 +245,10 @@ EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
     a.win_half = (p->flags & LF_PRIOR_WINDOW) ? 3.0f * p->sigma : 0.0f;
     a.dyn_only = (p->flags & LF_DYNAMIC_ONLY) ? 1 : 0;
     a.tau = p->tau_init;
+    a.d_absmax = (float)std::max(std::fabs((double)p->d_min),
+                                 std::fabs((double)p->d_min + (double)(p->D - 1) * p->d_step));
+    a.inv_step = (float)(1.0 / (double)p->d_step);
+    a.c_t2 = (float)(s2 * 0.69314718055994530942);
     return a;
 }
 

@@ -178,6 +178,9 @@ struct EmArgs {
     float win_half;       // > 0: the M-step searches only |d - mu| <= win_half
     int dyn_only;         // 1: only pixels with rho_ref < tau are reconstructed
     int lds_slots;        // dynamic-only: byte offset of 260 ints of LDS after the windows
+    float d_absmax;       // max |d_j| over the levels
+    float inv_step;       // 1 / d_step
+    float c_t2;           // 2 sigma^2 ln 2
     float tau;            // first-iteration threshold (dynamic-only test)
     int perm[kMaxViews];  // kernel view order -> array view index (perm[0] = reference)
     int bi[kMaxViews];    // integer baselines, kernel order (integer-shift path)
@@ -304,15 +307,14 @@ __device__ __forceinline__ void fetch(const typename Rec<ST>::T *win, const Wind
     }
 }
 
-// Exact energy at one level, E = cw * C - logP: two-pass q-weighted mean and
-// spread, summed in kernel view order; shared by the exact re-evaluation and
-// the exhaustive sweep so both give the same bits.
+// Exact energy at one level, E = cw * C - logP: two-pass weighted mean and
+// spread with the M-step weights wt, summed in kernel view order; shared by
+// the exact re-evaluation and the exhaustive sweep so both give the same bits.
+// With wt >= 0 and cw >= 0 the result is never below -P: C is a sum of
+// non-negative terms and the fma rounds monotonically.
 template <int K>
-__device__ __forceinline__ float exact_energy(const float2 (&f)[K], const float (&q)[K], bool empty, float invW,
-                                              float cw, float P, float &mx, float &my) {
-    float wt[K];   // the weights, all 1 when none is positive
-#pragma unroll
-    for (int k = 0; k < K; ++k) wt[k] = empty ? 1.0f : q[k];
+__device__ __forceinline__ float exact_energy(const float2 (&f)[K], const float (&wt)[K], float invW, float cw,
+                                              float P, float &mx, float &my) {
     float ax = 0.0f, ay = 0.0f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -484,165 +486,162 @@ __device__ __forceinline__ void search_range(const EmArgs &a, bool work, float m
     shi = __builtin_amdgcn_readfirstlane(wave_max(work ? whi : -1));
 }
 
-// One EM iteration of one active lane: M-step sweep over all levels with the
-// current weights, then the E-step and the objective at the chosen level.
-
-// [jlo, jhi] is the wave's prior window and [slo, shi] the union of its
-// lanes' search windows.
-template <int K, int ST, bool FRAC, bool EXH, bool SYM>
-__device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, const Window (&w)[K], const EmArgs &a,
-                                             int x, int jlo, int jhi, int slo, int shi, float Pc, Lane<K> &s,
-                                             bool with_obj) {
-    using R = typename Rec<ST>::T;
-    // ---- M-step: weights from the previous E-step (or the start) ----
+// M-step weights of one pixel (Eq. 6): the posteriors q_k, or all 1 when none
+// is positive (then the spread term is dropped, cw = 0); invW = 1 / sum wt.
+template <int K>
+__device__ __forceinline__ void mstep_weights(const EmArgs &a, const float (&q)[K], float (&wt)[K], float &invW,
+                                              float &cw) {
     float Q = 0.0f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) Q += s.q[k];
+    for (int k = 0; k < K; ++k) Q += q[k];
     const bool empty = !(Q > 0.0f);
-    float wt[K];   // sweep weights (all 1 when none is positive)
 #pragma unroll
-    for (int k = 0; k < K; ++k) wt[k] = empty ? 1.0f : s.q[k];
+    for (int k = 0; k < K; ++k) wt[k] = empty ? 1.0f : q[k];
     // hardware reciprocal (1 ulp): the exact energies of the fast and the
     // exhaustive sweep both use this value
-    const float invW = __builtin_amdgcn_rcpf(empty ? (float)K : Q);
-    const float cw = empty ? 0.0f : a.beta_p;
-    const float mu = s.mu;
-    int best_j = s.best_j;
-    const bool masked = a.win_half > 0.0f;   // uniform: search window set
+    invW = __builtin_amdgcn_rcpf(empty ? (float)K : Q);
+    cw = empty ? 0.0f : a.beta_p;
+}
 
-    if (EXH) {
-        // keeps the seed only when no level of the lane's window has a finite
-        // energy, i.e. when the window is empty and the seed is its fallback
-        float best_E = INFINITY;
-        for (int j = slo; j <= shi; ++j) {
-            float2 f[K];
-            float nn, mx, my;
-            f[0] = s.f0;
+// Level-0 LDS record index of each of a pixel's footprints (integer shifts).
+template <int K, bool FRAC>
+__device__ __forceinline__ void level0_index(const Window (&w)[K], const EmArgs &a, int x, int (&idx0)[K]) {
 #pragma unroll
-            for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, j, s.idx0[k], f[k], nn);
-            const float E = exact_energy<K>(f, s.q, empty, invW, cw, sweep_log_prior(a, j, mu, masked), mx, my);
-            if (E < best_E) {
-                best_E = E;
-                best_j = j;
-            }
-        }
-    } else {
-        // seed: exact energy at the previous level
-        float best_E;
-        {
-            float2 f[K];
-            float nn, mx, my;
-            f[0] = s.f0;
-#pragma unroll
-            for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, best_j, s.idx0[k], f[k], nn);
-            best_E = exact_energy<K>(f, s.q, empty, invW, cw, sweep_log_prior(a, best_j, mu, masked), mx, my);
-        }
-        // candidate test  E^ - M <= E_best  with the margin folded in:
-        //   cw (1 - margin_k) S - (cw / W) |A|^2  <=  E_best + margin_c + P_j,
-        // evaluated with the weights pre-scaled by sg = sqrt(cw / W), so that
-        // |A'|^2 = (cw / W) |A|^2 and S' = sg S, as c3 S' - |A'|^2 with
-        // c3 = cw (1 - margin_k) / sg (the extra roundings stay well inside
-        // margin_k's slack)
-        // hardware square root and reciprocal: c3 * sg is cw (1 - margin_k)
-        // to a few ulps, far inside margin_k's slack
-        const float sg = __builtin_amdgcn_sqrtf(cw * invW);
-        const float c3 = sg > 0.0f ? cw * (1.0f - a.margin_k) * __builtin_amdgcn_rcpf(sg) : 0.0f;
-        float ws[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) ws[k] = sg * wt[k];
-        const float A0x = ws[0] * s.f0.x, A0y = ws[0] * s.f0.y, S0 = ws[0] * s.n0;
-        float bound = best_E + a.margin_c;
-        float bound_c = bound + Pc;            // threshold where the prior is the constant ln gamma
-        float bound_hi = bound + a.prior_hi;   // threshold with the prior's upper bound
-        // Scores G consecutive levels from j0, then re-evaluates the
-        // candidates among them exactly, in increasing level order.
-        auto group = [&](auto Gc, int j0, bool inwin) {
-            constexpr int G = decltype(Gc)::value;
-            float2 f[G][K];
-            float lhs[G];
-#pragma unroll
-            for (int i = 0; i < G; ++i) {
-                f[i][0] = s.f0;
-                float ax = A0x, ay = A0y, S = S0;
-#pragma unroll
-                for (int k = 1; k < K; ++k) {
-                    float n;
-                    if constexpr (FRAC) {
-                        fetch<K, ST, FRAC>(win, w[k], a, k, x, j0 + i, 0, f[i][k], n);
-                    } else if constexpr (SYM) {
-                        // compile-time step per level: immediate LDS offsets
-                        const int b = sym_baseline<K>(k);   // folds once k is unrolled
-                        const R *base = win + s.idx0[k] - b * (b > 0 ? j0 + G - 1 : j0);
-                        const R r = base[b > 0 ? b * (G - 1 - i) : -b * i];
-                        f[i][k] = rec_f<ST>(r);
-                        n = rec_n<ST>(r);
-                    } else {
-                        const R r = win[s.idx0[k] - a.bi[k] * a.dstep_i * (j0 + i)];
-                        f[i][k] = rec_f<ST>(r);
-                        n = rec_n<ST>(r);
-                    }
-                    ax = fmaf(ws[k], f[i][k].x, ax);
-                    ay = fmaf(ws[k], f[i][k].y, ay);
-                    S = fmaf(ws[k], n, S);
-                }
-                lhs[i] = fmaf(c3, S, -fmaf(ax, ax, ay * ay));
-            }
-#pragma unroll
-            for (int i = 0; i < G; ++i) {
-                const int j = j0 + i;
-                // Inside the prior window the prior is evaluated only for
-                // levels that pass the test with its upper bound P_hi (few:
-                // the seed is close to the optimum); the current best level
-                // is already exact and is skipped.
-                float Pj = Pc;
-                bool cand;
-                if (inwin) {
-                    cand = false;
-                    if (lhs[i] <= bound_hi) {
-                        Pj = sweep_log_prior(a, j, mu, masked);
-                        cand = lhs[i] <= bound + Pj;
-                    }
-                } else {
-                    cand = lhs[i] <= bound_c;
-                }
-                if (cand && j != best_j) {
-                    float mx, my;
-                    const float E = exact_energy<K>(f[i], s.q, empty, invW, cw, Pj, mx, my);
-                    if (E < best_E || (E == best_E && j < best_j)) {
-                        best_E = E;
-                        best_j = j;
-                        bound = best_E + a.margin_c;
-                        bound_c = bound + Pc;
-                        bound_hi = bound + a.prior_hi;
-                    }
-                }
-            }
-        };
-        constexpr int G = sweep_group<K>();
-        auto sweep = [&](int jb, int je, bool inwin) {
-            int j = jb;
-            for (; j + G <= je; j += G) group(std::integral_constant<int, G>{}, j, inwin);
-            for (; j < je; ++j) group(std::integral_constant<int, 1>{}, j, inwin);
-        };
-        // levels [slo, shi] below, inside and above the prior window (a
-        // lane's search window lies inside its prior window)
-        const int lo = slo, hi = shi + 1;
-        const int j1 = min(max(jlo, lo), hi), j2 = min(max(jhi + 1, j1), hi);
-        sweep(lo, j1, false);
-        sweep(j1, j2, true);
-        sweep(j2, hi, false);
-    }
-    s.best_j = best_j;
+    for (int k = 0; k < K; ++k) idx0[k] = FRAC ? 0 : lane_index0(w[k], a.bi[k], a.dmin_i, x);
+}
 
-    // ---- E-step at the new disparity ----
+// Exact M-step energy of one pixel at level j.
+template <int K, int ST, bool FRAC>
+__device__ __forceinline__ float level_energy(const typename Rec<ST>::T *win, const Window (&w)[K], const EmArgs &a,
+                                              int x, const int (&idx0)[K], float2 f0, int j, const float (&wt)[K],
+                                              float invW, float cw, float mu, bool masked) {
     float2 f[K];
     float nn, mx, my;
-    f[0] = s.f0;
+    f[0] = f0;
 #pragma unroll
-    for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, best_j, s.idx0[k], f[k], nn);
-    (void)exact_energy<K>(f, s.q, empty, invW, cw, 0.0f, mx, my);
+    for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, j, idx0[k], f[k], nn);
+    return exact_energy<K>(f, wt, invW, cw, sweep_log_prior(a, j, mu, masked), mx, my);
+}
+
+// Fast M-step sweep of one pixel over levels jbase + [lo, hi): those in
+// jbase + [j1, j2) with the prior evaluated lazily, the others with the
+// constant ln gamma (levels outside the prior window).  ib[k] is the LDS
+// record index of view k at level jbase (integer shifts).  best_E and best_j
+// enter as the seed level and its exact energy and leave as the minimum,
+// ties to the lowest level.
+template <int K, int ST, bool FRAC, bool SYM>
+__device__ __forceinline__ void fast_sweep(const typename Rec<ST>::T *win, const Window (&w)[K], const EmArgs &a,
+                                           int x, const int (&ib)[K], int jbase, int lo, int j1, int j2, int hi,
+                                           float Pc, float phi, const float (&wt)[K], float invW, float cw, float2 f0,
+                                           float n0, float mu, bool masked, float &best_E, int &best_j) {
+    using R = typename Rec<ST>::T;
+    // candidate test  E^ - M <= E_best  with the margin folded in:
+    //   cw (1 - margin_k) S - (cw / W) |A|^2  <=  E_best + margin_c + P_j,
+    // evaluated with the weights pre-scaled by sg = sqrt(cw / W), so that
+    // |A'|^2 = (cw / W) |A|^2 and S' = sg S, as c3 S' - |A'|^2 with
+    // c3 = cw (1 - margin_k) / sg (the extra roundings stay well inside
+    // margin_k's slack)
+    // hardware square root and reciprocal: c3 * sg is cw (1 - margin_k)
+    // to a few ulps, far inside margin_k's slack
+    const float sg = __builtin_amdgcn_sqrtf(cw * invW);
+    const float c3 = sg > 0.0f ? cw * (1.0f - a.margin_k) * __builtin_amdgcn_rcpf(sg) : 0.0f;
+    float ws[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) ws[k] = sg * wt[k];
+    const float A0x = ws[0] * f0.x, A0y = ws[0] * f0.y, S0 = ws[0] * n0;
+    float bound = best_E + a.margin_c;
+    float bound_c = bound + Pc;            // threshold where the prior is the constant ln gamma
+    float bound_hi = bound + phi;          // threshold with the prior's upper bound over the levels
+    // Scores G consecutive levels from jbase + j0, then re-evaluates the
+    // candidates among them exactly, in increasing level order.
+    auto group = [&](auto Gc, int j0, bool inwin) {
+        constexpr int G = decltype(Gc)::value;
+        float2 f[G][K];
+        float lhs[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            f[i][0] = f0;
+            float ax = A0x, ay = A0y, S = S0;
+#pragma unroll
+            for (int k = 1; k < K; ++k) {
+                float n;
+                if constexpr (FRAC) {
+                    fetch<K, ST, FRAC>(win, w[k], a, k, x, jbase + j0 + i, 0, f[i][k], n);
+                } else if constexpr (SYM) {
+                    // compile-time step per level: immediate LDS offsets
+                    const int b = sym_baseline<K>(k);   // folds once k is unrolled
+                    const R *base = win + ib[k] - b * (b > 0 ? j0 + G - 1 : j0);
+                    const R r = base[b > 0 ? b * (G - 1 - i) : -b * i];
+                    f[i][k] = rec_f<ST>(r);
+                    n = rec_n<ST>(r);
+                } else {
+                    const R r = win[ib[k] - a.bi[k] * a.dstep_i * (j0 + i)];
+                    f[i][k] = rec_f<ST>(r);
+                    n = rec_n<ST>(r);
+                }
+                ax = fmaf(ws[k], f[i][k].x, ax);
+                ay = fmaf(ws[k], f[i][k].y, ay);
+                S = fmaf(ws[k], n, S);
+            }
+            lhs[i] = fmaf(c3, S, -fmaf(ax, ax, ay * ay));
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const int j = jbase + j0 + i;
+            // Inside the prior window the prior is evaluated only for
+            // levels that pass the test with its upper bound P_hi (few:
+            // the seed is close to the optimum); the current best level
+            // is already exact and is skipped.
+            float Pj = Pc;
+            bool cand;
+            if (inwin) {
+                cand = false;
+                if (lhs[i] <= bound_hi) {
+                    Pj = sweep_log_prior(a, j, mu, masked);
+                    cand = lhs[i] <= bound + Pj;
+                }
+            } else {
+                cand = lhs[i] <= bound_c;
+            }
+            if (cand && j != best_j) {
+                float mx, my;
+                const float E = exact_energy<K>(f[i], wt, invW, cw, Pj, mx, my);
+                if (E < best_E || (E == best_E && j < best_j)) {
+                    best_E = E;
+                    best_j = j;
+                    bound = best_E + a.margin_c;
+                    bound_c = bound + Pc;
+                    bound_hi = bound + phi;
+                }
+            }
+        }
+    };
+    constexpr int G = sweep_group<K>();
+    auto sweep = [&](int jb, int je, bool inwin) {
+        int j = jb;
+        for (; j + G <= je; j += G) group(std::integral_constant<int, G>{}, j, inwin);
+        for (; j < je; ++j) group(std::integral_constant<int, 1>{}, j, inwin);
+    };
+    sweep(lo, j1, false);
+    sweep(j1, j2, true);
+    sweep(j2, hi, false);
+}
+
+// E-step (Eq. 7) of one pixel at level j with the M-step weights wt: the
+// static posterior of each ray (or the enumeration E-step) and, with_obj,
+// the pixel's objective.
+template <int K, int ST, bool FRAC>
+__device__ __forceinline__ void estep(const typename Rec<ST>::T *win, const Window (&w)[K], const EmArgs &a, int x,
+                                      const int (&idx0)[K], float2 f0, int j, const float (&wt)[K], float invW,
+                                      float cw, Lane<K> &s, bool with_obj) {
+    float2 f[K];
+    float nn, mx, my;
+    f[0] = f0;
+#pragma unroll
+    for (int k = 1; k < K; ++k) fetch<K, ST, FRAC>(win, w[k], a, k, x, j, idx0[k], f[k], nn);
+    (void)exact_energy<K>(f, wt, invW, cw, 0.0f, mx, my);
     float L = 0.0f;
-    if (with_obj) L = log_prior(a, best_j, mu);
+    if (with_obj) L = log_prior(a, j, s.mu);
     if (a.mode >= 2) {
         s.L = L + enum_estep<K>(f, mx, my, a, s);
         return;
@@ -668,6 +667,235 @@ __device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, con
         }
     }
     s.L = L;
+}
+
+// Sweep range of the levels the prior window splits [slo, shi] into: below,
+// inside [j1, j2) and above it (a lane's search window lies inside its prior
+// window).
+__device__ __forceinline__ void window_split(int jlo, int jhi, int slo, int shi, int &lo, int &j1, int &j2, int &hi) {
+    lo = slo;
+    hi = shi + 1;
+    j1 = min(max(jlo, lo), hi);
+    j2 = min(max(jhi + 1, j1), hi);
+}
+
+// One EM iteration of one active lane: M-step sweep over all levels with the
+// current weights, then the E-step and the objective at the chosen level.
+// [jlo, jhi] is the wave's prior window and [slo, shi] the union of its
+// lanes' search windows.
+template <int K, int ST, bool FRAC, bool EXH, bool SYM>
+__device__ __forceinline__ void em_iteration(const typename Rec<ST>::T *win, const Window (&w)[K], const EmArgs &a,
+                                             int x, int jlo, int jhi, int slo, int shi, float Pc, Lane<K> &s,
+                                             bool with_obj) {
+    float wt[K], invW, cw;
+    mstep_weights<K>(a, s.q, wt, invW, cw);
+    const float mu = s.mu;
+    int best_j = s.best_j;
+    const bool masked = a.win_half > 0.0f;   // uniform: search window set
+    if (EXH) {
+        // keeps the seed only when no level of the lane's window has a finite
+        // energy, i.e. when the window is empty and the seed is its fallback
+        float best_E = INFINITY;
+        for (int j = slo; j <= shi; ++j) {
+            const float E = level_energy<K, ST, FRAC>(win, w, a, x, s.idx0, s.f0, j, wt, invW, cw, mu, masked);
+            if (E < best_E) {
+                best_E = E;
+                best_j = j;
+            }
+        }
+    } else {
+        // seed: exact energy at the previous level
+        float best_E = level_energy<K, ST, FRAC>(win, w, a, x, s.idx0, s.f0, best_j, wt, invW, cw, mu, masked);
+        int lo, j1, j2, hi;
+        window_split(jlo, jhi, slo, shi, lo, j1, j2, hi);
+        fast_sweep<K, ST, FRAC, SYM>(win, w, a, x, s.idx0, 0, lo, j1, j2, hi, Pc, a.prior_hi, wt, invW, cw, s.f0,
+                                     s.n0, mu, masked, best_E, best_j);
+    }
+    s.best_j = best_j;
+    estep<K, ST, FRAC>(win, w, a, x, s.idx0, s.f0, best_j, wt, invW, cw, s, with_obj);
+}
+
+// Levels that can still win under the prior bound of the M-step (Eq. 6):
+// the energy E_j = cw C_j - P_j of a level is never below -P_j (C_j >= 0,
+// see exact_energy), so a level whose log prior P_j, as the kernel
+// evaluates it, is below -E_best can neither beat nor tie the best energy
+// found so far.  P_j falls off with |d_j - mu|, so the levels that remain
+// form an interval [jl, jh] around mu; returns false when the bound excludes
+// nothing (E_best not below -ln gamma, or not finite).  The slacks cover
+// the error of the evaluated prior (hardware exp2 and log2 and the rounding
+// of (d_j - mu)^2 c: under 2e-5 relative on the exponential, 1e-5 (1 + |P|)
+// on P), of this function's own hardware exp2, log2 and square root, and
+// the rounding of d_j - mu and of the level position of mu.
+__device__ __forceinline__ bool prior_interval(const EmArgs &a, float best_E, float mu, int &jl, int &jh) {
+    const float tgt = -best_E - 1e-5f * (1.0f + fabsf(best_E));
+    // lower bound of exp(tgt) - gamma (the subtraction is exact while
+    // exp(tgt) <= 2 gamma)
+    const float G = __builtin_amdgcn_exp2f(tgt * kLog2e) * (1.0f - 0x1p-16f) - a.gamma;
+    if (!(G > 0.0f)) return false;
+    // exp(-t^2 / (2 sigma^2)) < G (1 - 1e-4) for |t| > tmax, where
+    // tmax^2 = -ln(G (1 - 1e-4)) 2 sigma^2 = -log2(G (1 - 1e-4)) 2 sigma^2 ln 2
+    const float l2 = __builtin_amdgcn_logf(fminf(G * (1.0f - 1e-4f), 1.0f));
+    const float tmax = __builtin_amdgcn_sqrtf(fmaxf(-l2, 0.0f) * a.c_t2) * (1.0f + 1e-4f) +
+                       0x1p-20f * (a.d_absmax + fabsf(mu));
+    const float m = (mu - a.d_min) * a.inv_step, r = tmax * a.inv_step;
+    jl = (int)fmaxf(ceilf(m - r - 0.01f), 0.0f);
+    jh = (int)fminf(floorf(m + r + 0.01f), (float)(a.D - 1));
+    return true;
+}
+
+// (E, j) <- the smaller of (E, j) and (E2, j2) in the sweep's order: lower
+// energy, then lower level.
+__device__ __forceinline__ void lex_min(float &E, int &j, float E2, int j2) {
+    if (E2 < E || (E2 == E && j2 < j)) {
+        E = E2;
+        j = j2;
+    }
+}
+
+// Position of the u-th set bit (u counted from 0) of a 64-bit mask with more
+// than u set bits.
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int u) {
+    int pos = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int p = pos + step;
+        if (__popcll(m & ((1ull << p) - 1ull)) <= u) pos = p;
+    }
+    return pos;
+}
+
+// Sweep overhead of handing a pixel's levels to other lanes, in levels.
+constexpr int kShareCost = 6;
+
+// One EM iteration of one wave with the M-step work rebalanced inside the
+// wave (integer shifts, fast sweep).  Each pixel's seed energy bounds the
+// levels that can still win (prior_interval).  A wave sweeps until its
+// slowest lane is done, so instead of every lane sweeping its own levels:
+//   * pixels with a bounded interval sweep a window of the wave's widest
+//     interval, placed over their own;
+//   * the levels of the pixels the bound leaves unbounded are cut into cp
+//     chunks each (cp a power of two, cp * n_unbounded <= 64), one chunk per
+//     lane: the pixel's M-step inputs come over by lane shuffles, each chunk
+//     is swept from the pixel's seed, and the chunk results are reduced
+//     back with the sweep's order (lower energy, then lower level).
+// The wave does this when it takes fewer levels than one full sweep, else
+// every lane sweeps its whole range.  The levels excluded cannot be the
+// minimum and the reduction keeps the tie rule, so the result is the full
+// sweep's, bit for bit.
+template <int K, int ST, bool SYM>
+__device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win, const Window (&w)[K],
+                                                 const EmArgs &a, int x, bool work, int jlo, int jhi, int slo,
+                                                 int shi, float Pc, Lane<K> &s, bool with_obj) {
+    using R = typename Rec<ST>::T;
+    const int lane = threadIdx.x & 63;
+    const bool masked = a.win_half > 0.0f;
+    const int x_idle = blockIdx.x * a.tile;   // a column inside every window, for lanes without a pixel
+
+    float wt[K], invW = 0.0f, cw = 0.0f, best_E = INFINITY;
+    int best_j = s.best_j;
+    int idx0[K];
+    level0_index<K, false>(w, a, work ? x : x_idle, idx0);
+    const R r0 = win[idx0[0]];
+    const float2 f0 = rec_f<ST>(r0);
+    const float n0 = rec_n<ST>(r0);
+    int jl = 0, jh = -1;
+    bool bnd = false;
+    if (work) {
+        mstep_weights<K>(a, s.q, wt, invW, cw);
+        best_E = level_energy<K, ST, false>(win, w, a, x, idx0, f0, best_j, wt, invW, cw, s.mu, masked);
+        bnd = prior_interval(a, best_E, s.mu, jl, jh);
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) wt[k] = 0.0f;
+    }
+    const bool unb = work && !bnd;
+    const uint64_t um = __ballot(unb);
+    const int nu = __popcll(um);
+    const bool anyb = __ballot(bnd) != 0;
+    // bounded windows: the wave's widest extents below and above each lane's
+    // nearest level c to mu, so that neighbouring lanes (whose c mostly
+    // agree) read neighbouring LDS records
+    const int c = nearest_level(a, s.mu);
+    const int el = __builtin_amdgcn_readfirstlane(wave_max(bnd ? max(c - jl, 0) : 0));
+    const int er = __builtin_amdgcn_readfirstlane(wave_max(bnd ? max(jh - c, 0) : 0));
+    const int wl = el + er + 1;
+    int cp = 1;
+    while (nu > 0 && cp * 2 * nu <= 64) cp *= 2;
+    // odd chunk lengths: the cp chunks of a pixel then start on different
+    // LDS banks
+    const int chunk = min(((a.D + cp - 1) / cp) | 1, a.D);
+    const int cost = (anyb ? wl : 0) + (nu > 0 ? chunk + kShareCost : 0);
+
+    if (cost >= a.D) {
+        // every lane sweeps its whole range
+        if (work) {
+            int lo, j1, j2, hi;
+            window_split(jlo, jhi, slo, shi, lo, j1, j2, hi);
+            fast_sweep<K, ST, false, SYM>(win, w, a, x, idx0, 0, lo, j1, j2, hi, Pc, a.prior_hi, wt, invW, cw, f0,
+                                          n0, s.mu, masked, best_E, best_j);
+        }
+    } else {
+        // bounded pixels: wl levels from js, covering [jl, jh], inside the range
+        if (anyb) {
+            const int js = min(max(c - el, 0), a.D - wl);
+            int ib[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) ib[k] = idx0[k] - a.bi[k] * a.dstep_i * js;
+            if (bnd)
+                fast_sweep<K, ST, false, SYM>(win, w, a, x, ib, js, 0, 0, wl, wl, Pc, a.prior_hi, wt, invW, cw, f0, n0,
+                                              s.mu, masked, best_E, best_j);
+        }
+        // unbounded pixels: lane h sweeps chunk (h % cp) of the (h / cp)-th one
+        if (nu > 0) {
+            const int u = lane / cp;
+            const bool helper = u < nu;
+            const int src = nth_set_bit(um, helper ? u : 0);
+            float hwt[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) hwt[k] = __shfl(wt[k], src, 64);
+            const float hinvW = __shfl(invW, src, 64), hcw = __shfl(cw, src, 64), hmu = __shfl(s.mu, src, 64);
+            float hE = __shfl(best_E, src, 64);
+            int hj = __shfl(best_j, src, 64);
+            // every shuffle runs on the whole wave: a lane shuffle reads
+            // nothing from lanes switched off by a branch
+            const int xs = __shfl(x, src, 64);
+            const int hx = helper ? xs : x_idle;
+            int hidx0[K];
+            level0_index<K, false>(w, a, hx, hidx0);
+            const R hr0 = win[hidx0[0]];
+            const int jb = min((lane % cp) * chunk, a.D - chunk);
+            // upper bound of the prior over the chunk: its value at the
+            // chunk's level nearest mu, plus the evaluation's error
+            const int jn = min(max(nearest_level(a, hmu), jb), jb + chunk - 1);
+            const float pn = log_prior(a, jn, hmu);
+            const float phi = pn + 1e-5f * (1.0f + fabsf(pn));
+            int ib[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) ib[k] = hidx0[k] - a.bi[k] * a.dstep_i * jb;
+            if (helper)
+                fast_sweep<K, ST, false, SYM>(win, w, a, hx, ib, jb, 0, 0, chunk, chunk, Pc, phi, hwt, hinvW, hcw,
+                                              rec_f<ST>(hr0), rec_n<ST>(hr0), hmu, masked, hE, hj);
+            // reduce each pixel's cp chunks (aligned groups of cp lanes)
+            for (int o = 1; o < cp; o <<= 1) {
+                const float E2 = __shfl_xor(hE, o, 64);
+                const int j2 = __shfl_xor(hj, o, 64);
+                lex_min(hE, hj, E2, j2);
+            }
+            const int rank = __popcll(um & ((1ull << lane) - 1ull));
+            const int jr = __shfl(hj, (unb ? rank : 0) * cp, 64);
+            if (unb) best_j = jr;
+        }
+    }
+    s.best_j = best_j;
+    if (work) {
+        // the E-step's inputs again (the same bits): cheaper than keeping
+        // them live through the sweeps
+        float wt2[K], invW2, cw2;
+        mstep_weights<K>(a, s.q, wt2, invW2, cw2);
+        int idx2[K];
+        level0_index<K, false>(w, a, x, idx2);
+        estep<K, ST, false>(win, w, a, x, idx2, rec_f<ST>(win[idx2[0]]), best_j, wt2, invW2, cw2, s, with_obj);
+    }
 }
 
 // Descriptor pair of storage ST as a pair of record storage RS (RS == ST,
@@ -784,7 +1012,11 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
     const int block_id = blockIdx.y * gridDim.x + blockIdx.x;
     for (int it = 0; it < a.n_iters; ++it) {
         const bool with_obj = a.want_obj || it == a.n_iters - 1;
-        if (work) em_iteration<K, RS, FRAC, EXH, SYM>(win, w, a, x, jlo, jhi, slo, shi, Pc, s, with_obj);
+        if constexpr (!EXH && !FRAC) {
+            shared_iteration<K, RS, SYM>(win, w, a, x, work, jlo, jhi, slo, shi, Pc, s, with_obj);
+        } else {
+            if (work) em_iteration<K, RS, FRAC, EXH, SYM>(win, w, a, x, jlo, jhi, slo, shi, Pc, s, with_obj);
+        }
         if (!with_obj) continue;
         // ---- FP64 block sum of the objective ----
         double sum = wave_sum(work ? (double)s.L : 0.0);

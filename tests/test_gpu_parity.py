@@ -273,6 +273,59 @@ def test_fast_sweep_matches_exhaustive_small(small_frame):
         assert np.array_equal(x, y)
 
 
+def _fast_vs_exhaustive(case, n_iters, extra=0):
+    import paper_2003_11076_amd as LF
+    out = []
+    for flags in (extra, extra | LF.LF_EXHAUSTIVE_SWEEP):
+        run = GpuRun(case, extra_flags=flags)
+        obj = run.iterate(n_iters, objective=True)
+        out.append(run.state() + (obj,))
+        run.close()
+    for x, y in zip(out[0], out[1]):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("workload", ["plain", "precision", "large"])
+def test_pruned_sweep_matches_exhaustive_on_scenes(workload):
+    """Structured scenes at full size, where most pixels' seed energies bound
+    the levels that can still win and the workgroups sweep those pixels in
+    narrow windows: every iteration's levels, weights and objective are the
+    exhaustive sweep's, bit for bit."""
+    fr = S.make_frame(S.workload_spec(workload))
+    case = Case.from_frame(fr)
+    _say(f"{workload} {case.W}x{case.H} K={case.K} D={case.D} {case.storage}: pruned fast vs exhaustive, "
+         f"{case.n_iters} iterations")
+    _fast_vs_exhaustive(case, case.n_iters)
+
+
+@pytest.mark.parametrize("label,mu_shift,sigma,gamma,mode", [
+    ("prior below the level range", -9.0, 2.0, 0.05, "soft"),
+    ("prior above the level range", 30.0, 2.0, 0.05, "soft"),
+    ("narrow prior", 0.0, 0.35, 0.05, "soft"),
+    ("prior wider than the level range", 0.0, 40.0, 0.05, "soft"),
+    ("small gamma", 0.0, 2.0, 1e-6, "hard"),
+    ("large gamma", 0.0, 2.0, 0.9, "soft"),
+])
+def test_pruned_sweep_edges_match_exhaustive(small_frame, label, mu_shift, sigma, gamma, mode):
+    """Windows clipped at either end of the level range, radii from one level
+    to wider than the range, and gamma from tiny to close to 1."""
+    case = Case.from_frame(small_frame, storage="f32", mode=mode, sigma=np.float32(sigma),
+                           gamma=np.float32(gamma))
+    case.mu_T = (case.mu_T + np.float32(mu_shift)).astype(np.float32)
+    _say(f"small_frame pruned fast vs exhaustive: {label} (mu {mu_shift:+}, sigma {sigma}, gamma {gamma}, {mode})")
+    _fast_vs_exhaustive(case, 5)
+
+
+@pytest.mark.parametrize("variant", ["dynamic-only", "window"])
+def test_pruned_sweep_variants_match_exhaustive_on_scene(variant):
+    import paper_2003_11076_amd as LF
+    fr = S.make_frame(S.workload_spec("plain"))
+    case = Case.from_frame(fr)
+    flag = LF.LF_DYNAMIC_ONLY if variant == "dynamic-only" else LF.LF_PRIOR_WINDOW
+    _say(f"plain {variant}: pruned fast vs exhaustive, 10 iterations")
+    _fast_vs_exhaustive(case, 10, extra=flag)
+
+
 def test_precision_fp16_error_against_unquantised_oracle():
     """Reported, not a parity bound: FP16 storage end to end (10 free-running
     iterations) against the FP64 oracle on unrounded inputs, rows 472..488."""
