@@ -9,11 +9,17 @@ fused launch) and lf_refocus (outputs stay in device memory).  The metric is
 EM-iteration throughput H*W*D*K*I / t in G(pixel*disparity*view) per second
 over the K timed steps, plus the p50/p99 of per-frame latency.
 
+The timed frames are dealt round robin to --streams contexts (default 2),
+each on its own HIP stream, so that one frame's kernels start while the last
+waves of the previous frame's EM launch are still finishing.  Latency is
+taken separately, one frame at a time on an otherwise idle GPU.
+
 The roofline object refers to the dominant kernel (the fused EM iterations):
 its algorithmic work is 6F + 12/K flops per (pixel, disparity, view) unit
 and iteration (F = 2 descriptor components), its duration is measured with
-HIP events on the stream it is launched on, and the peak is MI355X's FP32
-vector rate.  The CPU baseline is the FP64 oracle on the host cores.
+HIP events on the stream it is launched on, in the one-frame-at-a-time loop
+(a launch alone on the GPU), and the peak is MI355X's FP32 vector rate.  The
+CPU baseline is the FP64 oracle on the host cores.
 """
 from __future__ import annotations
 
@@ -64,6 +70,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="plain", choices=["small", "plain", "precision", "large"])
+    ap.add_argument("--streams", type=int, default=2,
+                    help="contexts (one HIP stream each) the timed frames are dealt to, round robin")
     ap.add_argument("--storage", default=None, choices=["f32", "f16", "bf16"])
     ap.add_argument("--mode", default="soft", choices=["soft", "hard"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -362,28 +370,34 @@ def main():
     sp = torch.from_numpy(frame.S_P).to(dev)
     mu = torch.from_numpy(frame.mu_T).to(dev)
     K, H, W, D, I = spec.K, spec.H, spec.W, spec.D, spec.n_iters
-    rgb = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
-    d_idx = torch.empty((H, W), dtype=torch.int32, device=dev)
-    q = torch.empty((K, H, W), dtype=torch.float32, device=dev)
-    hole = torch.empty((H, W), dtype=torch.uint8, device=dev)
     # device-resident inputs and outputs; the value check of the inputs is
     # read once after the timed frames instead of after each load, so frames
-    # queue back to back on the stream
+    # queue back to back on the streams
     flags = LF.LF_INPUTS_ON_DEVICE | LF.LF_OUTPUTS_ON_DEVICE | LF.LF_DEFERRED_CHECK
     p = LF.make_params(K, H, W, spec.ref, spec.baselines, spec.d_min, spec.d_step, D, frame.beta,
                        gamma=spec.gamma, sigma=spec.sigma, tau_init=spec.tau, storage=storage, mode=args.mode,
                        flags=flags)
+    n_streams = max(1, args.streams)
+    # default-priority streams; stream 0 is the current one
+    streams = [stream] + [torch.cuda.Stream(device=dev) for _ in range(n_streams - 1)]
     torch.cuda.synchronize()
-    ctx = LF.lf_em_init(p, views, sp, mu, hip_stream=stream.cuda_stream)
+    ctxs, outs = [], []
+    for st in streams:
+        ctxs.append(LF.lf_em_init(p, views, sp, mu, hip_stream=st.cuda_stream))
+        outs.append((torch.empty((H, W, 3), dtype=torch.float32, device=dev),
+                     torch.empty((H, W), dtype=torch.int32, device=dev),
+                     torch.empty((K, H, W), dtype=torch.float32, device=dev),
+                     torch.empty((H, W), dtype=torch.uint8, device=dev)))
 
-    def step(ev=None):
+    def step(i, ev=None):
+        ctx, out, st = ctxs[i % n_streams], outs[i % n_streams], streams[i % n_streams]
         LF.lf_em_load(ctx, views, sp, mu)
         if ev is not None:
-            ev[0].record(stream)
+            ev[0].record(st)
         LF.lf_em_iterate(ctx, I)
         if ev is not None:
-            ev[1].record(stream)
-        LF.lf_refocus(ctx, rgb, d_idx, q, hole, 0)
+            ev[1].record(st)
+        LF.lf_refocus(ctx, *out, 0)
 
     if args.calib_copy:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the
@@ -395,29 +409,33 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     log(args, f"warmup {args.warmup} steps")
-    for _ in range(args.warmup):
-        step()
+    for i in range(args.warmup):
+        step(i)
     torch.cuda.synchronize()
 
-    log(args, f"timing {args.steps} steps")
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    log(args, f"timing {args.steps} steps over {n_streams} stream(s)")
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
-        step(evs[i])
+        step(i)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
-    LF.lf_em_check(ctx)                       # the inputs of every timed frame were valid
-    em_ms = np.array([a.elapsed_time(b) for a, b in evs])
-    # latency of one frame on an otherwise idle stream (not part of the value)
+    for ctx in ctxs:
+        LF.lf_em_check(ctx)                   # the inputs of every timed frame were valid
+    # one frame at a time on an otherwise idle GPU: latency, and the EM
+    # launch's duration (HIP events on its stream) for the roofline
+    n_lat = min(args.steps, 100)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_lat)]
     lat = []
-    for i in range(min(args.steps, 100)):
+    for i in range(n_lat):
         t0 = time.perf_counter()
-        step()
+        step(0, evs[i])
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
-    LF.lf_em_check(ctx)
-    LF.lf_em_destroy(ctx)
+    em_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    for ctx in ctxs:
+        LF.lf_em_check(ctx)
+        LF.lf_em_destroy(ctx)
 
     units = H * W * D * K * I
     value = units * args.steps / t_total / 1e9
@@ -443,7 +461,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded scene generator, uint8 views, float32 S_P and mu_T)",
         "config": {"workload": spec.name, "K": K, "H": H, "W": W, "D": D, "em_iters": I, "storage": storage,
-                   "mode": args.mode, "parallelism": "single-gpu"},
+                   "mode": args.mode, "parallelism": "single-gpu", "streams": n_streams},
         "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "frames_per_s": args.steps / t_total,

@@ -144,11 +144,14 @@ size_t rec_bytes(int storage) { return storage == LF_F32 ? 16 : 8; }
 // ---------------------------------------------------------------------------
 // Kernel dispatch over (K, storage, integer/fractional shifts, sweep kind).
 // ---------------------------------------------------------------------------
-EmKernel pick_em(int K, int st, bool frac, bool exh, bool sym) {
-    switch (st) {
-        case LF_F32: return pick_em_f32(K, frac, exh, sym);
-        case LF_F16: return pick_em_f16(K, frac, exh, sym);
-        default: return pick_em_bf16(K, frac, exh, sym);
+// The fast sweep shares levels across a wave's lanes unless a search window
+// is set (its short ranges gain too little to pay for the prior bound).
+EmKernel pick_em(const lf_params *p, const Geometry &g) {
+    const bool exh = (p->flags & LF_EXHAUSTIVE_SWEEP) != 0, share = !(p->flags & LF_PRIOR_WINDOW);
+    switch (p->storage) {
+        case LF_F32: return pick_em_f32(p->K, g.frac, exh, g.sym, share);
+        case LF_F16: return pick_em_f16(p->K, g.frac, exh, g.sym, share);
+        default: return pick_em_bf16(p->K, g.frac, exh, g.sym, share);
     }
 }
 
@@ -253,7 +256,7 @@ EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
 }
 
 hipError_t launch_em(const lf_params *p, const Geometry &g, EmArgs a, int tile, size_t lds, hipStream_t s) {
-    EmKernel kern = pick_em(p->K, p->storage, g.frac, (p->flags & LF_EXHAUSTIVE_SWEEP) != 0, g.sym);
+    EmKernel kern = pick_em(p, g);
     a.tile = tile;
     if (a.dyn_only) {
         a.lds_slots = (int)((lds + 15) / 16 * 16);
@@ -386,7 +389,7 @@ static lf_status ctx_alloc(lf_ctx *c) {
     }
     int vgprs = 0;
     {
-        EmKernel kern = pick_em(p.K, p.storage, c->g.frac, (p.flags & LF_EXHAUSTIVE_SWEEP) != 0, c->g.sym);
+        EmKernel kern = pick_em(&p, c->g);
         hipFuncAttributes fa;
         if (kern && hipFuncGetAttributes(&fa, (const void *)kern) == hipSuccess) vgprs = fa.numRegs;
         (void)hipGetLastError();

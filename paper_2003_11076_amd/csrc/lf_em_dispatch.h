@@ -8,34 +8,40 @@
 
 namespace lfem {
 
-template <int K, int ST>
-static EmKernel pick_em_k(bool frac, bool exh, bool sym) {
-    if (exh)
-        return frac ? (EmKernel)lf_em_kernel<K, ST, true, true, false> : (EmKernel)lf_em_kernel<K, ST, false, true, false>;
-    if (frac) return (EmKernel)lf_em_kernel<K, ST, true, false, false>;
+template <int K, int ST, int SW>
+static EmKernel pick_em_fast(bool sym) {
     // Occupancy per view count: the fast sweep of few views fits 96 or 128
     // VGPRs with a few spills outside the sweep (five or four waves per SIMD;
     // FP32 descriptors carry two record paths and stay at four)
     if constexpr (K <= 5 && ST != 0) {
-        return sym ? (EmKernel)lf_em_kernel_w5<K, ST, false, false, true>
-                   : (EmKernel)lf_em_kernel_w5<K, ST, false, false, false>;
+        return sym ? (EmKernel)lf_em_kernel_w5<K, ST, false, SW, true>
+                   : (EmKernel)lf_em_kernel_w5<K, ST, false, SW, false>;
     } else if constexpr (K <= 6) {
-        return sym ? (EmKernel)lf_em_kernel_w4<K, ST, false, false, true>
-                   : (EmKernel)lf_em_kernel_w4<K, ST, false, false, false>;
+        return sym ? (EmKernel)lf_em_kernel_w4<K, ST, false, SW, true>
+                   : (EmKernel)lf_em_kernel_w4<K, ST, false, SW, false>;
     } else if constexpr (K <= 9) {
         // three waves per SIMD, with a tile wide enough for the LDS to hold them
-        return sym ? (EmKernel)lf_em_kernel_w3<K, ST, false, false, true>
-                   : (EmKernel)lf_em_kernel_w3<K, ST, false, false, false>;
+        return sym ? (EmKernel)lf_em_kernel_w3<K, ST, false, SW, true>
+                   : (EmKernel)lf_em_kernel_w3<K, ST, false, SW, false>;
     } else {
-        return sym ? (EmKernel)lf_em_kernel<K, ST, false, false, true> : (EmKernel)lf_em_kernel<K, ST, false, false, false>;
+        return sym ? (EmKernel)lf_em_kernel<K, ST, false, SW, true> : (EmKernel)lf_em_kernel<K, ST, false, SW, false>;
     }
 }
 
+template <int K, int ST>
+static EmKernel pick_em_k(bool frac, bool exh, bool sym, bool share) {
+    if (exh)
+        return frac ? (EmKernel)lf_em_kernel<K, ST, true, kSweepExhaustive, false>
+                    : (EmKernel)lf_em_kernel<K, ST, false, kSweepExhaustive, false>;
+    if (frac) return (EmKernel)lf_em_kernel<K, ST, true, kSweepLane, false>;
+    return share ? pick_em_fast<K, ST, kSweepShared>(sym) : pick_em_fast<K, ST, kSweepLane>(sym);
+}
+
 template <int ST>
-static EmKernel pick_em_storage(int K, bool frac, bool exh, bool sym) {
+static EmKernel pick_em_storage(int K, bool frac, bool exh, bool sym, bool share) {
     switch (K) {
 #define LF_CASE(n) \
-    case n: return pick_em_k<n, ST>(frac, exh, sym);
+    case n: return pick_em_k<n, ST>(frac, exh, sym, share);
         LF_CASE(2) LF_CASE(3) LF_CASE(4) LF_CASE(5) LF_CASE(6) LF_CASE(7) LF_CASE(8) LF_CASE(9)
         LF_CASE(10) LF_CASE(11) LF_CASE(12) LF_CASE(13) LF_CASE(14) LF_CASE(15) LF_CASE(16)
 #undef LF_CASE

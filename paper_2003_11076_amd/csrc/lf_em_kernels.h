@@ -767,6 +767,12 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, int u) {
 // Sweep overhead of handing a pixel's levels to other lanes, in levels.
 constexpr int kShareCost = 6;
 
+// M-step sweep of a kernel instance: the fast sweep with the prior bound and
+// the wave's lanes sharing levels (integer shifts), the exhaustive sweep, or
+// the fast sweep of each lane on its own (fractional shifts, and search
+// windows: their short ranges gain too little to pay for the bound).
+constexpr int kSweepShared = 0, kSweepExhaustive = 1, kSweepLane = 2;
+
 // One EM iteration of one wave with the M-step work rebalanced inside the
 // wave (integer shifts, fast sweep).  Each pixel's seed energy bounds the
 // levels that can still win (prior_interval).  A wave sweeps until its
@@ -812,6 +818,12 @@ __device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win,
     const uint64_t um = __ballot(unb);
     const int nu = __popcll(um);
     const bool anyb = __ballot(bnd) != 0;
+    // levels [slo, shi] hold every lane's search window (the whole range
+    // unless a search window is set); the levels outside a bounded lane's
+    // interval or outside [slo, shi] cannot win
+    const int nlev = shi - slo + 1;
+    jl = max(jl, slo);
+    jh = min(jh, shi);
     // bounded windows: the wave's widest extents below and above each lane's
     // nearest level c to mu, so that neighbouring lanes (whose c mostly
     // agree) read neighbouring LDS records
@@ -823,10 +835,10 @@ __device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win,
     while (nu > 0 && cp * 2 * nu <= 64) cp *= 2;
     // odd chunk lengths: the cp chunks of a pixel then start on different
     // LDS banks
-    const int chunk = min(((a.D + cp - 1) / cp) | 1, a.D);
+    const int chunk = min(((nlev + cp - 1) / cp) | 1, nlev);
     const int cost = (anyb ? wl : 0) + (nu > 0 ? chunk + kShareCost : 0);
 
-    if (cost >= a.D) {
+    if (cost >= nlev) {
         // every lane sweeps its whole range
         if (work) {
             int lo, j1, j2, hi;
@@ -835,9 +847,9 @@ __device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win,
                                           n0, s.mu, masked, best_E, best_j);
         }
     } else {
-        // bounded pixels: wl levels from js, covering [jl, jh], inside the range
+        // bounded pixels: wl levels from js, covering [jl, jh], inside [slo, shi]
         if (anyb) {
-            const int js = min(max(c - el, 0), a.D - wl);
+            const int js = min(max(c - el, slo), shi + 1 - wl);
             int ib[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) ib[k] = idx0[k] - a.bi[k] * a.dstep_i * js;
@@ -845,9 +857,12 @@ __device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win,
                 fast_sweep<K, ST, false, SYM>(win, w, a, x, ib, js, 0, 0, wl, wl, Pc, a.prior_hi, wt, invW, cw, f0, n0,
                                               s.mu, masked, best_E, best_j);
         }
-        // unbounded pixels: lane h sweeps chunk (h % cp) of the (h / cp)-th one
+        // unbounded pixels: with U = 64 / cp, lane h sweeps chunk h / U of
+        // the (h % U)-th one, so that the lanes sweeping the same chunk of
+        // neighbouring pixels read neighbouring LDS records
         if (nu > 0) {
-            const int u = lane / cp;
+            const int U = 64 / cp;
+            const int u = lane & (U - 1);
             const bool helper = u < nu;
             const int src = nth_set_bit(um, helper ? u : 0);
             float hwt[K];
@@ -863,7 +878,7 @@ __device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win,
             int hidx0[K];
             level0_index<K, false>(w, a, hx, hidx0);
             const R hr0 = win[hidx0[0]];
-            const int jb = min((lane % cp) * chunk, a.D - chunk);
+            const int jb = slo + min((lane / U) * chunk, nlev - chunk);
             // upper bound of the prior over the chunk: its value at the
             // chunk's level nearest mu, plus the evaluation's error
             const int jn = min(max(nearest_level(a, hmu), jb), jb + chunk - 1);
@@ -875,14 +890,14 @@ __device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win,
             if (helper)
                 fast_sweep<K, ST, false, SYM>(win, w, a, hx, ib, jb, 0, 0, chunk, chunk, Pc, phi, hwt, hinvW, hcw,
                                               rec_f<ST>(hr0), rec_n<ST>(hr0), hmu, masked, hE, hj);
-            // reduce each pixel's cp chunks (aligned groups of cp lanes)
-            for (int o = 1; o < cp; o <<= 1) {
+            // reduce each pixel's cp chunks (lanes u, u + U, u + 2U, ...)
+            for (int o = U; o < 64; o <<= 1) {
                 const float E2 = __shfl_xor(hE, o, 64);
                 const int j2 = __shfl_xor(hj, o, 64);
                 lex_min(hE, hj, E2, j2);
             }
             const int rank = __popcll(um & ((1ull << lane) - 1ull));
-            const int jr = __shfl(hj, (unb ? rank : 0) * cp, 64);
+            const int jr = __shfl(hj, unb ? rank : 0, 64);
             if (unb) best_j = jr;
         }
     }
@@ -912,7 +927,7 @@ __device__ __forceinline__ typename Pair<RS>::T to_record_pair(typename Pair<ST>
 __device__ __forceinline__ bool exact_in_half(float v) { return __half2float(__float2half_rn(v)) == v; }
 
 // The kernel body: descriptors of storage ST staged as records of storage RS.
-template <int K, int ST, int RS, bool FRAC, bool EXH, bool SYM>
+template <int K, int ST, int RS, bool FRAC, int SW, bool SYM>
 __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw, double *red) {
     using R = typename Rec<RS>::T;
     using P = typename Pair<ST>::T;
@@ -1012,10 +1027,12 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
     const int block_id = blockIdx.y * gridDim.x + blockIdx.x;
     for (int it = 0; it < a.n_iters; ++it) {
         const bool with_obj = a.want_obj || it == a.n_iters - 1;
-        if constexpr (!EXH && !FRAC) {
+        if constexpr (SW == kSweepShared && !FRAC) {
             shared_iteration<K, RS, SYM>(win, w, a, x, work, jlo, jhi, slo, shi, Pc, s, with_obj);
         } else {
-            if (work) em_iteration<K, RS, FRAC, EXH, SYM>(win, w, a, x, jlo, jhi, slo, shi, Pc, s, with_obj);
+            if (work)
+                em_iteration<K, RS, FRAC, SW == kSweepExhaustive, SYM>(win, w, a, x, jlo, jhi, slo, shi, Pc, s,
+                                                                        with_obj);
         }
         if (!with_obj) continue;
         // ---- FP64 block sum of the objective ----
@@ -1042,7 +1059,7 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
 // binary16 (|G| <= 2048 for the Sobel responses, the usual case) are staged
 // as binary16 records: the same values, read as 8 bytes instead of 12 per
 // record, and the same FP32 arithmetic, so the results are the same bits.
-template <int K, int ST, bool FRAC, bool EXH, bool SYM>
+template <int K, int ST, bool FRAC, int SW, bool SYM>
 __device__ __forceinline__ void em_entry(const EmArgs &a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double red[8];
@@ -1060,36 +1077,36 @@ __device__ __forceinline__ void em_entry(const EmArgs &a) {
                 exact = exact && exact_in_half(v.x) && exact_in_half(v.y);
             }
         }
-        if (__syncthreads_and(exact)) em_body<K, 0, 1, FRAC, EXH, SYM>(a, lds_raw, red);
-        else em_body<K, 0, 0, FRAC, EXH, SYM>(a, lds_raw, red);
+        if (__syncthreads_and(exact)) em_body<K, 0, 1, FRAC, SW, SYM>(a, lds_raw, red);
+        else em_body<K, 0, 0, FRAC, SW, SYM>(a, lds_raw, red);
     } else {
-        em_body<K, ST, ST, FRAC, EXH, SYM>(a, lds_raw, red);
+        em_body<K, ST, ST, FRAC, SW, SYM>(a, lds_raw, red);
     }
 }
 
-template <int K, int ST, bool FRAC, bool EXH, bool SYM>
+template <int K, int ST, bool FRAC, int SW, bool SYM>
 __global__ __launch_bounds__(256) void lf_em_kernel(EmArgs a) {
-    em_entry<K, ST, FRAC, EXH, SYM>(a);
+    em_entry<K, ST, FRAC, SW, SYM>(a);
 }
 
 // The same kernel held to 168 VGPRs, three waves per SIMD (views 7 to 9).
-template <int K, int ST, bool FRAC, bool EXH, bool SYM>
+template <int K, int ST, bool FRAC, int SW, bool SYM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void lf_em_kernel_w3(EmArgs a) {
-    em_entry<K, ST, FRAC, EXH, SYM>(a);
+    em_entry<K, ST, FRAC, SW, SYM>(a);
 }
 
 // The same kernel held to 96 VGPRs, five waves per SIMD (up to 5 views).
-template <int K, int ST, bool FRAC, bool EXH, bool SYM>
+template <int K, int ST, bool FRAC, int SW, bool SYM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void lf_em_kernel_w5(EmArgs a) {
-    em_entry<K, ST, FRAC, EXH, SYM>(a);
+    em_entry<K, ST, FRAC, SW, SYM>(a);
 }
 
 // The same kernel held to 128 VGPRs, four waves per SIMD: for small view
 // counts this costs a few spills outside the sweep and gains a wave of
 // latency hiding (the sweep alternates LDS reads and FMAs).
-template <int K, int ST, bool FRAC, bool EXH, bool SYM>
+template <int K, int ST, bool FRAC, int SW, bool SYM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void lf_em_kernel_w4(EmArgs a) {
-    em_entry<K, ST, FRAC, EXH, SYM>(a);
+    em_entry<K, ST, FRAC, SW, SYM>(a);
 }
 
 }  // namespace lfem
