@@ -774,7 +774,8 @@ constexpr int kShareCost = 6;
 constexpr int kSweepShared = 0, kSweepExhaustive = 1, kSweepLane = 2;
 
 // One EM iteration of one wave with the M-step work rebalanced inside the
-// wave (integer shifts, fast sweep).  Each pixel's seed energy bounds the
+// wave (integer shifts, fast sweep, no search window: the levels excluded by
+// a window would be swept, to no effect).  Each pixel's seed energy bounds the
 // levels that can still win (prior_interval).  A wave sweeps until its
 // slowest lane is done, so instead of every lane sweeping its own levels:
 //   * pixels with a bounded interval sweep a window of the wave's widest
@@ -818,12 +819,8 @@ __device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win,
     const uint64_t um = __ballot(unb);
     const int nu = __popcll(um);
     const bool anyb = __ballot(bnd) != 0;
-    // levels [slo, shi] hold every lane's search window (the whole range
-    // unless a search window is set); the levels outside a bounded lane's
-    // interval or outside [slo, shi] cannot win
-    const int nlev = shi - slo + 1;
-    jl = max(jl, slo);
-    jh = min(jh, shi);
+    // no search window here: every lane searches all D levels
+    const int nlev = a.D;
     // bounded windows: the wave's widest extents below and above each lane's
     // nearest level c to mu, so that neighbouring lanes (whose c mostly
     // agree) read neighbouring LDS records
@@ -847,9 +844,9 @@ __device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win,
                                           n0, s.mu, masked, best_E, best_j);
         }
     } else {
-        // bounded pixels: wl levels from js, covering [jl, jh], inside [slo, shi]
+        // bounded pixels: wl levels from js, covering [jl, jh], inside the range
         if (anyb) {
-            const int js = min(max(c - el, slo), shi + 1 - wl);
+            const int js = min(max(c - el, 0), a.D - wl);
             int ib[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) ib[k] = idx0[k] - a.bi[k] * a.dstep_i * js;
@@ -878,7 +875,7 @@ __device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win,
             int hidx0[K];
             level0_index<K, false>(w, a, hx, hidx0);
             const R hr0 = win[hidx0[0]];
-            const int jb = slo + min((lane / U) * chunk, nlev - chunk);
+            const int jb = min((lane / U) * chunk, a.D - chunk);
             // upper bound of the prior over the chunk: its value at the
             // chunk's level nearest mu, plus the evaluation's error
             const int jn = min(max(nearest_level(a, hmu), jb), jb + chunk - 1);
