@@ -389,7 +389,12 @@ static lf_status ctx_alloc(lf_ctx *c) {
     }
     int vgprs = 0;
     {
-        EmKernel kern = pick_em(&p, c->g);
+        // the tile follows the fast sweep's kernel also when the exhaustive
+        // sweep is asked for, so that both use the same blocks and the
+        // objective's FP64 block sums add up in the same order
+        lf_params pf = p;
+        pf.flags &= ~(uint32_t)LF_EXHAUSTIVE_SWEEP;
+        EmKernel kern = pick_em(&pf, c->g);
         hipFuncAttributes fa;
         if (kern && hipFuncGetAttributes(&fa, (const void *)kern) == hipSuccess) vgprs = fa.numRegs;
         (void)hipGetLastError();

@@ -10,21 +10,36 @@ namespace lfem {
 
 template <int K, int ST, int SW>
 static EmKernel pick_em_fast(bool sym) {
-    // Occupancy per view count: the fast sweep of few views fits 96 or 128
-    // VGPRs with a few spills outside the sweep (five or four waves per SIMD;
-    // FP32 descriptors carry two record paths and stay at four)
-    if constexpr (K <= 5 && ST != 0) {
-        return sym ? (EmKernel)lf_em_kernel_w5<K, ST, false, SW, true>
-                   : (EmKernel)lf_em_kernel_w5<K, ST, false, SW, false>;
-    } else if constexpr (K <= 6) {
-        return sym ? (EmKernel)lf_em_kernel_w4<K, ST, false, SW, true>
-                   : (EmKernel)lf_em_kernel_w4<K, ST, false, SW, false>;
-    } else if constexpr (K <= 9) {
-        // three waves per SIMD, with a tile wide enough for the LDS to hold them
-        return sym ? (EmKernel)lf_em_kernel_w3<K, ST, false, SW, true>
-                   : (EmKernel)lf_em_kernel_w3<K, ST, false, SW, false>;
+    if constexpr (SW == kSweepShared) {
+        // The shared sweep keeps more state per lane: four waves per SIMD up
+        // to six views (a few spills outside the sweep), the compiler's own
+        // register count above that (measured: both faster than five and
+        // three waves with the spills those caps force)
+        if constexpr (K <= 6) {
+            return sym ? (EmKernel)lf_em_kernel_w4<K, ST, false, SW, true>
+                       : (EmKernel)lf_em_kernel_w4<K, ST, false, SW, false>;
+        } else {
+            return sym ? (EmKernel)lf_em_kernel<K, ST, false, SW, true>
+                       : (EmKernel)lf_em_kernel<K, ST, false, SW, false>;
+        }
     } else {
-        return sym ? (EmKernel)lf_em_kernel<K, ST, false, SW, true> : (EmKernel)lf_em_kernel<K, ST, false, SW, false>;
+        // Occupancy per view count: the fast sweep of few views fits 96 or
+        // 128 VGPRs with a few spills outside the sweep (five or four waves
+        // per SIMD; FP32 descriptors carry two record paths and stay at four)
+        if constexpr (K <= 5 && ST != 0) {
+            return sym ? (EmKernel)lf_em_kernel_w5<K, ST, false, SW, true>
+                       : (EmKernel)lf_em_kernel_w5<K, ST, false, SW, false>;
+        } else if constexpr (K <= 6) {
+            return sym ? (EmKernel)lf_em_kernel_w4<K, ST, false, SW, true>
+                       : (EmKernel)lf_em_kernel_w4<K, ST, false, SW, false>;
+        } else if constexpr (K <= 9) {
+            // three waves per SIMD, with a tile wide enough for the LDS to hold them
+            return sym ? (EmKernel)lf_em_kernel_w3<K, ST, false, SW, true>
+                       : (EmKernel)lf_em_kernel_w3<K, ST, false, SW, false>;
+        } else {
+            return sym ? (EmKernel)lf_em_kernel<K, ST, false, SW, true>
+                       : (EmKernel)lf_em_kernel<K, ST, false, SW, false>;
+        }
     }
 }
 
