@@ -131,7 +131,7 @@ def feat_bytes(storage, K, H, W):
 # GPU runs through the C ABI (inputs as device tensors on torch's stream)
 # ---------------------------------------------------------------------------
 
-class GpuRun:
+class DeviceRun:
     def __init__(self, case: Case, device_inputs=True, q_warm=None, extra_flags=0):
         import torch
         import paper_2003_11076_amd as LF
@@ -291,7 +291,7 @@ def teacher_forced(case: Case, n_iters: int, rows=None, device_inputs=True, chec
     pr = O.ray_prior(op, case.S_P, case.mu_T, rows=(y0, y1))
     rho_o, q0_o = pr
     omr_o = pr.omr
-    run = GpuRun(case, device_inputs=device_inputs)
+    run = DeviceRun(case, device_inputs=device_inputs)
     try:
         f_g, rho_g = run.intermediates()
         assert np.array_equal(f_g[:, y0:y1], f_o[:, y0:y1]), "descriptors differ"

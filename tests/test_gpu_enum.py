@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import lf_scenes as S
-from lfcase import Case, GpuRun, random_case, teacher_forced
+from lfcase import Case, DeviceRun, random_case, teacher_forced
 
 pytestmark = pytest.mark.gpu
 
@@ -61,7 +61,7 @@ def test_enumeration_fast_sweep_matches_exhaustive():
     _say("enum_soft fast vs exhaustive sweep K=5 6x200 D=32 f16")
     outs = []
     for flags in (0, LF.LF_EXHAUSTIVE_SWEEP):
-        run = GpuRun(case, extra_flags=flags)
+        run = DeviceRun(case, extra_flags=flags)
         run.iterate(3)
         outs.append(run.state())
         run.close()

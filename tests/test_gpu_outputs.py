@@ -9,7 +9,7 @@ import pytest
 
 import lf_scenes as S
 import oracle as O
-from lfcase import Case, GpuRun, random_case, TOL_RGB
+from lfcase import Case, DeviceRun, random_case, TOL_RGB
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +57,7 @@ def test_per_iteration_refocus_and_segmentation(name, kw):
         case = random_case(kw.pop("K"), kw.pop("H"), kw.pop("W"), kw.pop("D"), seed=31, **kw)
     _say(f"per-iteration refocus and segmentation maps: {name} K={case.K} {case.H}x{case.W} D={case.D}")
     op = case.oracle_params()
-    run = GpuRun(case)
+    run = DeviceRun(case)
     try:
         for t in range(3):
             run.iterate(1)
@@ -82,14 +82,14 @@ def test_per_iteration_refocus_and_segmentation(name, kw):
 def test_refocus_between_iterations_leaves_the_state_alone():
     case = random_case(5, 6, 200, 32, storage="f16", seed=32)
     _say("iterate(1) + refocus + iterate(1) == iterate(2), bitwise")
-    a = GpuRun(case)
+    a = DeviceRun(case)
     a.iterate(1)
     a.refocus()
     _labels(a)
     a.iterate(1)
     sa = a.state()
     a.close()
-    b = GpuRun(case)
+    b = DeviceRun(case)
     b.iterate(2)
     sb = b.state()
     b.close()

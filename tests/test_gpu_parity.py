@@ -10,7 +10,7 @@ import pytest
 
 import lf_scenes as S
 import oracle as O
-from lfcase import Case, GpuRun, random_case, teacher_forced, near_tie
+from lfcase import Case, DeviceRun, random_case, teacher_forced, near_tie
 
 pytestmark = pytest.mark.gpu
 
@@ -80,12 +80,12 @@ def test_large_bf16_sampled_rows():
 def test_resume_is_bitwise(small_frame):
     case = Case.from_frame(small_frame, storage="f32")
     _say("small_frame resume: iterate(3)+iterate(2) vs iterate(5)")
-    a = GpuRun(case)
+    a = DeviceRun(case)
     a.iterate(3)
     a.iterate(2)
     qa, da, La = a.state()
     a.close()
-    b = GpuRun(case)
+    b = DeviceRun(case)
     b.iterate(5)
     qb, db, Lb = b.state()
     b.close()
@@ -95,11 +95,11 @@ def test_resume_is_bitwise(small_frame):
 def test_host_and_device_inputs_agree(small_frame):
     case = Case.from_frame(small_frame, storage="f16")
     _say("small_frame host vs device inputs, fp16")
-    a = GpuRun(case, device_inputs=True)
+    a = DeviceRun(case, device_inputs=True)
     a.iterate(4)
     ra = a.refocus()
     a.close()
-    b = GpuRun(case, device_inputs=False)
+    b = DeviceRun(case, device_inputs=False)
     b.iterate(4)
     rb = b.refocus()
     b.close()
@@ -111,7 +111,7 @@ def test_warm_start_uses_given_weights(small_frame):
     case = Case.from_frame(small_frame, storage="f32")
     _say("small_frame warm start")
     qw = np.random.default_rng(5).uniform(0, 1, (case.K, case.H, case.W)).astype(np.float32)
-    run = GpuRun(case, q_warm=qw)
+    run = DeviceRun(case, q_warm=qw)
     q0, _, _ = run.state(with_d=False)
     assert np.array_equal(q0, qw)
     run.iterate(1)
@@ -128,7 +128,7 @@ def test_warm_start_uses_given_weights(small_frame):
 def test_frame_objective_is_sum_of_pixels(small_frame):
     case = Case.from_frame(small_frame, storage="f32")
     _say("small_frame frame objective")
-    run = GpuRun(case)
+    run = DeviceRun(case)
     obj = run.iterate(3, objective=True)
     q, d, L = run.state()
     run.close()
@@ -139,7 +139,7 @@ def test_frame_objective_is_sum_of_pixels(small_frame):
 def test_median_refocus(small_frame):
     case = Case.from_frame(small_frame, storage="f32")
     _say("small_frame refocus with 3x3 median")
-    run = GpuRun(case)
+    run = DeviceRun(case)
     run.iterate(2)
     rgb0, d, q, hole = run.refocus(median=0)
     rgb3, _, _, _ = run.refocus(median=3)
@@ -208,7 +208,7 @@ def test_state_calls_out_of_order(small_frame):
     import paper_2003_11076_amd as LF
     case = Case.from_frame(small_frame, storage="f32")
     _say("ESTATE paths")
-    run = GpuRun(case)
+    run = DeviceRun(case)
     rgb = np.zeros((case.H, case.W, 3), np.float32)
     with pytest.raises(LF.LFError) as e:
         LF.lf_refocus(run.ctx, rgb)
@@ -222,7 +222,7 @@ def test_state_calls_out_of_order(small_frame):
 def test_free_running_agreement(small_frame):
     case = Case.from_frame(small_frame, storage="f32")
     _say("small_frame free-running agreement")
-    run = GpuRun(case)
+    run = DeviceRun(case)
     run.iterate(case.n_iters)
     rgb, d, q, hole = run.refocus()
     run.close()
@@ -251,7 +251,7 @@ def test_fast_sweep_matches_exhaustive_bitwise(K, H, W, D, b, dmin, dstep, st, m
     _say(f"fast vs exhaustive sweep K={K} {H}x{W} D={D} {st} {mode}")
     out = []
     for flags in (0, LF.LF_EXHAUSTIVE_SWEEP):
-        run = GpuRun(case, extra_flags=flags)
+        run = DeviceRun(case, extra_flags=flags)
         objs = [run.iterate(1, objective=True)[0] for _ in range(4)]
         out.append(run.state() + (np.array(objs),))
         run.close()
@@ -265,7 +265,7 @@ def test_fast_sweep_matches_exhaustive_small(small_frame):
     _say("small_frame fast vs exhaustive sweep, 5 iterations")
     out = []
     for flags in (0, LF.LF_EXHAUSTIVE_SWEEP):
-        run = GpuRun(case, extra_flags=flags)
+        run = DeviceRun(case, extra_flags=flags)
         obj = run.iterate(5, objective=True)
         out.append(run.state() + (obj,))
         run.close()
@@ -277,7 +277,7 @@ def _fast_vs_exhaustive(case, n_iters, extra=0):
     import paper_2003_11076_amd as LF
     out = []
     for flags in (extra, extra | LF.LF_EXHAUSTIVE_SWEEP):
-        run = GpuRun(case, extra_flags=flags)
+        run = DeviceRun(case, extra_flags=flags)
         obj = run.iterate(n_iters, objective=True)
         out.append(run.state() + (obj,))
         run.close()
@@ -332,7 +332,7 @@ def test_precision_fp16_error_against_unquantised_oracle():
     fr = S.make_frame(S.workload_spec("precision"))
     case = Case.from_frame(fr, storage="f16")
     _say("precision fp16 end to end vs the unquantised FP64 oracle, rows 472..488")
-    run = GpuRun(case)
+    run = DeviceRun(case)
     run.iterate(10)
     rgb, d, q, hole = run.refocus()
     run.close()

@@ -11,7 +11,7 @@ import threading
 import numpy as np
 import pytest
 
-from lfcase import random_case, Case, GpuRun
+from lfcase import random_case, Case, DeviceRun
 
 pytestmark = pytest.mark.gpu
 
@@ -72,7 +72,7 @@ class Server:
 
 
 def _plain(case, n_iters, q_warm=None):
-    run = GpuRun(case, q_warm=q_warm)
+    run = DeviceRun(case, q_warm=q_warm)
     run.iterate(n_iters)
     rgb, d, q, hole = run.refocus()
     run.close()

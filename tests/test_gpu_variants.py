@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import lf_scenes as S
-from lfcase import Case, GpuRun, random_case, teacher_forced
+from lfcase import Case, DeviceRun, random_case, teacher_forced
 
 pytestmark = pytest.mark.gpu
 
@@ -54,7 +54,7 @@ def test_large_window_sampled_rows():
 
 
 def _run(case, flags, n=3):
-    run = GpuRun(case, extra_flags=flags)
+    run = DeviceRun(case, extra_flags=flags)
     run.iterate(n)
     out = run.refocus()
     L = run.state()[2]
@@ -67,7 +67,7 @@ def test_dynamic_only_equals_plain_on_dynamic_pixels():
     _say("small_frame dynamic-only vs plain, bitwise on the dynamic reference pixels")
     (rgb0, d0, q0, h0), L0 = _run(case, 0)
     (rgb1, d1, q1, h1), L1 = _run(case, DYN)
-    run = GpuRun(case)
+    run = DeviceRun(case)
     _, rho = run.intermediates()
     run.close()
     dyn = rho[case.ref] < np.float32(case.tau)
