@@ -738,8 +738,10 @@ __device__ __forceinline__ bool prior_interval(const EmArgs &a, float best_E, fl
     const float tmax = __builtin_amdgcn_sqrtf(fmaxf(-l2, 0.0f) * a.c_t2) * (1.0f + 1e-4f) +
                        0x1p-20f * (a.d_absmax + fabsf(mu));
     const float m = (mu - a.d_min) * a.inv_step, r = tmax * a.inv_step;
-    jl = (int)fmaxf(ceilf(m - r - 0.01f), 0.0f);
-    jh = (int)fminf(floorf(m + r + 0.01f), (float)(a.D - 1));
+    // clamped to [0, D] and [-1, D - 1] before the conversion, so that a
+    // position far outside the level range converts exactly
+    jl = (int)fminf(fmaxf(ceilf(m - r - 0.01f), 0.0f), (float)a.D);
+    jh = (int)fmaxf(fminf(floorf(m + r + 0.01f), (float)(a.D - 1)), -1.0f);
     return true;
 }
 

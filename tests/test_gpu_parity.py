@@ -301,6 +301,7 @@ def test_pruned_sweep_matches_exhaustive_on_scenes(workload):
 @pytest.mark.parametrize("label,mu_shift,sigma,gamma,mode", [
     ("prior below the level range", -9.0, 2.0, 0.05, "soft"),
     ("prior above the level range", 30.0, 2.0, 0.05, "soft"),
+    ("prior far outside the level range", -1.0e5, 2.0, 0.05, "soft"),
     ("narrow prior", 0.0, 0.35, 0.05, "soft"),
     ("prior wider than the level range", 0.0, 40.0, 0.05, "soft"),
     ("small gamma", 0.0, 2.0, 1e-6, "hard"),
