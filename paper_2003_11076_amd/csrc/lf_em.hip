@@ -148,10 +148,11 @@ size_t rec_bytes(int storage) { return storage == LF_F32 ? 16 : 8; }
 // is set (its short ranges gain too little to pay for the prior bound).
 EmKernel pick_em(const lf_params *p, const Geometry &g) {
     const bool exh = (p->flags & LF_EXHAUSTIVE_SWEEP) != 0, share = !(p->flags & LF_PRIOR_WINDOW);
+    const bool enumerate = p->mode == LF_ENUM_SOFT || p->mode == LF_ENUM_HARD;
     switch (p->storage) {
-        case LF_F32: return pick_em_f32(p->K, g.frac, exh, g.sym, share);
-        case LF_F16: return pick_em_f16(p->K, g.frac, exh, g.sym, share);
-        default: return pick_em_bf16(p->K, g.frac, exh, g.sym, share);
+        case LF_F32: return pick_em_f32(p->K, g.frac, exh, g.sym, share, enumerate);
+        case LF_F16: return pick_em_f16(p->K, g.frac, exh, g.sym, share, enumerate);
+        default: return pick_em_bf16(p->K, g.frac, exh, g.sym, share, enumerate);
     }
 }
 

@@ -9,15 +9,23 @@
 namespace lfem {
 
 template <int K, int ST, int SW>
-static EmKernel pick_em_fast(bool sym) {
+static EmKernel pick_em_fast(bool sym, bool enumerate) {
     if constexpr (SW == kSweepShared) {
         // The shared sweep keeps more state per lane: four waves per SIMD up
         // to six views (a few spills outside the sweep), the compiler's own
         // register count above that (measured: both faster than five and
-        // three waves with the spills those caps force)
+        // three waves with the spills those caps force), except for the
+        // enumeration E-step of seven to nine views, whose 2^K loop gains
+        // more from three waves than the sweep loses
         if constexpr (K <= 6) {
             return sym ? (EmKernel)lf_em_kernel_w4<K, ST, false, SW, true>
                        : (EmKernel)lf_em_kernel_w4<K, ST, false, SW, false>;
+        } else if constexpr (K <= 9) {
+            if (enumerate)
+                return sym ? (EmKernel)lf_em_kernel_w3<K, ST, false, SW, true>
+                           : (EmKernel)lf_em_kernel_w3<K, ST, false, SW, false>;
+            return sym ? (EmKernel)lf_em_kernel<K, ST, false, SW, true>
+                       : (EmKernel)lf_em_kernel<K, ST, false, SW, false>;
         } else {
             return sym ? (EmKernel)lf_em_kernel<K, ST, false, SW, true>
                        : (EmKernel)lf_em_kernel<K, ST, false, SW, false>;
@@ -44,19 +52,19 @@ static EmKernel pick_em_fast(bool sym) {
 }
 
 template <int K, int ST>
-static EmKernel pick_em_k(bool frac, bool exh, bool sym, bool share) {
+static EmKernel pick_em_k(bool frac, bool exh, bool sym, bool share, bool enumerate) {
     if (exh)
         return frac ? (EmKernel)lf_em_kernel<K, ST, true, kSweepExhaustive, false>
                     : (EmKernel)lf_em_kernel<K, ST, false, kSweepExhaustive, false>;
     if (frac) return (EmKernel)lf_em_kernel<K, ST, true, kSweepLane, false>;
-    return share ? pick_em_fast<K, ST, kSweepShared>(sym) : pick_em_fast<K, ST, kSweepLane>(sym);
+    return share ? pick_em_fast<K, ST, kSweepShared>(sym, enumerate) : pick_em_fast<K, ST, kSweepLane>(sym, enumerate);
 }
 
 template <int ST>
-static EmKernel pick_em_storage(int K, bool frac, bool exh, bool sym, bool share) {
+static EmKernel pick_em_storage(int K, bool frac, bool exh, bool sym, bool share, bool enumerate) {
     switch (K) {
 #define LF_CASE(n) \
-    case n: return pick_em_k<n, ST>(frac, exh, sym, share);
+    case n: return pick_em_k<n, ST>(frac, exh, sym, share, enumerate);
         LF_CASE(2) LF_CASE(3) LF_CASE(4) LF_CASE(5) LF_CASE(6) LF_CASE(7) LF_CASE(8) LF_CASE(9)
         LF_CASE(10) LF_CASE(11) LF_CASE(12) LF_CASE(13) LF_CASE(14) LF_CASE(15) LF_CASE(16)
 #undef LF_CASE

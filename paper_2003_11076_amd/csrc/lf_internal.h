@@ -16,9 +16,9 @@ struct EmArgs;
 struct RefocusArgs;
 using EmKernel = void (*)(EmArgs);
 
-EmKernel pick_em_f32(int K, bool frac, bool exh, bool sym, bool share);
-EmKernel pick_em_f16(int K, bool frac, bool exh, bool sym, bool share);
-EmKernel pick_em_bf16(int K, bool frac, bool exh, bool sym, bool share);
+EmKernel pick_em_f32(int K, bool frac, bool exh, bool sym, bool share, bool enumerate);
+EmKernel pick_em_f16(int K, bool frac, bool exh, bool sym, bool share, bool enumerate);
+EmKernel pick_em_bf16(int K, bool frac, bool exh, bool sym, bool share, bool enumerate);
 
 struct ServeJob;
 using ServeKernel = void (*)(const ServeJob *, int);
