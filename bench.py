@@ -42,7 +42,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 # sources of the EM kernel: HBM traffic measured with rocprofv3 counters is
 # reported only while these are unchanged since the measurement
 EM_SOURCES = ("paper_2003_11076_amd/csrc/lf_em_kernels.h", "paper_2003_11076_amd/csrc/lf_em_f32.hip",
-              "paper_2003_11076_amd/csrc/lf_em_dispatch.h", "paper_2003_11076_amd/csrc/lf_em.hip")
+              "paper_2003_11076_amd/csrc/lf_em_dispatch.h", "paper_2003_11076_amd/csrc/lf_em.hip",
+              "paper_2003_11076_amd/csrc/lf_em_f16.hip", "paper_2003_11076_amd/csrc/lf_em_bf16.hip")
 
 
 def measured_traffic(workload):
