@@ -650,6 +650,9 @@ lf_status lf_refocus(lf_ctx *c, float *rgb, int32_t *d_idx, float *q, uint8_t *h
     float *rgb_k = median ? c->rgb_med : (dev_out ? rgb : c->rgb);
     r.rgb = rgb_k;
     r.hole = dev_out ? hole : c->hole;
+    // device outputs: the refocus pass writes the level and weights too
+    r.d_out = dev_out ? d_idx : nullptr;
+    r.q_out = dev_out ? q : nullptr;
     LF_HIP(launch_refocus(&p, r, c->stream), "refocus launch");
     if (median) LF_HIP(launch_median3(&p, c->rgb_med, dev_out ? rgb : c->rgb, c->stream), "median launch");
     lf_status st = LF_OK;
@@ -657,8 +660,10 @@ lf_status lf_refocus(lf_ctx *c, float *rgb, int32_t *d_idx, float *q, uint8_t *h
         if (st == LF_OK) st = copy_out(c, rgb, c->rgb, HW * 12);
         if (st == LF_OK && hole) st = copy_out(c, hole, c->hole, HW);
     }
-    if (st == LF_OK && d_idx) st = copy_out(c, d_idx, c->d_idx, HW * 4);
-    if (st == LF_OK && q) st = copy_out(c, q, c->q, HW * p.K * 4);
+    if (!dev_out) {
+        if (st == LF_OK && d_idx) st = copy_out(c, d_idx, c->d_idx, HW * 4);
+        if (st == LF_OK && q) st = copy_out(c, q, c->q, HW * p.K * 4);
+    }
     if (st != LF_OK) return st;
     if (!dev_out) {
         LF_HIP(hipStreamSynchronize(c->stream), "synchronize");

@@ -93,6 +93,8 @@ struct RefocusArgs {
     float tau;
     float *rgb;
     uint8_t *hole;
+    int32_t *d_out;         // device copies of the level and weights handed out, or null
+    float *q_out;
     int K, H, W, ref, frac;
     int dmin_i, dstep_i;
     float d_min, d_step;
@@ -106,6 +108,10 @@ __global__ __launch_bounds__(256) void lf_refocus_kernel(RefocusArgs a) {
     if (x >= a.W) return;
     const size_t HW = (size_t)a.H * a.W;
     const size_t pix = (size_t)y * a.W + x;
+    // the state handed out with the image, in the same pass
+    if (a.d_out) a.d_out[pix] = a.d_idx[pix];
+    if (a.q_out)
+        for (int k = 0; k < a.K; ++k) a.q_out[k * HW + pix] = a.q[k * HW + pix];
     if (a.rho_ref && !(a.rho_ref[pix] < a.tau)) {
         // dynamic-only: a static reference ray shows the background itself
         const uint8_t *c_ref = a.views + (((size_t)a.ref * a.H + y) * a.W + x) * 3;
