@@ -214,10 +214,13 @@ static double log_prior(const lfo_params *p, double d, double mu)
     return log(p->gamma + exp(-(z * z) / (2.0 * p->sigma * p->sigma)));
 }
 
-/* Level index nearest mu (clamped to the level range). */
+/* Level index nearest mu (clamped to the level range).  A mu exactly
+ * half-way between two levels takes the lower one, the same rule as the arg
+ * min's ties.  The quotient is formed in double from the single-precision
+ * mu, d_min and d_step, so a half-way point is seen exactly. */
 static int nearest_level(const lfo_params *p, double mu)
 {
-    double j = nearbyint((mu - p->d_min) / p->d_step);
+    double j = ceil((mu - p->d_min) / p->d_step - 0.5);
     if (j < 0.0) j = 0.0;
     if (j > p->D - 1) j = p->D - 1;
     return (int)j;

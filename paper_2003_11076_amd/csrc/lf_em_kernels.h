@@ -371,20 +371,25 @@ __device__ __forceinline__ void prior_window(const EmArgs &a, bool active, float
     jlo = a.D;
     jhi = -1;
     if (active) {
-        jlo = (int)fmaxf(ceilf((mu - a.prior_T - a.d_min) / a.d_step), 0.0f);
-        jhi = (int)fminf(floorf((mu + a.prior_T - a.d_min) / a.d_step), (float)(a.D - 1));
-        jlo = min(jlo, a.D);
-        jhi = max(jhi, -1);
+        // clamped in float before the conversion: mu far outside the level
+        // range (or not finite, with the deferred input check) stays defined
+        jlo = (int)fminf(fmaxf(ceilf((mu - a.prior_T - a.d_min) / a.d_step), 0.0f), (float)a.D);
+        jhi = (int)fmaxf(fminf(floorf((mu + a.prior_T - a.d_min) / a.d_step), (float)(a.D - 1)), -1.0f);
     }
     // uniform across the wave: keep them in scalar registers
     jlo = __builtin_amdgcn_readfirstlane(wave_min(jlo));
     jhi = __builtin_amdgcn_readfirstlane(wave_max(jhi));
 }
 
-// Seed level of the first sweep: the level nearest the prior disparity.
+// The level nearest the prior disparity, clamped to the level range; a mu
+// exactly half-way between two levels takes the lower one (the arg min's tie
+// rule).  The quotient is formed in double from the single-precision mu,
+// d_min and d_step, so a half-way point is seen exactly.  It decides the
+// level of pixels that are not swept (dynamic-only, an empty search window)
+// and seeds the first sweep.
 __device__ __forceinline__ int nearest_level(const EmArgs &a, float mu) {
-    const float jf = rintf((mu - a.d_min) / a.d_step);
-    return (int)fminf(fmaxf(jf, 0.0f), (float)(a.D - 1));
+    const double t = ((double)mu - (double)a.d_min) / (double)a.d_step;
+    return (int)fmin(fmax(ceil(t - 0.5), 0.0), (double)(a.D - 1));
 }
 
 constexpr float kLog2e = 1.44269504088896341f;
@@ -470,9 +475,9 @@ __device__ __forceinline__ void search_window(const EmArgs &a, float mu, int &wl
     if (a.win_half > 0.0f) {
         const float lo = ceilf((mu - a.win_half - a.d_min) / a.d_step);
         const float hi = floorf((mu + a.win_half - a.d_min) / a.d_step);
-        wlo = (int)fmaxf(lo, 0.0f);
-        whi = (int)fminf(hi, (float)(a.D - 1));
-        if (!(lo <= (float)(a.D - 1)) || !(hi >= 0.0f) || wlo > whi) wlo = whi = nearest_level(a, mu);
+        wlo = (int)fminf(fmaxf(lo, 0.0f), (float)(a.D - 1));
+        whi = (int)fmaxf(fminf(hi, (float)(a.D - 1)), 0.0f);
+        if (!(lo <= (float)(a.D - 1)) || !(hi >= 0.0f) || lo > hi) wlo = whi = nearest_level(a, mu);
     }
 }
 

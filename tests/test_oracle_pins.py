@@ -802,3 +802,167 @@ def test_prior_corners_take_the_nearest_level():
     pts = np.array([[0, 0, 4, 1], [20, 10, 7, 0]], np.int32)        # a point on a corner already
     assert len(O.prior_corners(p, pts)) == 5
     assert len(O.prior_corners(p, np.zeros((0, 4), np.int32))) == 0
+
+
+# ---------------------------------------------------------------- rules at their exact boundaries
+
+@pytest.mark.parametrize("d_min,d_step", [(0.0, 1.0), (-3.0, 0.5), (1.25, 0.75)])
+def test_nearest_level_half_way_takes_the_lower_level(d_min, d_step):
+    """A pixel that is not swept (dynamic-only, static reference ray) takes
+    the level nearest mu_T; exactly half-way between two levels the lower one
+    wins, as for the arg min's ties.  Checked against numpy's argmin (first
+    index of the smallest distance) with mu_T on and next to half-way points,
+    and beyond both ends of the level range."""
+    K, H, W, D = 3, 4, 24, 10
+    b = [-1.0, 0.0, 1.0]
+    rng = np.random.default_rng(70)
+    levels = d_min + d_step * np.arange(D, dtype=np.float64)
+    half = (levels[:-1] + levels[1:]) / 2.0
+    mu = np.concatenate([half, half + d_step / 8, half - d_step / 8, levels,
+                         [levels[0] - 5 * d_step, levels[-1] + 5 * d_step, levels[0] - d_step / 2,
+                          levels[-1] + d_step / 2]])
+    assert np.all(mu.astype(np.float32) == mu)                 # every value exact in float32
+    mu = np.resize(mu, H * W).astype(np.float32).reshape(H, W)
+    views = rng.integers(0, 256, size=(K, H, W, 3), dtype=np.uint8)
+    S_P = np.ones((K, H, W), np.float32)                       # every reference ray static: none swept
+    p = _params(K, H, W, b, D, 400.0, ref=1, d_min=d_min, d_step=d_step, dyn_only=True)
+    r = O.reconstruct(p, views, S_P, mu, 1)
+    dist = np.abs(levels[None, None, :] - mu[..., None].astype(np.float64))
+    assert np.array_equal(r["d_idx"], np.argmin(dist, axis=-1))
+    n_half = int(np.isin(mu.astype(np.float64), half).sum())
+    assert n_half >= len(half)
+
+
+def test_empty_search_window_takes_the_lower_nearest_level():
+    """A search window holding no level falls back to the level nearest
+    mu_T, the lower one when mu_T is half-way (numpy's argmin)."""
+    K, H, W, D = 3, 2, 16, 8
+    b = [-1.0, 0.0, 1.0]
+    rng = np.random.default_rng(71)
+    views = rng.integers(0, 256, size=(K, H, W, 3), dtype=np.uint8)
+    S_P = np.full((K, H, W), 0.9, np.float32)
+    mu = np.resize(np.array([0.5, 1.5, 2.5, 3.5, 4.5, 5.5, 6.5, 3.25], np.float32), (H, W)).astype(np.float32)
+    # levels 0, 1, ..., 7 with a window of 0.25: no level within it at a half-way mu
+    p = _params(K, H, W, b, D, 400.0, ref=1, window=0.25)
+    r = O.reconstruct(p, views, S_P, mu, 1)
+    levels = np.arange(D, dtype=np.float64)
+    want = np.argmin(np.abs(levels[None, None, :] - mu[..., None].astype(np.float64)), axis=-1)
+    assert np.array_equal(r["d_idx"], want)
+
+
+def test_support_point_window_with_exactly_static_min_static_pixels_is_kept():
+    """A grid point is a support point when it and at least static_min
+    pixels of its window are static: exactly static_min is enough, one fewer
+    is not (the count is brute-forced here)."""
+    rng = np.random.default_rng(72)
+    K, H, W, D, d0 = 3, 30, 60, 12, 3
+    b = [-1.0, 0.0, 1.0]
+    plane = _plane_views(K, H, W, b, d0, rng)
+    p = _params(K, H, W, b, D, 100.0, ref=1)
+    sp = O.make_support_params()
+    x0, y0 = 27, 12                                        # a grid point (2 + 5i)
+    win = [(y0 + dy, x0 + dx) for dy in range(-2, 3) for dx in range(-2, 3) if (dy, dx) != (0, 0)]
+    for n_dyn, kept in [(25 - sp.static_min, True), (26 - sp.static_min, False)]:
+        S_P = np.ones((K, H, W), np.float32)
+        for (yy, xx) in win[:n_dyn]:
+            S_P[1, yy, xx] = 0.0
+        n_static = int((S_P[1, y0 - 2:y0 + 3, x0 - 2:x0 + 3] >= np.float32(0.7)).sum())
+        assert n_static == 25 - n_dyn
+        pts = O.support_points(p, sp, plane, S_P)
+        ref_pt = (pts[:, 0] == x0) & (pts[:, 1] == y0) & (pts[:, 3] == 1)
+        assert ref_pt.any() == kept, (n_static, kept)
+
+
+def test_consistency_filter_is_the_brute_force_count():
+    """The consistency filter keeps a point with at least incon_min others
+    within incon_radius pixels (Chebyshev) and incon_levels levels, bounds
+    included: checked by brute force over the unfiltered points of a scene
+    whose two planes lie exactly incon_levels apart."""
+    rng = np.random.default_rng(73)
+    K, H, W, D = 3, 40, 90, 16
+    b = [-1.0, 0.0, 1.0]
+    pad = 12
+    tex = rng.integers(0, 256, size=(H, W + 2 * pad, 3))
+    views = np.zeros((K, H, W, 3), np.uint8)
+    for k in range(K):
+        for x in range(W):
+            d = 4 if x < W // 2 else 6                      # two planes, levels 4 and 6
+            views[k, :, x] = tex[:, pad + x + int(b[k]) * d]
+    ones = np.ones((K, H, W), np.float32)
+    p = _params(K, H, W, b, D, 100.0, ref=1)
+    raw = O.support_points(p, O.make_support_params(incon_min=0), views, ones)
+    levels = set(raw[:, 2].tolist())
+    assert {4, 6} <= levels
+    for incon_levels, incon_min in [(2, 8), (2, 12), (1, 8), (3, 12)]:
+        sp = O.make_support_params(incon_levels=incon_levels, incon_min=incon_min)
+        got = O.support_points(p, sp, views, ones)
+        du = np.abs(raw[:, None, 0] - raw[None, :, 0])
+        dy = np.abs(raw[:, None, 1] - raw[None, :, 1])
+        dl = np.abs(raw[:, None, 2] - raw[None, :, 2])
+        near = (du <= 10) & (dy <= 10) & (dl <= incon_levels)
+        np.fill_diagonal(near, False)
+        want = raw[near.sum(axis=1) >= incon_min]
+        assert np.array_equal(got, want), (incon_levels, incon_min)
+    # the bound matters on this scene: pairs exactly two levels apart decide some points
+    a = O.support_points(p, O.make_support_params(incon_levels=2, incon_min=12), views, ones)
+    c = O.support_points(p, O.make_support_params(incon_levels=1, incon_min=12), views, ones)
+    assert len(a) > len(c)
+
+
+def test_transferred_points_landing_on_one_pixel_keep_the_lowest_view():
+    """With the plane at a multiple of the grid step, the grid points of
+    every non-reference view land on the same reference pixels: one point per
+    pixel is kept, from the lowest view (view 0 sees the whole occluded part
+    here)."""
+    rng = np.random.default_rng(74)
+    K, H, W, D, d0 = 5, 40, 100, 16, 5
+    b = [-2.0, -1.0, 0.0, 1.0, 2.0]
+    views = _plane_views(K, H, W, b, d0, rng)
+    views[2, 10:30, 40:70] = rng.integers(0, 256, size=(20, 30, 3))
+    S_P = np.ones((K, H, W), np.float32)
+    S_P[2, 10:30, 40:70] = 0.0
+    p = _params(K, H, W, b, D, 100.0, ref=2)
+    pts = O.support_points(p, O.make_support_params(), views, S_P)
+    moved = pts[:, 3] != 2
+    assert moved.sum() > 20
+    key = pts[:, 1].astype(np.int64) * W + pts[:, 0]
+    assert len(np.unique(key)) == len(key)                  # one point per reference pixel
+    assert np.all(pts[moved, 3] == 0)                       # the lowest view wins every collision
+    # every view's grid point would have landed on these pixels
+    for a in (1, 3, 4):
+        xa = pts[moved, 0] - int(b[a]) * d0
+        assert np.all((xa - 2) % 5 == 0)
+
+
+def test_match_cost_tie_takes_the_lowest_level():
+    """The two sides of the reference see the plane at adjacent levels j and
+    j + 1 (view 0 at j, view 2 at j + 1), so the side-robust cost is exactly
+    0 at both: the lower level is the match."""
+    rng = np.random.default_rng(75)
+    K, H, W, D, j = 3, 30, 80, 12, 4
+    b = [-1.0, 0.0, 1.0]
+    pad = 20
+    tex = rng.integers(0, 256, size=(H, W + 2 * pad, 3))
+    views = np.zeros((K, H, W, 3), np.uint8)
+    views[0] = tex[:, pad - j:pad - j + W]                  # x + b_0 j
+    views[1] = tex[:, pad:pad + W]
+    views[2] = tex[:, pad + (j + 1):pad + (j + 1) + W]      # x + b_2 (j + 1)
+    ones = np.ones((K, H, W), np.float32)
+    p = _params(K, H, W, b, D, 100.0, ref=1)
+    pts = O.support_points(p, O.make_support_params(), views, ones)
+    inner = (pts[:, 0] >= 2 + 2 + j + 1) & (pts[:, 0] < W - 2 - 2 - j - 1)
+    assert inner.sum() > 20
+    assert np.all(pts[inner, 2] == j)
+
+
+def test_prior_corner_takes_the_euclidean_nearest_point():
+    """A corner takes the level of its nearest point in Euclidean distance:
+    here the nearest in L1 (and in Chebyshev) is another point."""
+    p = _params(3, 20, 30, [-1, 0, 1], 10, 100.0, ref=1)
+    pts = np.array([[6, 0, 2, 1], [4, 4, 7, 1], [25, 15, 5, 1]], np.int32)
+    out = O.prior_corners(p, pts)
+    corner = out[(out[:, 0] == 0) & (out[:, 1] == 0)]
+    d2 = (pts[:, 0] - 0.0) ** 2 + (pts[:, 1] - 0.0) ** 2
+    l1 = np.abs(pts[:, 0]) + np.abs(pts[:, 1])
+    assert np.argmin(d2) != np.argmin(l1)
+    assert corner[0, 2] == pts[np.argmin(d2), 2] == 7
