@@ -41,9 +41,11 @@ F_DESC = 2
 ROOT = os.path.dirname(os.path.abspath(__file__))
 # sources of the EM kernel: HBM traffic measured with rocprofv3 counters is
 # reported only while these are unchanged since the measurement
-EM_SOURCES = ("paper_2003_11076_amd/csrc/lf_em_kernels.h", "paper_2003_11076_amd/csrc/lf_em_f32.hip",
-              "paper_2003_11076_amd/csrc/lf_em_dispatch.h", "paper_2003_11076_amd/csrc/lf_em.hip",
-              "paper_2003_11076_amd/csrc/lf_em_f16.hip", "paper_2003_11076_amd/csrc/lf_em_bf16.hip")
+def _em_sources():
+    import glob
+    csrc = os.path.join(ROOT, "paper_2003_11076_amd", "csrc")
+    names = sorted(glob.glob(os.path.join(csrc, "lf_em*.hip")) + glob.glob(os.path.join(csrc, "lf_em*.h")))
+    return [os.path.relpath(n, ROOT) for n in names]
 
 
 def measured_traffic(workload):
@@ -57,7 +59,7 @@ def measured_traffic(workload):
     with open(path) as f:
         rec = json.load(f)
     h = hashlib.sha256()
-    for src in EM_SOURCES:
+    for src in _em_sources():
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
     if h.hexdigest()[:16] != rec.get("src_hash"):

@@ -299,6 +299,42 @@ hipError_t launch_median3(const lf_params *p, const float *in, float *out, hipSt
     return hipGetLastError();
 }
 
+// Refocus of the current state (Eq. 2) into rgb (through rgb_med and the 3x3
+// median when median == 3), the holes into hole (nullable); d_out / q_out
+// (nullable) receive device copies of the level and weights in the same pass.
+hipError_t launch_refocus_frame(const lf_params *p, const Geometry &g, const uint8_t *views, const int32_t *d_idx,
+                                const float *q, const float *rho, float *rgb, uint8_t *hole, float *rgb_med,
+                                int median, int32_t *d_out, float *q_out, hipStream_t s) {
+    RefocusArgs r = make_refocus_args(p, g);
+    r.views = views;
+    r.d_idx = d_idx;
+    r.q = q;
+    r.rho_ref = (p->flags & LF_DYNAMIC_ONLY) ? rho + (size_t)p->ref * p->H * p->W : nullptr;
+    r.tau = p->tau_init;
+    r.rgb = median ? rgb_med : rgb;
+    r.hole = hole;
+    r.d_out = d_out;
+    r.q_out = q_out;
+    hipError_t e = launch_refocus(p, r, s);
+    if (e == hipSuccess && median) e = launch_median3(p, rgb_med, rgb, s);
+    return e;
+}
+
+// objective[t] = sum over blocks b, in block order, of partials[t][b] for
+// t < n: the same additions in the same order as the host sum of the plain
+// context, so both give the same bits.
+hipError_t launch_objective_sum(const double *partials, int n_blocks, int n, double *objective, hipStream_t s) {
+    hipLaunchKernelGGL(lf_objective_sum_kernel, dim3((n + 63) / 64), dim3(64), 0, s, partials, n_blocks, n, objective);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(lf_fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (int32_t *)p, n,
+                       (int32_t)v);
+    return hipGetLastError();
+}
+
 // Row-tile width of the EM kernel: the width (a multiple of the 64-lane
 // wave, up to 256) with the best product of waves resident per SIMD (capped
 // at 4; bounded by the kernel's VGPRs and the CU's LDS) and lanes doing
@@ -330,6 +366,39 @@ int choose_tile(const lf_params *p, const Geometry &g, size_t lds_limit, size_t 
         }
     }
     return best;
+}
+
+lf_status em_launch_shape(const lf_params *p, const Geometry &g, int device, int *tile, size_t *lds) {
+    size_t lds_limit = 0;
+    {
+        int v = 0;
+        hipError_t e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+        if (e != hipSuccess) return hip_error(e, "device attribute");
+        lds_limit = (size_t)v;
+    }
+    size_t lds_cu = 0;
+    {
+        int v = 0;
+        hipError_t e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device);
+        if (e != hipSuccess) return hip_error(e, "device attribute");
+        lds_cu = v > 0 ? (size_t)v : lds_limit;
+    }
+    int vgprs = 0;
+    {
+        // the tile follows the fast sweep's kernel also when the exhaustive
+        // sweep is asked for, so that both use the same blocks and the
+        // objective's FP64 block sums add up in the same order
+        lf_params pf = *p;
+        pf.flags &= ~(uint32_t)LF_EXHAUSTIVE_SWEEP;
+        EmKernel kern = pick_em(&pf, g);
+        hipFuncAttributes fa;
+        if (kern && hipFuncGetAttributes(&fa, (const void *)kern) == hipSuccess) vgprs = fa.numRegs;
+        (void)hipGetLastError();
+    }
+    *tile = choose_tile(p, g, lds_limit, lds_cu, vgprs, lds);
+    if (!*tile)
+        return set_error(LF_EINVAL, "disparity halo needs %zu bytes of LDS per block, more than %zu", *lds, lds_limit);
+    return LF_OK;
 }
 
 }  // namespace lfem
@@ -368,41 +437,15 @@ struct lf_ctx {
     int64_t iters;
 };
 
-static constexpr int kMaxItersPerLaunch = 64;
+
 
 static lf_status ctx_alloc(lf_ctx *c) {
     const lf_params &p = c->p;
     const size_t HW = (size_t)p.H * p.W, KHW = HW * p.K;
     const bool dev_in = p.flags & LF_INPUTS_ON_DEVICE;
     const bool dev_out = p.flags & LF_OUTPUTS_ON_DEVICE;
-    size_t lds_limit = 0;
-    {
-        int v = 0;
-        LF_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device), "device attribute");
-        lds_limit = (size_t)v;
-    }
-    size_t lds_cu = 0;
-    {
-        int v = 0;
-        LF_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device),
-               "device attribute");
-        lds_cu = v > 0 ? (size_t)v : lds_limit;
-    }
-    int vgprs = 0;
-    {
-        // the tile follows the fast sweep's kernel also when the exhaustive
-        // sweep is asked for, so that both use the same blocks and the
-        // objective's FP64 block sums add up in the same order
-        lf_params pf = p;
-        pf.flags &= ~(uint32_t)LF_EXHAUSTIVE_SWEEP;
-        EmKernel kern = pick_em(&pf, c->g);
-        hipFuncAttributes fa;
-        if (kern && hipFuncGetAttributes(&fa, (const void *)kern) == hipSuccess) vgprs = fa.numRegs;
-        (void)hipGetLastError();
-    }
-    c->tile = choose_tile(&p, c->g, lds_limit, lds_cu, vgprs, &c->lds);
-    if (!c->tile)
-        return set_error(LF_EINVAL, "disparity halo needs %zu bytes of LDS per block, more than %zu", c->lds, lds_limit);
+    lf_status st0 = em_launch_shape(&p, c->g, c->device, &c->tile, &c->lds);
+    if (st0 != LF_OK) return st0;
     c->n_blocks = ((p.W + c->tile - 1) / c->tile) * p.H;
     ArenaPlan plan;
     if (!dev_in) {
@@ -641,20 +684,11 @@ lf_status lf_refocus(lf_ctx *c, float *rgb, int32_t *d_idx, float *q, uint8_t *h
     const lf_params &p = c->p;
     const size_t HW = (size_t)p.H * p.W;
     const bool dev_out = p.flags & LF_OUTPUTS_ON_DEVICE;
-    RefocusArgs r = make_refocus_args(&p, c->g);
-    r.views = c->views;
-    r.d_idx = c->d_idx;
-    r.q = c->q;
-    r.rho_ref = (p.flags & LF_DYNAMIC_ONLY) ? c->rho + (size_t)p.ref * HW : nullptr;
-    r.tau = p.tau_init;
-    float *rgb_k = median ? c->rgb_med : (dev_out ? rgb : c->rgb);
-    r.rgb = rgb_k;
-    r.hole = dev_out ? hole : c->hole;
     // device outputs: the refocus pass writes the level and weights too
-    r.d_out = dev_out ? d_idx : nullptr;
-    r.q_out = dev_out ? q : nullptr;
-    LF_HIP(launch_refocus(&p, r, c->stream), "refocus launch");
-    if (median) LF_HIP(launch_median3(&p, c->rgb_med, dev_out ? rgb : c->rgb, c->stream), "median launch");
+    LF_HIP(launch_refocus_frame(&p, c->g, c->views, c->d_idx, c->q, c->rho, dev_out ? rgb : c->rgb,
+                                dev_out ? hole : c->hole, c->rgb_med, median, dev_out ? d_idx : nullptr,
+                                dev_out ? q : nullptr, c->stream),
+           "refocus launch");
     lf_status st = LF_OK;
     if (!dev_out) {
         if (st == LF_OK) st = copy_out(c, rgb, c->rgb, HW * 12);

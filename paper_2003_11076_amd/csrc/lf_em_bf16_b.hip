@@ -1,0 +1,10 @@
+// EM kernel instances with BF16 descriptor storage for 6 to 9 views.
+// Each storage format and view-count range is a translation unit of its own
+// so that the instances compile in parallel.
+#include "lf_em_dispatch.h"
+
+namespace lfem {
+EmKernel pick_em_bf16_b(int K, bool frac, bool exh, bool sym, bool share, bool enumerate) {
+    return pick_em_range<2, 6, 9>(K, frac, exh, sym, share, enumerate);
+}
+}  // namespace lfem

@@ -1,6 +1,6 @@
 // Instantiation of the EM kernel for every view count, shift kind and sweep
-// kind of one storage precision.  Each storage precision is compiled in its
-// own translation unit (lf_em_f32.hip, lf_em_f16.hip, lf_em_bf16.hip).
+// kind of one storage precision.  Each storage precision and range of view
+// counts is compiled in its own translation unit (lf_em_{f32,f16,bf16}_{a,b,c}.hip).
 #pragma once
 
 #include "lf_em_kernels.h"
@@ -60,15 +60,14 @@ static EmKernel pick_em_k(bool frac, bool exh, bool sym, bool share, bool enumer
     return share ? pick_em_fast<K, ST, kSweepShared>(sym, enumerate) : pick_em_fast<K, ST, kSweepLane>(sym, enumerate);
 }
 
-template <int ST>
-static EmKernel pick_em_storage(int K, bool frac, bool exh, bool sym, bool share, bool enumerate) {
-    switch (K) {
-#define LF_CASE(n) \
-    case n: return pick_em_k<n, ST>(frac, exh, sym, share, enumerate);
-        LF_CASE(2) LF_CASE(3) LF_CASE(4) LF_CASE(5) LF_CASE(6) LF_CASE(7) LF_CASE(8) LF_CASE(9)
-        LF_CASE(10) LF_CASE(11) LF_CASE(12) LF_CASE(13) LF_CASE(14) LF_CASE(15) LF_CASE(16)
-#undef LF_CASE
-        default: return nullptr;
+// The instance of view count K in [KLO, KHI] (nullptr outside it).
+template <int ST, int KLO, int KHI>
+static EmKernel pick_em_range(int K, bool frac, bool exh, bool sym, bool share, bool enumerate) {
+    if constexpr (KLO > KHI) {
+        return nullptr;
+    } else {
+        if (K == KLO) return pick_em_k<KLO, ST>(frac, exh, sym, share, enumerate);
+        return pick_em_range<ST, KLO + 1, KHI>(K, frac, exh, sym, share, enumerate);
     }
 }
 

@@ -225,6 +225,18 @@ __global__ __launch_bounds__(256) void lf_fill_i32_kernel(int32_t *p, size_t n, 
     if (i < n) p[i] = v;
 }
 
+// Frame objective of each iteration from the EM kernel's FP64 block sums,
+// summed in block order by one lane per iteration.
+__global__ __launch_bounds__(64) void lf_objective_sum_kernel(const double *__restrict__ partials, int n_blocks,
+                                                              int n, double *__restrict__ objective) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const double *row = partials + (size_t)t * n_blocks;
+    double s = 0.0;
+    for (int b = 0; b < n_blocks; ++b) s += row[b];
+    objective[t] = s;
+}
+
 // grid (ceil(W/256), H, K)
 __global__ __launch_bounds__(256) void lf_seg_scatter_kernel(SegArgs a) {
     const int k = blockIdx.z, y = blockIdx.y;

@@ -19,6 +19,12 @@ using EmKernel = void (*)(EmArgs);
 EmKernel pick_em_f32(int K, bool frac, bool exh, bool sym, bool share, bool enumerate);
 EmKernel pick_em_f16(int K, bool frac, bool exh, bool sym, bool share, bool enumerate);
 EmKernel pick_em_bf16(int K, bool frac, bool exh, bool sym, bool share, bool enumerate);
+// view-count ranges 2-5 (a), 6-9 (b) and 10-16 (c) of each storage format
+#define LF_PICK_PART(name) EmKernel name(int K, bool frac, bool exh, bool sym, bool share, bool enumerate);
+LF_PICK_PART(pick_em_f32_a) LF_PICK_PART(pick_em_f32_b) LF_PICK_PART(pick_em_f32_c)
+LF_PICK_PART(pick_em_f16_a) LF_PICK_PART(pick_em_f16_b) LF_PICK_PART(pick_em_f16_c)
+LF_PICK_PART(pick_em_bf16_a) LF_PICK_PART(pick_em_bf16_b) LF_PICK_PART(pick_em_bf16_c)
+#undef LF_PICK_PART
 
 struct ServeJob;
 using ServeKernel = void (*)(const ServeJob *, int);
@@ -78,5 +84,14 @@ hipError_t launch_descriptors(const lf_params *p, const uint8_t *views, void *fe
 hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *mu_T, const float *q_warm,
                             float *rho, float *omr, float *q, uint32_t *bad, int check, hipStream_t s);
 hipError_t launch_median3(const lf_params *p, const float *in, float *out, hipStream_t s);
+hipError_t launch_em(const lf_params *p, const Geometry &g, EmArgs a, int tile, size_t lds, hipStream_t s);
+hipError_t launch_refocus_frame(const lf_params *p, const Geometry &g, const uint8_t *views, const int32_t *d_idx,
+                                const float *q, const float *rho, float *rgb, uint8_t *hole, float *rgb_med,
+                                int median, int32_t *d_out, float *q_out, hipStream_t s);
+hipError_t launch_objective_sum(const double *partials, int n_blocks, int n, double *objective, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
+// Row-tile width and block LDS of the EM kernel for these parameters on a device.
+lf_status em_launch_shape(const lf_params *p, const Geometry &g, int device, int *tile, size_t *lds);
+constexpr int kMaxItersPerLaunch = 64;
 
 }  // namespace lfem
