@@ -230,6 +230,45 @@ lf_status lf_em_state(lf_ctx *c, float *q, int32_t *d_idx, float *L_pix);
  */
 lf_status lf_em_intermediates(lf_ctx *c, void *feat, float *rho);
 
+/*
+ * lf_em_frame_noalloc -- for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): one whole frame, the work of lf_em_init, lf_em_iterate(n_iters)
+ * and lf_refocus with device inputs and outputs, giving the same bits, with
+ * no allocation of any kind.  The intermediate buffers (descriptors, ray
+ * prior, per-pixel objective, the objective's block sums, the median's input)
+ * live in one fixed device array of LF_NOALLOC_SCRATCH_BYTES that each GPU
+ * holds from the library's first use on it until the process ends.
+ *   p          : parameters as lf_em_init; the pointer flags are implied
+ *                (every pointer below is device memory) and LF_DEFERRED_CHECK
+ *                is ignored.
+ *   views, S_P, mu_T, q_warm : device inputs as lf_em_init (q_warm nullable).
+ *   n_iters    : EM iterations, 1 <= n_iters <= 100000.
+ *   rgb        : device float [H][W][3]; hole device uint8 [H][W] or NULL.
+ *   d_idx, q   : device int32 [H][W] and float [K][H][W]: the EM state,
+ *                written in place (required).
+ *   median     : 0 or 3, as lf_refocus.
+ *   objective  : device double [n_iters] or NULL: the frame objective after
+ *                each iteration, as lf_em_iterate.
+ *   invalid    : device uint32 or NULL: receives the number of invalid input
+ *                values (S_P outside [0,1], mu_T not finite, q_warm outside
+ *                [0,1]); results of a frame with invalid inputs are
+ *                meaningless.
+ *   hip_stream : stream the work is queued on (NULL: the null stream); the
+ *                call returns without waiting for it.
+ * Every call on one GPU uses that GPU's one scratch array, which keeps the
+ * last call's contents: calls that overlap on one GPU (queued on different
+ * streams, or from several threads) race and give undefined results.
+ * Errors: LF_EINVAL (as lf_em_init, plus NULL rgb, d_idx or q, n_iters or
+ * median out of range, a frame whose buffers exceed the scratch array: about
+ * K*H*W*(pair bytes + 8) + H*W*4, plus H*W*12 with the median), LF_EDEVICE.
+ */
+#define LF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+lf_status lf_em_frame_noalloc(const lf_params *p, const uint8_t *views, const float *S_P, const float *mu_T,
+                              const float *q_warm, int32_t n_iters, float *rgb, int32_t *d_idx, float *q,
+                              uint8_t *hole, int32_t median, double *objective, uint32_t *invalid,
+                              void *hip_stream);
+
 /* lf_em_destroy -- wait for the context's work, free it.  NULL is a no-op. */
 void lf_em_destroy(lf_ctx *c);
 

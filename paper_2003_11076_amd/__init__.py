@@ -82,11 +82,12 @@ def lib():
         L.lf_segmentation_maps.argtypes = [vp, vp]
         L.lf_em_check.argtypes = [vp]
         L.lf_em_intermediates.argtypes = [vp, vp, vp]
+        L.lf_em_frame_noalloc.argtypes = [P, vp, vp, vp, vp, i32, vp, vp, vp, vp, i32, vp, vp, vp]
         L.lf_em_destroy.argtypes = [vp]
         L.lf_em_destroy.restype = None
         L.lf_last_error.restype = ctypes.c_char_p
         for f in ("lf_em_init", "lf_em_load", "lf_em_iterate", "lf_refocus", "lf_em_state", "lf_em_intermediates",
-                  "lf_segmentation_maps", "lf_em_check"):
+                  "lf_segmentation_maps", "lf_em_check", "lf_em_frame_noalloc"):
             getattr(L, f).restype = i32
         _bind_server(L)
         _bind_prior(L)
@@ -232,6 +233,17 @@ def lf_segmentation_maps(ctx, labels):
 
 def lf_em_intermediates(ctx, feat=None, rho=None):
     return _check(lib().lf_em_intermediates(ctx, addr(feat), addr(rho)))
+
+
+LF_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def lf_em_frame_noalloc(p: lf_params, views, S_P, mu_T, q_warm, n_iters, rgb, d_idx, q, hole=None, median=0,
+                        objective=None, invalid=None, hip_stream=None):
+    """One whole frame with no allocation; every array is device memory."""
+    return _check(lib().lf_em_frame_noalloc(ctypes.byref(p), addr(views), addr(S_P), addr(mu_T), addr(q_warm),
+                                            int(n_iters), addr(rgb), addr(d_idx), addr(q), addr(hole), int(median),
+                                            addr(objective), addr(invalid), hip_stream))
 
 
 def lf_em_destroy(ctx):
