@@ -346,10 +346,12 @@ lf_status lf_build_prior(const lf_params *p, const lf_support_params *sp, const 
 
 typedef struct lf_server lf_server;   /* opaque */
 
-/* Called once per submitted frame from the server's service thread, after
- * the frame's outputs are in the caller's buffers (status LF_OK) or when the
- * frame failed (LF_EDEVICE).  Must not block for long; may call
- * lf_submit_frame but not lf_server_drain or lf_server_destroy. */
+/* Called once per submitted frame from one of the server's worker threads,
+ * after the frame's outputs are in the caller's buffers (status LF_OK), or
+ * when the frame failed (LF_EINVAL: invalid values in device inputs;
+ * LF_EDEVICE).  A worker in a callback takes no new batch: callbacks should
+ * not block for long.  May call lf_submit_frame but not lf_server_drain or
+ * lf_server_destroy. */
 typedef void (*lf_done_fn)(int64_t frame_id, lf_status status, void *user);
 
 typedef struct {
@@ -360,6 +362,7 @@ typedef struct {
     double wall_s;                                    /* first submission -> last completion  */
     double frames_per_s;                              /* completed / wall_s                   */
     int64_t hbm_in_use, hbm_peak;                     /* bytes of the HBM arena               */
+    int64_t max_batch_frames;                         /* most frames in one launch            */
 } lf_server_stats_t;
 
 /*
@@ -367,35 +370,51 @@ typedef struct {
  * frame (descriptors, ray prior, n_iters EM iterations, refocus, Eq. 2) for
  * frames of any size, view count (K <= 9), level count and storage, with the
  * previous frame's weights of the same stream (same K, H, W) as its first
- * weights instead of the 0.7 threshold (warm start).
+ * weights instead of the 0.7 threshold (warm start).  Four worker threads,
+ * each with its own HIP stream, take batches of pending frames: every frame
+ * of the oldest admissible frame's kernel key (storage, K, integer or
+ * fractional shifts, search window or not) that is admissible then, up to 16,
+ * runs in one kernel launch.  A frame is admissible when no earlier frame of
+ * its stream is running and its buffers fit the HBM budget.
  *   hbm_budget_bytes : device arena (>= 64 KiB) every admitted frame's buffers and every
  *                      stream's warm-start weights come from; frames wait for
- *                      admission until theirs fit.
+ *                      admission until theirs fit.  When nothing running will
+ *                      free memory, the warm starts of idle streams are given
+ *                      up, oldest first (those streams start cold).
  *   max_streams      : stream ids are 0..max_streams-1.
  *   n_iters          : EM iterations per frame.
- *   staging_bytes    : pinned host staging for submitted frames (0: the smaller
- *                      of the budget and 1 GiB); when full, submission returns
- *                      LF_EAGAIN.
+ *   staging_bytes    : pinned host staging for host inputs and outputs (0: the
+ *                      smaller of the budget and 1 GiB); when full, submission
+ *                      of a frame with host buffers returns LF_EAGAIN.  (An
+ *                      argument beyond the paper's problem statement: the host
+ *                      side of the server's memory budget.)
  * Errors: LF_EINVAL, LF_ENOMEM (arena allocation), LF_EDEVICE.
  */
 lf_status lf_server_create(lf_server **out, size_t hbm_budget_bytes, int32_t max_streams, int32_t n_iters,
                            size_t staging_bytes);
 
 /*
- * lf_submit_frame -- queue one frame of stream `stream_id`.  Host inputs
- * (views, S_P, mu_T as in lf_em_init) are copied before return.  Outputs are
- * written to the caller's host buffers before `done` runs: rgb_out float
- * [H][W][3] (required), d_out int32 [H][W] (nullable), q_out float [K][H][W]
- * (nullable).  Frames of one stream complete in submission order; frames of
- * different streams run concurrently, batched into shared launches as they
- * are admitted.  Results do not depend on what else is running.  The
- * output buffers must stay valid until `done` has run for the frame (or
- * lf_server_drain / lf_server_destroy has returned): the server writes them
- * from its service thread.
- * Errors: LF_EINVAL (as lf_em_init, plus K > 9, stream_id out of range, a
- * flag other than LF_PRIOR_WINDOW and LF_DYNAMIC_ONLY set, a frame larger
- * than the arenas), LF_EAGAIN (staging full), or
- * the error a previous device failure left.
+ * lf_submit_frame -- queue one frame of stream `stream_id`.
+ *   p      : parameters as lf_em_init.  Flags: LF_INPUTS_ON_DEVICE (views,
+ *            S_P, mu_T are device memory, used in place: the caller keeps
+ *            them unchanged until `done` has run; their values are checked on
+ *            the device and a frame with invalid values completes with
+ *            LF_EINVAL), LF_OUTPUTS_ON_DEVICE (rgb_out, d_out, q_out are
+ *            device memory, written by the kernel), LF_PRIOR_WINDOW,
+ *            LF_DYNAMIC_ONLY.
+ *   views, S_P, mu_T : inputs as lf_em_init; host inputs are checked and
+ *            copied before return.
+ *   rgb_out : float [H][W][3] (required); d_out int32 [H][W] (nullable);
+ *            q_out float [K][H][W] (nullable).  Written before `done` runs.
+ * Frames of one stream complete in submission order; frames of different
+ * streams run concurrently, batched into shared launches as they are
+ * admitted.  Results do not depend on what else is running.  Output buffers
+ * must stay valid until `done` has run for the frame (or lf_server_drain /
+ * lf_server_destroy has returned).
+ * Errors: LF_EINVAL (as lf_em_init, plus K > 9, stream_id out of range,
+ * LF_EXHAUSTIVE_SWEEP or LF_DEFERRED_CHECK set, a frame larger than the
+ * arenas), LF_EAGAIN (staging full), or the error a previous device failure
+ * left.
  */
 lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, const uint8_t *views,
                           const float *S_P, const float *mu_T, float *rgb_out, int32_t *d_out, float *q_out,

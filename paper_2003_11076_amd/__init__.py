@@ -101,7 +101,7 @@ class lf_server_stats_t(ctypes.Structure):
         ("rejected", ctypes.c_int64), ("batches", ctypes.c_int64), ("mean_batch_frames", ctypes.c_double),
         ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
         ("max_ms", ctypes.c_double), ("wall_s", ctypes.c_double), ("frames_per_s", ctypes.c_double),
-        ("hbm_in_use", ctypes.c_int64), ("hbm_peak", ctypes.c_int64),
+        ("hbm_in_use", ctypes.c_int64), ("hbm_peak", ctypes.c_int64), ("max_batch_frames", ctypes.c_int64),
     ]
 
 

@@ -796,14 +796,15 @@ constexpr int kSweepShared = 0, kSweepExhaustive = 1, kSweepLane = 2;
 // every lane sweeps its whole range.  The levels excluded cannot be the
 // minimum and the reduction keeps the tie rule, so the result is the full
 // sweep's, bit for bit.
+// x_idle is a column inside every view's window (the tile's first), read by
+// lanes without a pixel.
 template <int K, int ST, bool SYM>
 __device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win, const Window (&w)[K],
-                                                 const EmArgs &a, int x, bool work, int jlo, int jhi, int slo,
-                                                 int shi, float Pc, Lane<K> &s, bool with_obj) {
+                                                 const EmArgs &a, int x, int x_idle, bool work, int jlo, int jhi,
+                                                 int slo, int shi, float Pc, Lane<K> &s, bool with_obj) {
     using R = typename Rec<ST>::T;
     const int lane = threadIdx.x & 63;
     const bool masked = a.win_half > 0.0f;
-    const int x_idle = blockIdx.x * a.tile;   // a column inside every window, for lanes without a pixel
 
     float wt[K], invW = 0.0f, cw = 0.0f, best_E = INFINITY;
     int best_j = s.best_j;
@@ -1032,7 +1033,7 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
     for (int it = 0; it < a.n_iters; ++it) {
         const bool with_obj = a.want_obj || it == a.n_iters - 1;
         if constexpr (SW == kSweepShared && !FRAC) {
-            shared_iteration<K, RS, SYM>(win, w, a, x, work, jlo, jhi, slo, shi, Pc, s, with_obj);
+            shared_iteration<K, RS, SYM>(win, w, a, x, x0, work, jlo, jhi, slo, shi, Pc, s, with_obj);
         } else {
             if (work)
                 em_iteration<K, RS, FRAC, SW == kSweepExhaustive, SYM>(win, w, a, x, jlo, jhi, slo, shi, Pc, s,

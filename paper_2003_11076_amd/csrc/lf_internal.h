@@ -28,9 +28,13 @@ LF_PICK_PART(pick_em_bf16_a) LF_PICK_PART(pick_em_bf16_b) LF_PICK_PART(pick_em_b
 
 struct ServeJob;
 using ServeKernel = void (*)(const ServeJob *, int);
-ServeKernel pick_serve_f32();
-ServeKernel pick_serve_f16();
-ServeKernel pick_serve_bf16();
+// frame-server instances of view counts 2-5 (a) and 6-9 (b) per storage format
+ServeKernel pick_serve_f32_a(int K, int kind);
+ServeKernel pick_serve_f32_b(int K, int kind);
+ServeKernel pick_serve_f16_a(int K, int kind);
+ServeKernel pick_serve_f16_b(int K, int kind);
+ServeKernel pick_serve_bf16_a(int K, int kind);
+ServeKernel pick_serve_bf16_b(int K, int kind);
 
 // Integer-shift geometry: when every baseline and both level parameters are
 // integers, footprints x - b_k d_j are exact integers and the kernels index

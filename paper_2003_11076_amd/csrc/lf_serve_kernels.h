@@ -1,13 +1,15 @@
 // Batched frame kernel of the frame server (gfx950).
 //
 // One launch covers every (frame, row tile) pair of a batch of admitted
-// frames, which may differ in size, view count, level count and storage of
-// their own: block b finds its frame through the batch's tile prefix table.
-// Each block runs the whole method for one row tile of 128 pixels of one
-// frame, with nothing written to HBM in between:
+// frames of one kernel key: the same storage format, view count and sweep
+// kind, any size and level count.  Block b finds its frame through the
+// batch's tile prefix table.  Each block runs the whole method for one row
+// tile of kServeTile pixels of one frame, with nothing written to HBM in
+// between:
 //   descriptors of the tile's windows, from three staged rows of R+G+B
 //   (Sec. III-C) -> ray prior of each pixel's rays (Sec. III-B) -> n EM
-//   iterations (Sec. III-C, III-D) -> refocus of the static rays (Eq. 2).
+//   iterations (Sec. III-C, III-D), with the plain context's sweeps ->
+//   refocus of the static rays (Eq. 2).
 // Tiles depend on nothing but their frame's inputs (and the stream's
 // previous weights), so a frame gives the same bits alone or in any mix.
 #pragma once
@@ -19,24 +21,29 @@ namespace lfem {
 constexpr int kServeTile = 128;
 constexpr int kServeMaxViews = 9;
 
+// Sweep kinds of the serve kernel instances (one launch per kind):
+// integer shifts of a unit-spaced symmetric array and of any array, shared
+// by the wave's lanes under the prior bound; integer shifts with a search
+// window, each lane on its own; fractional shifts.
+constexpr int kServeSharedSym = 0, kServeShared = 1, kServeLane = 2, kServeFrac = 3, kServeKinds = 4;
+
 struct ServeJob {
     EmArgs em;               // levels, prior, margins, view order, shape; em.mu_T, em.q, em.d_idx
     const uint8_t *views;    // [K][H][W][3]
     const float *S_P;        // [K][H][W]
-    const float *q_warm;     // [K][H][W] previous weights of the stream, or null (threshold start)
     float *rgb;              // [H][W][3]
-    uint8_t *hole;           // [H][W]
-    int K, ref, frac, sym, tiles_x, tile_start, n_tiles;
+    float *q_out;            // [K][H][W] caller's copy of the weights (device), or null
+    uint32_t *bad;           // count of invalid input values (checked inputs), or null
+    int warm;                // em.q holds the stream's previous weights (the first weights)
+    int check;               // count S_P outside [0,1] and mu_T not finite into *bad
+    int ref, tiles_x, tile_start, n_tiles;
     float tau;
 };
 
-// LDS bytes a job needs: descriptor records plus three int16 rows of
-// intensity sums per view window (with one column of border on each side).
-template <int ST>
-__host__ __device__ inline size_t serve_rec_bytes() { return ST == 0 ? 16 : 8; }
-
-template <int K, int ST, bool FRAC, bool SYM>
+template <int K, int ST, int KIND>
 __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsigned char *lds) {
+    constexpr bool FRAC = KIND == kServeFrac;
+    constexpr bool SYM = KIND == kServeSharedSym;
     using R = typename Rec<ST>::T;
     const EmArgs &a = job.em;
     const int tid = threadIdx.x;
@@ -46,14 +53,13 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
     const int W = a.W, H = a.H;
     const bool active = x < W;
     const size_t HW = (size_t)H * W;
-    const size_t pix = (size_t)y * W + x;
+    const size_t pix = (size_t)y * W + (active ? x : 0);
 
     Window w[K];
     int total;
     view_windows<K, FRAC>(a, x0, w, total);
     R *win = reinterpret_cast<R *>(lds);
     int16_t *lsum = reinterpret_cast<int16_t *>(lds + (size_t)total * sizeof(R));
-    // staged positions of all windows (the intensity rows are sized by these)
 
     // 1) rows y-1, y, y+1 of R+G+B over each window's columns (+1 border)
     int c0[K], nc[K], loff[K];
@@ -102,6 +108,7 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
     bool work = active;   // pixel reconstructed (all of them unless dynamic-only)
     if (active) {
         s.mu = a.mu_T[pix];
+        uint32_t nbad = job.check ? !(fabsf(s.mu) <= 1e6f) : 0u;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const size_t row = ((size_t)a.perm[k] * H + y) * W;
@@ -109,9 +116,14 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
             ray_prior_value(job.S_P + row, W, x, a.b[k], s.mu, ST, r, om);
             s.la[k] = (r > 0.0f ? logf(r) : -INFINITY) + a.lambda;
             s.lb[k] = (om > 0.0f ? logf(om) : -INFINITY);
-            s.q[k] = job.q_warm ? job.q_warm[row + x] : ((r >= job.tau) ? 1.0f : 0.0f);
+            s.q[k] = job.warm ? a.q[row + x] : ((r >= job.tau) ? 1.0f : 0.0f);
             if (k == 0 && a.dyn_only) work = r < job.tau;    // kernel view 0 is the reference
+            if (job.check) {
+                const float sv = job.S_P[row + x];
+                nbad += !(sv >= 0.0f && sv <= 1.0f);
+            }
         }
+        if (nbad) atomicAdd(job.bad, nbad);
         s.best_j = nearest_level(a, s.mu);
 #pragma unroll
         for (int k = 0; k < K; ++k) s.idx0[k] = FRAC ? 0 : lane_index0(w[k], a.bi[k], a.dmin_i, x);
@@ -121,19 +133,27 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
         for (int k = 0; k < K; ++k) s.q[k] = s.la[k] = s.lb[k] = 0.0f;
     }
 
-    // 4) EM iterations
+    // 4) EM iterations: the plain context's sweeps (the same bits)
     const float Pc = kLn2 * __builtin_amdgcn_logf(a.gamma);
     int jlo, jhi, slo, shi;
     prior_window(a, work, s.mu, jlo, jhi);
     search_range(a, work, s.mu, slo, shi);
-    if (work)
-        for (int it = 0; it < a.n_iters; ++it)
-            em_iteration<K, ST, FRAC, false, SYM>(win, w, a, x, jlo, jhi, slo, shi, Pc, s, false);
+    for (int it = 0; it < a.n_iters; ++it) {
+        if constexpr (KIND == kServeSharedSym || KIND == kServeShared) {
+            shared_iteration<K, ST, SYM>(win, w, a, x, x0, work, jlo, jhi, slo, shi, Pc, s, false);
+        } else {
+            if (work) em_iteration<K, ST, FRAC, false, false>(win, w, a, x, jlo, jhi, slo, shi, Pc, s, false);
+        }
+    }
 
     // 5) outputs: weights, level, refocus of the static rays
     if (active) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) a.q[(size_t)a.perm[k] * HW + pix] = s.q[k];
+        for (int k = 0; k < K; ++k) {
+            const size_t i = (size_t)a.perm[k] * HW + pix;
+            a.q[i] = s.q[k];
+            if (job.q_out) job.q_out[i] = s.q[k];
+        }
         a.d_idx[pix] = s.best_j;
         float acc[3] = {0.0f, 0.0f, 0.0f};
         int n = 0;
@@ -170,50 +190,83 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
             }
         }
         float *o = job.rgb + pix * 3;
-        if (!work) {              // static reference ray: the reference pixel is the background
+        if (!work || n == 0) {
+            // a static reference ray (dynamic-only) or no static ray at all:
+            // the reference pixel itself
             const uint8_t *c_ref = job.views + (((size_t)job.ref * H + y) * W + x) * 3;
 #pragma unroll
             for (int c = 0; c < 3; ++c) o[c] = (float)c_ref[c] / 255.0f;
-            job.hole[pix] = 0;
-        } else if (n > 0) {
+        } else {
             const float den = 255.0f * (float)n;
 #pragma unroll
             for (int c = 0; c < 3; ++c) o[c] = acc[c] / den;
-            job.hole[pix] = 0;
-        } else {
-            const uint8_t *c_ref = job.views + (((size_t)job.ref * H + y) * W + x) * 3;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) o[c] = (float)c_ref[c] / 255.0f;
-            job.hole[pix] = 1;
         }
     }
 }
 
-template <int ST>
-__global__ __launch_bounds__(kServeTile) void lf_serve_kernel(const ServeJob *__restrict__ jobs, int n_jobs) {
+template <int K, int ST, int KIND>
+__device__ __forceinline__ void serve_entry(const ServeJob *__restrict__ jobs, int n_jobs) {
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int s_job;
-    if (threadIdx.x == 0) {
-        int j = 0;
-        while (j + 1 < n_jobs && (int)blockIdx.x >= jobs[j + 1].tile_start) ++j;
-        s_job = j;
-    }
-    __syncthreads();
-    const int j = __builtin_amdgcn_readfirstlane(s_job);
+    int j = 0;
+    while (j + 1 < n_jobs && (int)blockIdx.x >= jobs[j + 1].tile_start) ++j;
+    j = __builtin_amdgcn_readfirstlane(j);
     const ServeJob &job = jobs[j];
-    const int tile = (int)blockIdx.x - job.tile_start;
-    const bool frac = job.frac != 0;
-    switch (job.K) {
-#define LF_SERVE_CASE(n)                                              \
-    case n:                                                           \
-        if (frac) serve_tile<n, ST, true, false>(job, tile, lds);     \
-        else if (job.sym) serve_tile<n, ST, false, true>(job, tile, lds); \
-        else serve_tile<n, ST, false, false>(job, tile, lds);         \
-        break;
-        LF_SERVE_CASE(2) LF_SERVE_CASE(3) LF_SERVE_CASE(4) LF_SERVE_CASE(5)
-        LF_SERVE_CASE(6) LF_SERVE_CASE(7) LF_SERVE_CASE(8) LF_SERVE_CASE(9)
-#undef LF_SERVE_CASE
-        default: break;
+    serve_tile<K, ST, KIND>(job, (int)blockIdx.x - job.tile_start, lds);
+}
+
+// Register budgets as the plain context's instances: the shared sweep at
+// four waves per SIMD up to six views and the compiler's own count above;
+// the per-lane sweep at five (up to five FP16/BF16 views), four (up to six)
+// or three waves (up to nine).
+template <int K, int ST, int KIND>
+__global__ __launch_bounds__(kServeTile) void lf_serve_kernel(const ServeJob *__restrict__ jobs, int n_jobs) {
+    serve_entry<K, ST, KIND>(jobs, n_jobs);
+}
+template <int K, int ST, int KIND>
+__global__ __launch_bounds__(kServeTile) __attribute__((amdgpu_waves_per_eu(5, 8))) void lf_serve_kernel_w5(
+    const ServeJob *__restrict__ jobs, int n_jobs) {
+    serve_entry<K, ST, KIND>(jobs, n_jobs);
+}
+template <int K, int ST, int KIND>
+__global__ __launch_bounds__(kServeTile) __attribute__((amdgpu_waves_per_eu(4, 8))) void lf_serve_kernel_w4(
+    const ServeJob *__restrict__ jobs, int n_jobs) {
+    serve_entry<K, ST, KIND>(jobs, n_jobs);
+}
+template <int K, int ST, int KIND>
+__global__ __launch_bounds__(kServeTile) __attribute__((amdgpu_waves_per_eu(3, 8))) void lf_serve_kernel_w3(
+    const ServeJob *__restrict__ jobs, int n_jobs) {
+    serve_entry<K, ST, KIND>(jobs, n_jobs);
+}
+
+using ServeKernel = void (*)(const ServeJob *, int);
+
+template <int K, int ST, int KIND>
+ServeKernel serve_instance() {
+    if constexpr (KIND == kServeSharedSym || KIND == kServeShared) {
+        if constexpr (K <= 6) return lf_serve_kernel_w4<K, ST, KIND>;
+        else return lf_serve_kernel<K, ST, KIND>;
+    } else {
+        if constexpr (K <= 5 && ST != 0) return lf_serve_kernel_w5<K, ST, KIND>;
+        else if constexpr (K <= 6) return lf_serve_kernel_w4<K, ST, KIND>;
+        else return lf_serve_kernel_w3<K, ST, KIND>;
+    }
+}
+
+// The instance of view count K in [KLO, KHI] (nullptr outside it).
+template <int ST, int KLO, int KHI>
+ServeKernel pick_serve_range(int K, int kind) {
+    if constexpr (KLO > KHI) {
+        return nullptr;
+    } else {
+        if (K == KLO) {
+            switch (kind) {
+                case kServeSharedSym: return serve_instance<KLO, ST, kServeSharedSym>();
+                case kServeShared: return serve_instance<KLO, ST, kServeShared>();
+                case kServeLane: return serve_instance<KLO, ST, kServeLane>();
+                default: return serve_instance<KLO, ST, kServeFrac>();
+            }
+        }
+        return pick_serve_range<ST, KLO + 1, KHI>(K, kind);
     }
 }
 

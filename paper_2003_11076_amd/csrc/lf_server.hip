@@ -1,16 +1,19 @@
 // Frame server: continuous batching of light-field frames from many streams.
 //
-// Frames are submitted by any thread.  Their host inputs are copied into a
-// pinned staging arena at submission (when it is full the call returns
-// LF_EAGAIN).  A service thread admits frames in arrival order as soon as
-// their stream is idle and the HBM budget holds their buffers, groups every
-// frame admitted at that moment into one batch, and launches the batch as
-// one kernel (per storage format) covering all (frame, row tile) pairs, on
-// one of several HIP streams, so batches overlap on the device.  When a
-// batch's event completes, outputs are copied to the caller's buffers, the
-// frame's weights stay on the device as its stream's warm start, memory is
-// released and the caller's callback runs.  Kernel boundaries give the
-// batches a coherent view of the inputs the copies wrote.
+// Frames are submitted by any thread.  Host inputs are copied into a pinned
+// staging arena at submission (when it is full the call returns LF_EAGAIN);
+// device inputs are used in place.  A pool of workers, each with its own HIP
+// stream, serves the queue: a free worker admits, in arrival order, every
+// pending frame that shares the oldest admissible frame's kernel key
+// (storage, view count, sweep kind), whose stream has no frame running and
+// whose buffers fit the HBM budget, and runs them as one batch: host->device
+// copies, one kernel launch covering all (frame, row tile) pairs, device->
+// host copies.  Batches of different workers overlap on the device; frames
+// that arrive while others run join the next batch.  When a batch's stream
+// has finished, the worker copies host outputs out of the staging (holding
+// no lock), releases memory, keeps each frame's weights on the device as its
+// stream's warm start, and runs the callbacks.  Kernel boundaries give each
+// batch a coherent view of the inputs the copies wrote.
 #include "lf_em.h"
 #include "lf_internal.h"
 #include "lf_serve_kernels.h"
@@ -23,6 +26,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -72,6 +76,7 @@ class RangeAllocator {
     size_t used() const { return used_; }
     size_t peak() const { return peak_; }
     size_t size() const { return size_; }
+    void reset_peak() { peak_ = used_; }
 
   private:
     std::map<size_t, size_t> free_;
@@ -80,44 +85,65 @@ class RangeAllocator {
 
 using Clock = std::chrono::steady_clock;
 
+ServeKernel pick_serve(int storage, int K, int kind) {
+    switch (storage) {
+        case LF_F32: return K <= 5 ? pick_serve_f32_a(K, kind) : pick_serve_f32_b(K, kind);
+        case LF_F16: return K <= 5 ? pick_serve_f16_a(K, kind) : pick_serve_f16_b(K, kind);
+        default: return K <= 5 ? pick_serve_bf16_a(K, kind) : pick_serve_bf16_b(K, kind);
+    }
+}
+
 struct SrvFrame {
     int64_t id;
     int stream;
     lf_params p;
     Geometry g;
     float lambda;
+    int kind, key;            // sweep kind; kernel key (storage, K, kind): frames of one key share launches
+    bool dev_in, dev_out;
+    const uint8_t *views;     // caller's device inputs (dev_in)
+    const float *S_P, *mu_T;
     float *rgb_out;
     int32_t *d_out;
     float *q_out;
     lf_done_fn done;
     void *user;
-    // pinned staging: inputs then outputs
+    // pinned staging: host inputs, then host outputs
     size_t h_off = 0, h_bytes = 0;
-    size_t in_views, in_sp, in_mu, out_rgb, out_d, out_q, out_hole;
-    // device: frame block (inputs, outputs but q) and the weights block
-    size_t d_off = 0, d_bytes = 0, q_off = 0, q_bytes = 0;
+    size_t in_views = 0, in_sp = 0, in_mu = 0, out_rgb = 0, out_d = 0, out_q = 0;
+    // device frame block: host inputs, and the outputs the caller does not
+    // take in device memory
+    size_t d_off = 0, d_bytes = 0;
+    size_t o_views = 0, o_sp = 0, o_mu = 0, o_rgb = 0, o_d = 0;
+    bool rgb_internal = false, d_internal = false;
+    // the stream's weights block (K*H*W floats)
+    size_t q_bytes = 0;
     bool warm = false;
     int tiles_x = 0, n_tiles = 0;
     size_t lds = 0;
-    Clock::time_point t_submit, t_admit, t_done;
+    Clock::time_point t_submit, t_done;
     lf_status status = LF_OK;
 };
 
 struct SrvStream {
-    bool busy = false;
-    bool has_warm = false;
+    bool busy = false;      // a frame of the stream is admitted and not yet finished
+    bool has_q = false;     // a weights block of shape (K, H, W) is held
+    bool warm = false;      // it holds a finished frame's weights
     int K = 0, H = 0, W = 0;
     size_t q_off = 0, q_bytes = 0;
-    int64_t last_use = 0;      // completion order, for evicting the oldest warm start
-};
-
-struct SrvBatch {
-    int slot;
-    hipEvent_t ev;
-    std::vector<SrvFrame *> frames;
+    int64_t last_use = 0;   // completion order, for evicting the oldest warm start
 };
 
 constexpr size_t kMaxBatch = 16;
+constexpr int kWorkers = 4;
+
+struct SrvWorker {
+    hipStream_t hs = nullptr;
+    size_t djobs_off = 0, hjobs_off = 0;   // job table + per-job invalid-value counters
+    std::thread th;
+};
+
+size_t job_area_bytes() { return kMaxBatch * sizeof(ServeJob) + kMaxBatch * sizeof(uint32_t); }
 
 }  // namespace lfem
 
@@ -128,28 +154,21 @@ struct lf_server {
     int n_iters = 8;
     int max_streams = 1;
     size_t lds_limit = 65536;
-    // device arena
-    char *dpool = nullptr;
+    char *dpool = nullptr;        // device arena
     RangeAllocator dalloc;
-    // pinned staging arena
-    char *hpool = nullptr;
+    char *hpool = nullptr;        // pinned staging arena
     RangeAllocator halloc;
-    // streams of the device work
-    static constexpr int kSlots = 3;
-    hipStream_t hs[kSlots] = {};
-    bool slot_busy[kSlots] = {};
-    size_t djobs_off[kSlots] = {}, hjobs_off[kSlots] = {};   // job tables reserved per slot
-    int64_t use_clock = 0;
+    SrvWorker workers[kWorkers];
     std::vector<SrvStream> streams;
     std::deque<SrvFrame *> pending;
-    std::vector<SrvBatch *> inflight;
-    std::thread worker;
+    int inflight = 0;             // batches admitted and not yet finished
+    int64_t use_clock = 0;
     std::mutex mu;
     std::condition_variable cv, cv_idle;
     bool stop = false;
     int64_t next_id = 0;
     // statistics
-    int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, batches = 0, batch_frames = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, batches = 0, batch_frames = 0, max_batch = 0;
     std::vector<double> lat_ms;
     Clock::time_point t_first, t_last;
     bool any = false;
@@ -164,277 +183,254 @@ size_t frame_lds(const lf_params &p, const Geometry &g) {
     return pairs * rec_bytes(p.storage) + 2 * 3 * (pairs + 2 * (size_t)p.K) + 64;
 }
 
-void fail_frame(SrvFrame *f, lf_status st) { f->status = st; }
+int frame_kind(const lf_params &p, const Geometry &g) {
+    if (g.frac) return kServeFrac;
+    if (p.flags & LF_PRIOR_WINDOW) return kServeLane;
+    return g.sym ? kServeSharedSym : kServeShared;
+}
 
-// Launch one batch (caller holds the lock).  Returns false on a HIP error.
-bool launch_batch(lf_server *s, SrvBatch *b, std::string &err) {
-    hipStream_t st = s->hs[b->slot];
-    const size_t nj = b->frames.size();
-    // the slot's job tables (pinned and device), grouped by storage
-    ServeJob *hj = reinterpret_cast<ServeJob *>(s->hpool + s->hjobs_off[b->slot]);
-    ServeJob *dj = reinterpret_cast<ServeJob *>(s->dpool + s->djobs_off[b->slot]);
-    int order = 0;
-    size_t lds_max[3] = {0, 0, 0};
-    int start[3] = {0, 0, 0}, count[3] = {0, 0, 0}, tiles[3] = {0, 0, 0};
-    for (int stg = 0; stg < 3; ++stg) {
-        start[stg] = order;
-        for (SrvFrame *f : b->frames) {
-            if (f->p.storage != stg) continue;
-            const lf_params &p = f->p;
-            const size_t HW = (size_t)p.H * p.W, KHW = HW * p.K;
-            char *h = s->hpool + f->h_off;
-            char *d = s->dpool + f->d_off;
-            ServeJob &J = hj[order++];
-            std::memset(&J, 0, sizeof J);
-            J.em = make_em_args(&p, f->g, f->lambda);
-            J.em.H = p.H;
-            J.em.W = p.W;
-            J.em.tile = kServeTile;
-            J.em.n_iters = s->n_iters;
-            // device layout of the frame block
-            size_t o = 0;
-            auto carve = [&](size_t bytes) { size_t r = o; o += RangeAllocator::round(bytes); return r; };
-            const size_t o_views = carve(KHW * 3), o_sp = carve(KHW * 4), o_mu = carve(HW * 4), o_rgb = carve(HW * 12),
-                         o_d = carve(HW * 4), o_hole = carve(HW);
-            J.views = reinterpret_cast<const uint8_t *>(d + o_views);
-            J.S_P = reinterpret_cast<const float *>(d + o_sp);
-            J.em.mu_T = reinterpret_cast<const float *>(d + o_mu);
-            J.rgb = reinterpret_cast<float *>(d + o_rgb);
-            J.em.d_idx = reinterpret_cast<int32_t *>(d + o_d);
-            J.hole = reinterpret_cast<uint8_t *>(d + o_hole);
-            J.em.q = reinterpret_cast<float *>(s->dpool + f->q_off);
-            J.q_warm = f->warm ? reinterpret_cast<const float *>(s->dpool + s->streams[f->stream].q_off) : nullptr;
-            J.K = p.K;
-            J.ref = p.ref;
-            J.frac = f->g.frac ? 1 : 0;
-            J.sym = f->g.sym ? 1 : 0;
-            J.tiles_x = f->tiles_x;
-            J.tile_start = tiles[stg];
-            J.n_tiles = f->n_tiles;
-            J.tau = p.tau_init;
-            tiles[stg] += f->n_tiles;
-            lds_max[stg] = std::max(lds_max[stg], f->lds);
-            // inputs to the device
-            hipError_t e;
-            e = hipMemcpyAsync(d + o_views, h + f->in_views, KHW * 3, hipMemcpyHostToDevice, st);
-            if (e == hipSuccess) e = hipMemcpyAsync(d + o_sp, h + f->in_sp, KHW * 4, hipMemcpyHostToDevice, st);
-            if (e == hipSuccess) e = hipMemcpyAsync(d + o_mu, h + f->in_mu, HW * 4, hipMemcpyHostToDevice, st);
-            if (e != hipSuccess) {
-                err = hipGetErrorString(e);
-                return false;
+// Admit one frame (lock held): its device block, and its stream's weights
+// block (used in place by a frame of the same shape).  When nothing in flight
+// will free memory (can_evict), the oldest warm starts of idle streams are
+// given up until it fits, this stream's own last.
+bool admit(lf_server *s, SrvFrame *f, SrvStream &ss, bool can_evict) {
+    const lf_params &p = f->p;
+    if (ss.has_q && !(ss.K == p.K && ss.H == p.H && ss.W == p.W)) {
+        s->dalloc.release(ss.q_off, ss.q_bytes);   // shape changed: the stream starts cold
+        ss.has_q = ss.warm = false;
+    }
+    for (;;) {
+        size_t doff = 0, qoff = 0;
+        bool ok = f->d_bytes == 0 || s->dalloc.alloc(f->d_bytes, doff);
+        if (ok && !ss.has_q) {
+            ok = s->dalloc.alloc(f->q_bytes, qoff);
+            if (!ok && f->d_bytes) s->dalloc.release(doff, f->d_bytes);
+        }
+        if (ok) {
+            f->d_off = doff;
+            if (!ss.has_q) {
+                ss.has_q = true;
+                ss.warm = false;
+                ss.K = p.K;
+                ss.H = p.H;
+                ss.W = p.W;
+                ss.q_off = qoff;
+                ss.q_bytes = f->q_bytes;
             }
+            f->warm = ss.warm;
+            return true;
         }
-        count[stg] = order - start[stg];
+        if (!can_evict) return false;
+        SrvStream *victim = nullptr;
+        for (SrvStream &o : s->streams)
+            if (o.has_q && !o.busy && &o != &ss && (!victim || o.last_use < victim->last_use)) victim = &o;
+        if (!victim && ss.has_q) victim = &ss;
+        if (!victim) return false;
+        s->dalloc.release(victim->q_off, victim->q_bytes);
+        victim->has_q = victim->warm = false;
     }
-    hipError_t e = hipMemcpyAsync(dj, hj, nj * sizeof(ServeJob), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) {
-        err = hipGetErrorString(e);
-        return false;
-    }
-    for (int stg = 0; stg < 3; ++stg) {
-        if (!count[stg]) continue;
-        ServeKernel k = stg == 0 ? pick_serve_f32() : (stg == 1 ? pick_serve_f16() : pick_serve_bf16());
-        hipLaunchKernelGGL(k, dim3(tiles[stg]), dim3(kServeTile), lds_max[stg], st, dj + start[stg], count[stg]);
-        e = hipGetLastError();
-        if (e != hipSuccess) {
-            err = hipGetErrorString(e);
-            return false;
+}
+
+// Form a batch (lock held): pending frames in arrival order with the key of
+// the first admissible one; a stream's frames stay in submission order.
+void form_batch(lf_server *s, std::vector<SrvFrame *> &b) {
+    int key = -1;
+    std::vector<char> blocked((size_t)s->max_streams, 0);
+    for (auto it = s->pending.begin(); it != s->pending.end() && b.size() < kMaxBatch;) {
+        SrvFrame *f = *it;
+        SrvStream &ss = s->streams[f->stream];
+        if (ss.busy || blocked[f->stream] || (key >= 0 && f->key != key)) {
+            blocked[f->stream] = 1;
+            ++it;
+            continue;
         }
+        if (!admit(s, f, ss, b.empty() && s->inflight == 0)) break;   // memory: keep arrival order
+        key = f->key;
+        ss.busy = true;
+        b.push_back(f);
+        it = s->pending.erase(it);
     }
-    // outputs back to the pinned staging
-    for (SrvFrame *f : b->frames) {
+}
+
+// Queue one batch on the worker's stream and wait for it (no lock held).
+bool run_batch(lf_server *s, SrvWorker &wk, std::vector<SrvFrame *> &b, std::string &err) {
+    const hipStream_t st = wk.hs;
+    const size_t nj = b.size();
+    ServeJob *hj = reinterpret_cast<ServeJob *>(s->hpool + wk.hjobs_off);
+    ServeJob *dj = reinterpret_cast<ServeJob *>(s->dpool + wk.djobs_off);
+    uint32_t *hbad = reinterpret_cast<uint32_t *>(s->hpool + wk.hjobs_off + kMaxBatch * sizeof(ServeJob));
+    uint32_t *dbad = reinterpret_cast<uint32_t *>(s->dpool + wk.djobs_off + kMaxBatch * sizeof(ServeJob));
+    int tiles = 0;
+    size_t lds = 0;
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < nj; ++i) {
+        SrvFrame *f = b[i];
         const lf_params &p = f->p;
         const size_t HW = (size_t)p.H * p.W, KHW = HW * p.K;
         char *h = s->hpool + f->h_off;
         char *d = s->dpool + f->d_off;
-        size_t o = 0;
-        auto carve = [&](size_t bytes) { size_t r = o; o += RangeAllocator::round(bytes); return r; };
-        carve(KHW * 3);
-        carve(KHW * 4);
-        carve(HW * 4);
-        const size_t o_rgb = carve(HW * 12), o_d = carve(HW * 4), o_hole = carve(HW);
-        e = hipMemcpyAsync(h + f->out_rgb, d + o_rgb, HW * 12, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(h + f->out_d, d + o_d, HW * 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(h + f->out_hole, d + o_hole, HW, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess && f->q_out)
-            e = hipMemcpyAsync(h + f->out_q, s->dpool + f->q_off, KHW * 4, hipMemcpyDeviceToHost, st);
-        if (e != hipSuccess) {
-            err = hipGetErrorString(e);
-            return false;
+        ServeJob &J = hj[i];
+        std::memset(&J, 0, sizeof J);
+        J.em = make_em_args(&p, f->g, f->lambda);
+        J.em.tile = kServeTile;
+        J.em.n_iters = s->n_iters;
+        J.views = f->dev_in ? f->views : reinterpret_cast<const uint8_t *>(d + f->o_views);
+        J.S_P = f->dev_in ? f->S_P : reinterpret_cast<const float *>(d + f->o_sp);
+        J.em.mu_T = f->dev_in ? f->mu_T : reinterpret_cast<const float *>(d + f->o_mu);
+        J.rgb = f->rgb_internal ? reinterpret_cast<float *>(d + f->o_rgb) : f->rgb_out;
+        J.em.d_idx = f->d_internal ? reinterpret_cast<int32_t *>(d + f->o_d) : f->d_out;
+        J.em.q = reinterpret_cast<float *>(s->dpool + s->streams[f->stream].q_off);
+        J.q_out = f->dev_out ? f->q_out : nullptr;
+        J.bad = dbad + i;
+        J.warm = f->warm ? 1 : 0;
+        J.check = f->dev_in ? 1 : 0;
+        J.ref = p.ref;
+        J.tiles_x = f->tiles_x;
+        J.tile_start = tiles;
+        J.n_tiles = f->n_tiles;
+        J.tau = p.tau_init;
+        hbad[i] = 0;
+        tiles += f->n_tiles;
+        lds = std::max(lds, f->lds);
+        if (!f->dev_in) {
+            e = hipMemcpyAsync(d + f->o_views, h + f->in_views, KHW * 3, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(d + f->o_sp, h + f->in_sp, KHW * 4, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(d + f->o_mu, h + f->in_mu, HW * 4, hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) break;
         }
     }
-    e = hipEventRecord(b->ev, st);
+    // the job table and the zeroed counters in one copy
+    if (e == hipSuccess) e = hipMemcpyAsync(dj, hj, job_area_bytes(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        ServeKernel k = pick_serve(b[0]->p.storage, b[0]->p.K, b[0]->kind);
+        if (!k) {
+            err = "no kernel instance for the frame";
+            return false;
+        }
+        hipLaunchKernelGGL(k, dim3(tiles), dim3(kServeTile), lds, st, dj, (int)nj);
+        e = hipGetLastError();
+    }
+    for (size_t i = 0; i < nj && e == hipSuccess; ++i) {
+        SrvFrame *f = b[i];
+        if (f->dev_out) continue;
+        const lf_params &p = f->p;
+        const size_t HW = (size_t)p.H * p.W, KHW = HW * p.K;
+        char *h = s->hpool + f->h_off;
+        char *d = s->dpool + f->d_off;
+        e = hipMemcpyAsync(h + f->out_rgb, d + f->o_rgb, HW * 12, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && f->d_out) e = hipMemcpyAsync(h + f->out_d, d + f->o_d, HW * 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && f->q_out)
+            e = hipMemcpyAsync(h + f->out_q, s->dpool + s->streams[f->stream].q_off, KHW * 4, hipMemcpyDeviceToHost,
+                               st);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(hbad, dbad, nj * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         err = hipGetErrorString(e);
+        (void)hipGetLastError();
         return false;
+    }
+    for (size_t i = 0; i < nj; ++i) {
+        SrvFrame *f = b[i];
+        if (hbad[i]) {
+            f->status = set_error(LF_EINVAL, "frame %lld: %u input values invalid (S_P outside [0,1] or mu_T not "
+                                             "finite)", (long long)f->id, hbad[i]);
+            continue;
+        }
+        if (f->dev_out) continue;
+        // host outputs out of the staging (no lock held)
+        const lf_params &p = f->p;
+        const size_t HW = (size_t)p.H * p.W, KHW = HW * p.K;
+        const char *h = s->hpool + f->h_off;
+        std::memcpy(f->rgb_out, h + f->out_rgb, HW * 12);
+        if (f->d_out) std::memcpy(f->d_out, h + f->out_d, HW * 4);
+        if (f->q_out) std::memcpy(f->q_out, h + f->out_q, KHW * 4);
     }
     return true;
 }
 
-// Admit frames and launch a batch if a device stream is free (lock held).
-void schedule(lf_server *s) {
-    int slot = -1;
-    for (int i = 0; i < lf_server::kSlots; ++i)
-        if (!s->slot_busy[i]) {
-            slot = i;
-            break;
-        }
-    if (slot < 0 || s->pending.empty()) return;
-    SrvBatch *b = new SrvBatch();
-    b->slot = slot;
-    for (auto it = s->pending.begin(); it != s->pending.end() && b->frames.size() < kMaxBatch;) {
-        SrvFrame *f = *it;
+// Finish a batch (lock held): memory, warm starts, statistics.
+void finish_batch(lf_server *s, std::vector<SrvFrame *> &b, bool ok) {
+    for (SrvFrame *f : b) {
         SrvStream &ss = s->streams[f->stream];
-        if (ss.busy) {
-            ++it;
-            continue;
+        if (!ok && f->status == LF_OK) f->status = LF_EDEVICE;
+        if (f->status == LF_OK) {
+            ss.warm = true;          // the frame's weights are the stream's warm start
+            ss.last_use = ++s->use_clock;
+        } else if (ss.has_q) {
+            s->dalloc.release(ss.q_off, ss.q_bytes);   // weights of a failed frame are not kept
+            ss.has_q = ss.warm = false;
         }
-        const lf_params &p = f->p;
-        const size_t HW = (size_t)p.H * p.W, KHW = HW * p.K;
-        f->d_bytes = RangeAllocator::round(KHW * 3) + RangeAllocator::round(KHW * 4) + RangeAllocator::round(HW * 4) +
-                     RangeAllocator::round(HW * 12) + RangeAllocator::round(HW * 4) + RangeAllocator::round(HW);
-        f->q_bytes = KHW * 4;
-        const bool same_shape = ss.has_warm && ss.K == p.K && ss.H == p.H && ss.W == p.W;
-        if (ss.has_warm && !same_shape) {
-            // shape changed: the stream starts cold, its old weights go
-            s->dalloc.release(ss.q_off, ss.q_bytes);
-            ss.has_warm = false;
-        }
-        size_t doff = 0, qoff = 0;
-        bool fit = false;
-        for (;;) {
-            if (s->dalloc.alloc(f->d_bytes, doff)) {
-                if (s->dalloc.alloc(f->q_bytes, qoff)) {
-                    fit = true;
-                    break;
-                }
-                s->dalloc.release(doff, f->d_bytes);
-            }
-            // nothing in flight or admitted will free memory: give up the
-            // oldest warm start of an idle stream (that stream starts cold)
-            if (!s->inflight.empty() || !b->frames.empty()) break;
-            SrvStream *victim = nullptr;
-            for (SrvStream &o : s->streams)
-                if (o.has_warm && !o.busy && &o != &ss && (!victim || o.last_use < victim->last_use)) victim = &o;
-            if (!victim) break;
-            s->dalloc.release(victim->q_off, victim->q_bytes);
-            victim->has_warm = false;
-        }
-        if (!fit) break;  // budget: wait for memory (arrival order is kept)
-        f->d_off = doff;
-        f->q_off = qoff;
-        f->warm = same_shape;
-        f->t_admit = Clock::now();
-        ss.busy = true;
-        b->frames.push_back(f);
-        it = s->pending.erase(it);
-    }
-    if (b->frames.empty()) {
-        delete b;
-        return;
-    }
-    if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) {
-        s->sticky = LF_EDEVICE;
-        s->sticky_msg = "event creation";
-    }
-    std::string err;
-    if (s->sticky == LF_OK && !launch_batch(s, b, err)) {
-        s->sticky = LF_EDEVICE;
-        s->sticky_msg = "batch launch: " + err;
-    }
-    s->slot_busy[slot] = true;
-    s->batches += 1;
-    s->batch_frames += (int64_t)b->frames.size();
-    s->inflight.push_back(b);
-}
-
-// Finish completed batches (lock held); callbacks are returned to run unlocked.
-void reap(lf_server *s, std::vector<SrvFrame *> &finished) {
-    for (auto it = s->inflight.begin(); it != s->inflight.end();) {
-        SrvBatch *b = *it;
-        hipError_t q = s->sticky == LF_OK ? hipEventQuery(b->ev) : hipSuccess;
-        if (q == hipErrorNotReady) {
-            ++it;
-            continue;
-        }
-        const bool ok = (q == hipSuccess) && s->sticky == LF_OK;
-        if (q != hipSuccess && q != hipErrorNotReady && s->sticky == LF_OK) {
-            s->sticky = LF_EDEVICE;
-            s->sticky_msg = hipGetErrorString(q);
-        }
-        for (SrvFrame *f : b->frames) {
-            const lf_params &p = f->p;
-            const size_t HW = (size_t)p.H * p.W, KHW = HW * p.K;
-            const char *h = s->hpool + f->h_off;
-            SrvStream &ss = s->streams[f->stream];
-            if (ok) {
-                std::memcpy(f->rgb_out, h + f->out_rgb, HW * 12);
-                if (f->d_out) std::memcpy(f->d_out, h + f->out_d, HW * 4);
-                if (f->q_out) std::memcpy(f->q_out, h + f->out_q, KHW * 4);
-                // the frame's weights become the stream's warm start
-                if (ss.has_warm) s->dalloc.release(ss.q_off, ss.q_bytes);
-                ss.has_warm = true;
-                ss.K = p.K;
-                ss.H = p.H;
-                ss.W = p.W;
-                ss.q_off = f->q_off;
-                ss.q_bytes = f->q_bytes;
-                ss.last_use = ++s->use_clock;
-            } else {
-                fail_frame(f, LF_EDEVICE);
-                s->dalloc.release(f->q_off, f->q_bytes);
-            }
-            s->dalloc.release(f->d_off, f->d_bytes);
-            s->halloc.release(f->h_off, f->h_bytes);
-            ss.busy = false;
-            f->t_done = Clock::now();
-            finished.push_back(f);
-        }
-        (void)hipEventDestroy(b->ev);
-        s->slot_busy[b->slot] = false;
-        delete b;
-        it = s->inflight.erase(it);
+        if (f->d_bytes) s->dalloc.release(f->d_off, f->d_bytes);
+        if (f->h_bytes) s->halloc.release(f->h_off, f->h_bytes);
+        ss.busy = false;
+        f->t_done = Clock::now();
     }
 }
 
-void service(lf_server *s) {
+void record(lf_server *s, std::vector<SrvFrame *> &b) {
+    for (SrvFrame *f : b) {
+        const double ms = std::chrono::duration<double, std::milli>(f->t_done - f->t_submit).count();
+        if (f->status == LF_OK) {
+            s->completed += 1;
+            s->lat_ms.push_back(ms);
+        } else {
+            s->failed += 1;
+        }
+        s->t_last = f->t_done;
+        delete f;
+    }
+}
+
+void worker_main(lf_server *s, int wi) {
     (void)hipSetDevice(s->device);
+    SrvWorker &wk = s->workers[wi];
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        std::vector<SrvFrame *> finished;
-        reap(s, finished);
-        schedule(s);
-        const bool idle = s->pending.empty() && s->inflight.empty();
-        if (!finished.empty()) {
-            lk.unlock();
-            for (SrvFrame *f : finished) {
-                if (f->done) f->done(f->id, f->status, f->user);
-            }
-            lk.lock();
-            for (SrvFrame *f : finished) {
-                const double ms = std::chrono::duration<double, std::milli>(f->t_done - f->t_submit).count();
-                if (f->status == LF_OK) {
-                    s->completed += 1;
-                    s->lat_ms.push_back(ms);
-                } else {
-                    s->failed += 1;
+        std::vector<SrvFrame *> b;
+        for (;;) {
+            if (s->sticky != LF_OK) {
+                // after a device failure every pending frame fails
+                while (!s->pending.empty() && b.size() < kMaxBatch) {
+                    SrvFrame *f = s->pending.front();
+                    s->pending.pop_front();
+                    f->status = s->sticky;
+                    f->t_done = Clock::now();
+                    b.push_back(f);
                 }
-                s->t_last = f->t_done;
-                delete f;
+                if (!b.empty()) break;
+            } else {
+                form_batch(s, b);
+                if (!b.empty()) break;
             }
-            s->cv_idle.notify_all();
-            continue;
-        }
-        if (idle) {
-            s->cv_idle.notify_all();
-            if (s->stop) break;
+            if (s->stop && s->pending.empty() && s->inflight == 0) return;
             s->cv.wait(lk);
-        } else if (!s->inflight.empty()) {
-            // device work outstanding: poll its events at a short interval
-            s->cv.wait_for(lk, std::chrono::microseconds(20));
-        } else {
-            s->cv.wait_for(lk, std::chrono::microseconds(200));
         }
+        const bool failed_early = s->sticky != LF_OK;
+        if (!failed_early) {
+            s->inflight += 1;
+            s->batches += 1;
+            s->batch_frames += (int64_t)b.size();
+            s->max_batch = std::max<int64_t>(s->max_batch, (int64_t)b.size());
+            lk.unlock();
+            std::string err;
+            const bool ok = run_batch(s, wk, b, err);
+            lk.lock();
+            if (!ok && s->sticky == LF_OK) {
+                s->sticky = LF_EDEVICE;
+                s->sticky_msg = "batch: " + err;
+            }
+            finish_batch(s, b, ok);
+            s->inflight -= 1;
+        }
+        // memory was released: other workers may admit now
+        s->cv.notify_all();
+        lk.unlock();
+        for (SrvFrame *f : b)
+            if (f->done) f->done(f->id, f->status, f->user);
+        lk.lock();
+        record(s, b);
+        s->cv_idle.notify_all();
     }
 }
 
@@ -445,6 +441,14 @@ double percentile(std::vector<double> v, double q) {
     const size_t i = (size_t)pos;
     const double fr = pos - i;
     return i + 1 < v.size() ? v[i] * (1.0 - fr) + v[i + 1] * fr : v[i];
+}
+
+void server_free(lf_server *s) {
+    for (SrvWorker &w : s->workers)
+        if (w.hs) (void)hipStreamDestroy(w.hs);
+    if (s->hpool) (void)hipHostFree(s->hpool);
+    if (s->dpool) (void)hipFree(s->dpool);
+    delete s;
 }
 
 }  // namespace
@@ -459,6 +463,7 @@ lf_status lf_server_create(lf_server **out, size_t hbm_budget_bytes, int32_t max
     if (n_iters < 0 || n_iters > 1000) return set_error(LF_EINVAL, "n_iters=%d outside [0,1000]", n_iters);
     if (hbm_budget_bytes < ((size_t)64 << 10)) return set_error(LF_EINVAL, "HBM budget below 64 KiB");
     if (staging_bytes == 0) staging_bytes = std::min(hbm_budget_bytes, (size_t)1 << 30);
+    staging_bytes = std::max(staging_bytes, kWorkers * RangeAllocator::round(job_area_bytes()));
     lf_server *s = new lf_server();
     s->n_iters = n_iters;
     s->max_streams = max_streams;
@@ -472,37 +477,31 @@ lf_status lf_server_create(lf_server **out, size_t hbm_budget_bytes, int32_t max
     hipError_t e = hipMalloc((void **)&s->dpool, hbm_budget_bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        delete s;
+        s->dpool = nullptr;
+        server_free(s);
         return set_error(LF_ENOMEM, "HBM arena of %zu bytes: %s", hbm_budget_bytes, hipGetErrorString(e));
     }
     s->dalloc.reset(hbm_budget_bytes);
     e = hipHostMalloc((void **)&s->hpool, staging_bytes, hipHostMallocDefault);
     if (e != hipSuccess) {
-        (void)hipFree(s->dpool);
-        delete s;
+        s->hpool = nullptr;
+        server_free(s);
         return set_error(LF_ENOMEM, "pinned staging of %zu bytes: %s", staging_bytes, hipGetErrorString(e));
     }
     s->halloc.reset(staging_bytes);
-    for (int i = 0; i < lf_server::kSlots; ++i) {
-        if (!s->dalloc.alloc(kMaxBatch * sizeof(ServeJob), s->djobs_off[i]) ||
-            !s->halloc.alloc(kMaxBatch * sizeof(ServeJob), s->hjobs_off[i])) {
-            (void)hipHostFree(s->hpool);
-            (void)hipFree(s->dpool);
-            delete s;
+    for (SrvWorker &w : s->workers) {
+        if (!s->dalloc.alloc(job_area_bytes(), w.djobs_off) || !s->halloc.alloc(job_area_bytes(), w.hjobs_off)) {
+            server_free(s);
             return set_error(LF_EINVAL, "budget or staging too small for the job tables");
         }
-    }
-    for (int i = 0; i < lf_server::kSlots; ++i) {
-        e = hipStreamCreateWithFlags(&s->hs[i], hipStreamNonBlocking);
+        e = hipStreamCreateWithFlags(&w.hs, hipStreamNonBlocking);
         if (e != hipSuccess) {
-            for (int j = 0; j < i; ++j) (void)hipStreamDestroy(s->hs[j]);
-            (void)hipHostFree(s->hpool);
-            (void)hipFree(s->dpool);
-            delete s;
+            w.hs = nullptr;
+            server_free(s);
             return hip_error(e, "stream creation");
         }
     }
-    s->worker = std::thread(service, s);
+    for (int i = 0; i < kWorkers; ++i) s->workers[i].th = std::thread(worker_main, s, i);
     *out = s;
     return LF_OK;
 }
@@ -517,17 +516,29 @@ lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, c
     if (stream_id < 0 || stream_id >= s->max_streams)
         return set_error(LF_EINVAL, "stream_id=%d outside [0,%d)", stream_id, s->max_streams);
     if (p->K > kServeMaxViews) return set_error(LF_EINVAL, "the server handles K <= %d views", kServeMaxViews);
-    if (p->flags & (LF_INPUTS_ON_DEVICE | LF_OUTPUTS_ON_DEVICE | LF_EXHAUSTIVE_SWEEP))
-        return set_error(LF_EINVAL, "the server takes host inputs and outputs, and of the flags only "
+    if (p->flags & (LF_EXHAUSTIVE_SWEEP | LF_DEFERRED_CHECK))
+        return set_error(LF_EINVAL, "the server takes of the flags only LF_INPUTS_ON_DEVICE, LF_OUTPUTS_ON_DEVICE, "
                                     "LF_PRIOR_WINDOW and LF_DYNAMIC_ONLY");
     if (!views || !S_P || !mu_T || !rgb_out) return set_error(LF_EINVAL, "views, S_P, mu_T and rgb_out are required");
-    st = validate_host_values(p, S_P, mu_T, nullptr);
-    if (st != LF_OK) return st;
     SrvFrame *f = new SrvFrame();
     f->p = *p;
+    f->dev_in = (p->flags & LF_INPUTS_ON_DEVICE) != 0;
+    f->dev_out = (p->flags & LF_OUTPUTS_ON_DEVICE) != 0;
+    if (!f->dev_in) {
+        st = validate_host_values(p, S_P, mu_T, nullptr);
+        if (st != LF_OK) {
+            delete f;
+            return st;
+        }
+    }
     f->g = make_geometry(p);
     f->lambda = derived_lambda(p);
+    f->kind = frame_kind(*p, f->g);
+    f->key = (p->storage * (kServeMaxViews + 1) + p->K) * kServeKinds + f->kind;
     f->stream = stream_id;
+    f->views = views;
+    f->S_P = S_P;
+    f->mu_T = mu_T;
     f->rgb_out = rgb_out;
     f->d_out = d_out;
     f->q_out = q_out;
@@ -542,42 +553,64 @@ lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, c
                          s->lds_limit);
     }
     const size_t HW = (size_t)p->H * p->W, KHW = HW * p->K;
-    size_t o = 0;
-    auto carve = [&](size_t bytes) { size_t r = o; o += RangeAllocator::round(bytes); return r; };
-    f->in_views = carve(KHW * 3);
-    f->in_sp = carve(KHW * 4);
-    f->in_mu = carve(HW * 4);
-    f->out_rgb = carve(HW * 12);
-    f->out_d = carve(HW * 4);
-    f->out_q = carve(KHW * 4);
-    f->out_hole = carve(HW);
-    f->h_bytes = o;
+    {
+        size_t o = 0;
+        auto carve = [&](size_t bytes) { size_t r = o; o += RangeAllocator::round(bytes); return r; };
+        if (!f->dev_in) {
+            f->in_views = carve(KHW * 3);
+            f->in_sp = carve(KHW * 4);
+            f->in_mu = carve(HW * 4);
+        }
+        if (!f->dev_out) {
+            f->out_rgb = carve(HW * 12);
+            if (d_out) f->out_d = carve(HW * 4);
+            if (q_out) f->out_q = carve(KHW * 4);
+        }
+        f->h_bytes = o;
+    }
+    {
+        size_t o = 0;
+        auto carve = [&](size_t bytes) { size_t r = o; o += RangeAllocator::round(bytes); return r; };
+        if (!f->dev_in) {
+            f->o_views = carve(KHW * 3);
+            f->o_sp = carve(KHW * 4);
+            f->o_mu = carve(HW * 4);
+        }
+        f->rgb_internal = !f->dev_out;
+        f->d_internal = !f->dev_out || !d_out;
+        if (f->rgb_internal) f->o_rgb = carve(HW * 12);
+        if (f->d_internal) f->o_d = carve(HW * 4);
+        f->d_bytes = o;
+    }
+    f->q_bytes = KHW * 4;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->sticky != LF_OK) {
             delete f;
             return set_error(s->sticky, "server failed earlier: %s", s->sticky_msg.c_str());
         }
-        // a frame that could never fit the arenas is an argument error
-        const size_t need = RangeAllocator::round(KHW * 3) + RangeAllocator::round(KHW * 4) +
-                            RangeAllocator::round(HW * 4) + RangeAllocator::round(HW * 12) +
-                            RangeAllocator::round(HW * 4) + RangeAllocator::round(HW) + RangeAllocator::round(KHW * 4);
-        const size_t reserved = lf_server::kSlots * RangeAllocator::round(kMaxBatch * sizeof(ServeJob));
-        if (f->h_bytes + reserved > s->halloc.size() || need + reserved > s->dalloc.size()) {
+        // a frame that could never fit the arenas is an argument error (with
+        // every other stream's weights given up, a frame needs its own
+        // block and its stream's weights)
+        const size_t reserved = kWorkers * RangeAllocator::round(job_area_bytes());
+        if (f->h_bytes + reserved > s->halloc.size() ||
+            RangeAllocator::round(f->d_bytes) + RangeAllocator::round(f->q_bytes) + reserved > s->dalloc.size()) {
             delete f;
             return set_error(LF_EINVAL, "frame larger than the server's arenas");
         }
-        if (!s->halloc.alloc(f->h_bytes, f->h_off)) {
+        if (f->h_bytes && !s->halloc.alloc(f->h_bytes, f->h_off)) {
             s->rejected += 1;
             delete f;
             return set_error(LF_EAGAIN, "staging full; retry when frames complete");
         }
         f->id = s->next_id++;
     }
-    char *h = s->hpool + f->h_off;
-    std::memcpy(h + f->in_views, views, KHW * 3);
-    std::memcpy(h + f->in_sp, S_P, KHW * 4);
-    std::memcpy(h + f->in_mu, mu_T, HW * 4);
+    if (!f->dev_in) {
+        char *h = s->hpool + f->h_off;
+        std::memcpy(h + f->in_views, views, KHW * 3);
+        std::memcpy(h + f->in_sp, S_P, KHW * 4);
+        std::memcpy(h + f->in_mu, mu_T, HW * 4);
+    }
     f->t_submit = t_call;
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -596,8 +629,8 @@ lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, c
 lf_status lf_server_drain(lf_server *s) {
     if (!s) return set_error(LF_EINVAL, "server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
-    s->cv.notify_one();
-    s->cv_idle.wait(lk, [&] { return s->pending.empty() && s->inflight.empty(); });
+    s->cv.notify_all();
+    s->cv_idle.wait(lk, [&] { return s->pending.empty() && s->inflight == 0; });
     if (s->sticky != LF_OK) return set_error(s->sticky, "%s", s->sticky_msg.c_str());
     return LF_OK;
 }
@@ -625,15 +658,17 @@ lf_status lf_server_stats(lf_server *s, lf_server_stats_t *out) {
     out->frames_per_s = out->wall_s > 0 ? s->completed / out->wall_s : 0.0;
     out->hbm_in_use = (int64_t)s->dalloc.used();
     out->hbm_peak = (int64_t)s->dalloc.peak();
+    out->max_batch_frames = s->max_batch;
     return LF_OK;
 }
 
 lf_status lf_server_reset_stats(lf_server *s) {
     if (!s) return set_error(LF_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    s->submitted = s->completed = s->failed = s->rejected = s->batches = s->batch_frames = 0;
+    s->submitted = s->completed = s->failed = s->rejected = s->batches = s->batch_frames = s->max_batch = 0;
     s->lat_ms.clear();
     s->any = false;
+    s->dalloc.reset_peak();
     return LF_OK;
 }
 
@@ -645,14 +680,11 @@ void lf_server_destroy(lf_server *s) {
         s->stop = true;
     }
     s->cv.notify_all();
-    if (s->worker.joinable()) s->worker.join();
-    for (int i = 0; i < lf_server::kSlots; ++i) {
-        (void)hipStreamSynchronize(s->hs[i]);
-        (void)hipStreamDestroy(s->hs[i]);
-    }
-    (void)hipHostFree(s->hpool);
-    (void)hipFree(s->dpool);
-    delete s;
+    for (SrvWorker &w : s->workers)
+        if (w.th.joinable()) w.th.join();
+    for (SrvWorker &w : s->workers)
+        if (w.hs) (void)hipStreamSynchronize(w.hs);
+    server_free(s);
 }
 
 }  // extern "C"

@@ -181,26 +181,24 @@ def test_admission_waits_for_budget_and_drops_nothing():
 
 
 def test_submission_backpressure():
-    """Staging full -> LF_EAGAIN.  The first frame's completion callback holds
-    the service thread (at most 30 s) until the test has seen LF_EAGAIN, so
-    the staged frames cannot complete in the meantime."""
+    """Staging full -> LF_EAGAIN.  Every completion callback holds its worker
+    (at most 30 s) until the test has seen LF_EAGAIN, so once the workers are
+    held no staged frame can complete in the meantime."""
     import paper_2003_11076_amd as LF
     case = random_case(5, 16, 256, 16, storage="f16", seed=5)
     _say("server staging back-pressure")
     release = threading.Event()
     got_eagain = False
     with Server(n_iters=1, staging=700 * 1024) as srv:      # two frames of 311 KB fit
-        first = {}
 
         def hold(fid, status, user):
-            if not first.get("held"):          # the first completion holds the service thread
-                first["held"] = True
-                release.wait(30.0)
+            release.wait(30.0)
             srv._on_done(fid, status, user)
 
         srv._cb = LF.lf_done_fn(hold)
+        srv.keep.append(srv._cb)
         try:
-            for i in range(20):
+            for i in range(40):
                 try:
                     srv.submit(i % 4, case)
                 except LF.LFError as e:
@@ -213,6 +211,142 @@ def test_submission_backpressure():
         srv.submit(0, case)                       # accepted again once frames completed
         srv.drain()
     assert got_eagain
+
+
+def _hold_workers(srv, LF, release, n_workers=4):
+    """Occupies every worker of the server: one frame of a distinct kernel
+    key per worker (distinct keys never share a batch), each completion
+    callback held until `release` is set (at most 30 s).  Returns once all
+    workers are held."""
+    import time
+    held = threading.Semaphore(0)
+
+    def hold(fid, status, user):
+        held.release()
+        release.wait(30.0)
+        srv._on_done(fid, status, user)
+
+    srv._cb = LF.lf_done_fn(hold)
+    srv.keep.append(srv._cb)           # alive until the server is destroyed
+    for i in range(n_workers):
+        srv.submit(100 + i, random_case(2 + i, 3, 40, 8, storage="f32", seed=90 + i))
+    t0 = time.monotonic()
+    for _ in range(n_workers):
+        assert held.acquire(timeout=30.0), "workers not all busy"
+    assert time.monotonic() - t0 < 30.0
+    srv._cb = LF.lf_done_fn(srv._on_done)
+
+
+def test_frames_waiting_together_share_one_launch():
+    """Frames of one kernel key that wait while every worker is busy run in
+    one launch, and give the bits of each frame alone."""
+    import paper_2003_11076_amd as LF
+    frames = [random_case(5, 6, 150, 24, storage="f16", seed=300 + i) for i in range(6)]
+    _say("server: six frames queued behind busy workers")
+    alone = []
+    with Server(n_iters=3, streams=128) as srv:
+        for i, c in enumerate(frames):
+            _, out = srv.submit(i, c)
+            srv.drain()
+            alone.append(out)
+    release = threading.Event()
+    with Server(n_iters=3, streams=128) as srv:
+        try:
+            _hold_workers(srv, LF, release)
+            outs = [srv.submit(i, c)[1] for i, c in enumerate(frames)]
+        finally:
+            release.set()
+        srv.drain()
+        st = srv.stats()
+    # the four frames that held the workers, then the six queued ones
+    assert st.completed == 10 and st.failed == 0, (st.completed, st.failed)
+    assert st.max_batch_frames >= 2, st.max_batch_frames
+    print(f"queued frames: {st.batches} launches, at most {st.max_batch_frames} frames in one")
+    for a, b in zip(alone, outs):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_device_inputs_and_outputs_equal_host_ones():
+    """LF_INPUTS_ON_DEVICE / LF_OUTPUTS_ON_DEVICE: the same bits as host
+    buffers and as the plain context, warm start included."""
+    import torch
+    import paper_2003_11076_amd as LF
+    dev = torch.device("cuda:0")
+    cases = [random_case(5, 7, 170, 24, storage="f16", seed=41), random_case(5, 7, 170, 24, storage="f16", seed=42),
+             random_case(3, 5, 90, 16, storage="f32", seed=43)]
+    _say("server: device inputs and outputs")
+    host = []
+    with Server(n_iters=2) as srv:
+        for c in cases:
+            host.append(srv.submit(0 if c.K == 5 else 1, c)[1])
+        srv.drain()
+    flags = LF.LF_INPUTS_ON_DEVICE | LF.LF_OUTPUTS_ON_DEVICE
+    devout, keep = [], []
+    with Server(n_iters=2) as srv:
+        for c in cases:
+            ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (c.views, c.S_P, c.mu_T)]
+            o = (torch.full((c.H, c.W, 3), -1.0, device=dev), torch.full((c.H, c.W), -1, dtype=torch.int32, device=dev),
+                 torch.full((c.K, c.H, c.W), -1.0, device=dev))
+            keep.append((ins, o))
+            LF.lf_submit_frame(srv.srv, 0 if c.K == 5 else 1, c.api_params(flags), *ins, *o, srv._cb)
+        srv.drain()
+        torch.cuda.synchronize()
+        devout = [[t.cpu().numpy() for t in o] for _, o in keep]
+    for h, d in zip(host, devout):
+        for a, b in zip(h, d):
+            assert np.array_equal(a, b)
+    prgb, pd, pq = _plain(cases[1], 2, q_warm=host[0][2])
+    assert np.array_equal(devout[1][0], prgb) and np.array_equal(devout[1][1], pd)
+    assert np.array_equal(devout[1][2], pq)
+
+
+def test_invalid_device_inputs_fail_the_frame_only():
+    import torch
+    import paper_2003_11076_amd as LF
+    dev = torch.device("cuda:0")
+    good = random_case(3, 4, 64, 8, storage="f32", seed=7)
+    bad_sp = good.S_P.copy()
+    bad_sp[1, 2, 5] = 1.5
+    _say("server: invalid values in device inputs")
+    flags = LF.LF_INPUTS_ON_DEVICE | LF.LF_OUTPUTS_ON_DEVICE
+    keep = []
+    with Server(n_iters=1) as srv:
+        fids = []
+        for i, sp in enumerate((bad_sp, good.S_P)):
+            ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (good.views, sp, good.mu_T)]
+            o = torch.zeros((good.H, good.W, 3), device=dev)
+            keep.append((ins, o))
+            fids.append(LF.lf_submit_frame(srv.srv, i, good.api_params(flags), *ins, o, None, None, srv._cb))
+        srv.drain()
+        st = srv.stats()
+        assert srv.done[fids[0]] == LF.LF_EINVAL and srv.done[fids[1]] == LF.LF_OK
+        assert st.completed == 1 and st.failed == 1
+
+
+def test_tight_budget_serves_a_warm_stream():
+    """A budget holding one frame's buffers and its stream's weights only:
+    consecutive frames of the stream reuse the weights in place, and drain
+    returns."""
+    import paper_2003_11076_amd as LF
+    c = random_case(4, 6, 120, 16, storage="f16", seed=8)
+    lo, hi = 64 << 10, 8 << 20
+    while hi - lo > 256:                       # smallest budget the frame is accepted with
+        mid = (lo + hi) // 2
+        try:
+            with Server(budget=mid, n_iters=1, staging=32 << 20) as srv:
+                srv.submit(0, c)
+                srv.drain()
+            hi = mid
+        except LF.LFError as e:
+            assert e.status == LF.LF_EINVAL
+            lo = mid
+    _say(f"server: three frames of one stream in a {hi} byte budget")
+    with Server(budget=hi, n_iters=1, staging=32 << 20) as srv:
+        outs = [srv.submit(0, c)[1] for _ in range(3)]
+        srv.drain()
+        st = srv.stats()
+    assert st.completed == 3 and st.failed == 0
 
 
 def test_server_rejects_bad_frames():
