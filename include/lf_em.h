@@ -201,6 +201,19 @@ lf_status lf_refocus(lf_ctx *c, float *rgb, int32_t *d_idx, float *q, uint8_t *h
 lf_status lf_segmentation_maps(lf_ctx *c, uint8_t *labels);
 
 /*
+ * lf_em_sweep_count -- diagnostics of the M-step's work: runs n_iters EM
+ * iterations exactly as lf_em_iterate (the same state afterwards) and
+ * returns in *level_steps the number of level steps the sweeps took, summed
+ * over the waves of 64 pixels and the iterations: a wave that sweeps n
+ * levels for its pixels counts n, so 64 * level_steps / (H * W * D * n_iters)
+ * is the share of the full sweep's level evaluations the hardware issued
+ * (the prior bound skips levels that cannot win; lanes of a wave sweep
+ * together).  Waits for the stream.
+ * Errors: as lf_em_iterate, LF_EINVAL (level_steps NULL).
+ */
+lf_status lf_em_sweep_count(lf_ctx *c, int32_t n_iters, uint64_t *level_steps);
+
+/*
  * lf_em_check -- wait for all work queued on the context's stream and report
  * a deferred input check (LF_DEFERRED_CHECK): LF_EINVAL when any frame loaded
  * since the last report had invalid values (the frame is then unloaded).
@@ -419,6 +432,12 @@ lf_status lf_server_create(lf_server **out, size_t hbm_budget_bytes, int32_t max
 lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, const uint8_t *views,
                           const float *S_P, const float *mu_T, float *rgb_out, int32_t *d_out, float *q_out,
                           lf_done_fn done, void *user, int64_t *frame_id);
+
+/* lf_server_hold -- hold (hold != 0) or release admission: while held, no
+ * new batch starts and submitted frames queue, so that a group of frames
+ * submitted together is admitted together (they share launches as their
+ * kernel keys allow).  lf_server_drain releases a hold. */
+lf_status lf_server_hold(lf_server *s, int32_t hold);
 
 /* lf_server_drain -- block until every submitted frame has completed. */
 lf_status lf_server_drain(lf_server *s);

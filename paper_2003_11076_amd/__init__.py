@@ -82,12 +82,13 @@ def lib():
         L.lf_segmentation_maps.argtypes = [vp, vp]
         L.lf_em_check.argtypes = [vp]
         L.lf_em_intermediates.argtypes = [vp, vp, vp]
+        L.lf_em_sweep_count.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint64)]
         L.lf_em_frame_noalloc.argtypes = [P, vp, vp, vp, vp, i32, vp, vp, vp, vp, i32, vp, vp, vp]
         L.lf_em_destroy.argtypes = [vp]
         L.lf_em_destroy.restype = None
         L.lf_last_error.restype = ctypes.c_char_p
         for f in ("lf_em_init", "lf_em_load", "lf_em_iterate", "lf_refocus", "lf_em_state", "lf_em_intermediates",
-                  "lf_segmentation_maps", "lf_em_check", "lf_em_frame_noalloc"):
+                  "lf_segmentation_maps", "lf_em_check", "lf_em_frame_noalloc", "lf_em_sweep_count"):
             getattr(L, f).restype = i32
         _bind_server(L)
         _bind_prior(L)
@@ -161,11 +162,13 @@ def _bind_server(L):
     L.lf_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, i32, i32, ctypes.c_size_t]
     L.lf_submit_frame.argtypes = [vp, i32, P, vp, vp, vp, vp, vp, vp, lf_done_fn, vp, ctypes.POINTER(ctypes.c_int64)]
     L.lf_server_drain.argtypes = [vp]
+    L.lf_server_hold.argtypes = [vp, i32]
     L.lf_server_stats.argtypes = [vp, ctypes.POINTER(lf_server_stats_t)]
     L.lf_server_reset_stats.argtypes = [vp]
     L.lf_server_destroy.argtypes = [vp]
     L.lf_server_destroy.restype = None
-    for f in ("lf_server_create", "lf_submit_frame", "lf_server_drain", "lf_server_stats", "lf_server_reset_stats"):
+    for f in ("lf_server_create", "lf_submit_frame", "lf_server_drain", "lf_server_stats", "lf_server_reset_stats",
+              "lf_server_hold"):
         getattr(L, f).restype = i32
 
 
@@ -223,6 +226,13 @@ def lf_em_state(ctx, q=None, d_idx=None, L_pix=None):
     return _check(lib().lf_em_state(ctx, addr(q), addr(d_idx), addr(L_pix)))
 
 
+def lf_em_sweep_count(ctx, n_iters) -> int:
+    """Runs n_iters iterations; returns the sweeps' level steps summed over waves."""
+    v = ctypes.c_uint64(0)
+    _check(lib().lf_em_sweep_count(ctx, int(n_iters), ctypes.byref(v)))
+    return v.value
+
+
 def lf_em_check(ctx):
     return _check(lib().lf_em_check(ctx))
 
@@ -266,6 +276,10 @@ def lf_submit_frame(srv, stream_id, p: lf_params, views, S_P, mu_T, rgb_out, d_o
                                  addr(rgb_out), addr(d_out), addr(q_out), done if done is not None else lf_done_fn(),
                                  user, ctypes.byref(fid)))
     return fid.value
+
+
+def lf_server_hold(srv, hold):
+    return _check(lib().lf_server_hold(srv, int(bool(hold))))
 
 
 def lf_server_drain(srv):

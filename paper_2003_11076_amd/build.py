@@ -38,8 +38,13 @@ def _deps():
     return _sources() + glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
 
 
-def _compile(src):
+def _compile(src, incremental=False):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        # every header counts as a dependency of every source
+        deps = [src] + glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+        if all(os.path.getmtime(obj) >= os.path.getmtime(d) for d in deps):
+            return obj, ""
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
@@ -48,14 +53,16 @@ def _compile(src):
     return obj, err
 
 
-def build(force: bool = True, verbose: bool = False) -> str:
-    """Compile all HIP sources and link liblfem.so.  Returns the library path."""
+def build(force: bool = True, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile all HIP sources and link liblfem.so.  Returns the library path.
+    incremental: recompile only sources older than their object (or than any
+    header)."""
     if not force and os.path.exists(OUT) and all(os.path.getmtime(OUT) >= os.path.getmtime(d) for d in _deps()):
         return OUT
     os.makedirs(BUILD, exist_ok=True)
     srcs = _sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        results = list(ex.map(_compile, srcs))
+        results = list(ex.map(lambda src: _compile(src, incremental), srcs))
     for _, err in results:
         if verbose and err.strip():
             print(err, file=sys.stderr)
@@ -69,4 +76,4 @@ def build(force: bool = True, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(force="--force" in sys.argv or True, verbose=True))
+    print(build(force=True, verbose=True, incremental="--incremental" in sys.argv))

@@ -428,6 +428,7 @@ struct lf_ctx {
     uint8_t *hole;
     double *obj;
     uint32_t *bad;
+    unsigned long long *sweep;  // level-step counter of lf_em_sweep_count
     double *h_obj;          // pinned
     uint32_t *h_bad;        // pinned
     bool check_pending;     // deferred value check of device inputs not yet read
@@ -462,6 +463,7 @@ static lf_status ctx_alloc(lf_ctx *c) {
     plan.add(&c->lpix, HW * 4);
     plan.add(&c->obj, (size_t)kMaxItersPerLaunch * c->n_blocks * 8);
     plan.add(&c->bad, 256);
+    plan.add(&c->sweep, 256);
     if (!dev_out) {
         plan.add(&c->rgb, HW * 12);
         plan.add(&c->hole, HW);
@@ -622,12 +624,13 @@ static lf_status deferred_check(lf_ctx *c) {
                                 "mu_T not finite or q_warm outside [0,1])", bad);
 }
 
-lf_status lf_em_iterate(lf_ctx *c, int32_t n_iters, double *objective) {
+static lf_status iterate(lf_ctx *c, int32_t n_iters, double *objective, unsigned long long *sweep) {
     g_last_error.clear();
     if (!c) return set_error(LF_EINVAL, "context is NULL");
     if (n_iters < 0) return set_error(LF_EINVAL, "n_iters=%d < 0", n_iters);
     if (!c->loaded) return set_error(LF_ESTATE, "no frame loaded");
     EmArgs a = make_em_args(&c->p, c->g, c->lambda);
+    a.sweep_count = sweep;
     a.feat = c->feat;
     a.rho = c->rho;
     a.omr = c->omr;
@@ -660,6 +663,21 @@ lf_status lf_em_iterate(lf_ctx *c, int32_t n_iters, double *objective) {
     }
     c->iters += n_iters;
     return LF_OK;
+}
+
+lf_status lf_em_iterate(lf_ctx *c, int32_t n_iters, double *objective) { return iterate(c, n_iters, objective, nullptr); }
+
+lf_status lf_em_sweep_count(lf_ctx *c, int32_t n_iters, uint64_t *level_steps) {
+    if (!c) return set_error(LF_EINVAL, "context is NULL");
+    if (!level_steps) return set_error(LF_EINVAL, "level_steps is NULL");
+    LF_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(c->sweep), 2, 0u, c->stream), "clear counter");
+    lf_status st = iterate(c, n_iters, nullptr, c->sweep);
+    if (st != LF_OK) return st;
+    unsigned long long v = 0;
+    LF_HIP(hipMemcpyAsync(&v, c->sweep, sizeof v, hipMemcpyDeviceToHost, c->stream), "copy counter");
+    LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    *level_steps = v;
+    return deferred_check(c);
 }
 
 lf_status lf_em_check(lf_ctx *c) {

@@ -182,6 +182,7 @@ struct EmArgs {
     float inv_step;       // 1 / d_step
     float c_t2;           // 2 sigma^2 ln 2
     float tau;            // first-iteration threshold (dynamic-only test)
+    unsigned long long *sweep_count;  // diagnostic, or null: level steps the sweeps take, summed over waves
     int perm[kMaxViews];  // kernel view order -> array view index (perm[0] = reference)
     int bi[kMaxViews];    // integer baselines, kernel order (integer-shift path)
     float b[kMaxViews];   // baselines, kernel order
@@ -797,9 +798,10 @@ constexpr int kSweepShared = 0, kSweepExhaustive = 1, kSweepLane = 2;
 // minimum and the reduction keeps the tie rule, so the result is the full
 // sweep's, bit for bit.
 // x_idle is a column inside every view's window (the tile's first), read by
-// lanes without a pixel.
+// lanes without a pixel.  Returns the number of level steps the wave's sweep
+// takes (uniform; diagnostics).
 template <int K, int ST, bool SYM>
-__device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win, const Window (&w)[K],
+__device__ __forceinline__ int shared_iteration(const typename Rec<ST>::T *win, const Window (&w)[K],
                                                  const EmArgs &a, int x, int x_idle, bool work, int jlo, int jhi,
                                                  int slo, int shi, float Pc, Lane<K> &s, bool with_obj) {
     using R = typename Rec<ST>::T;
@@ -842,6 +844,7 @@ __device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win,
     // LDS banks
     const int chunk = min(((nlev + cp - 1) / cp) | 1, nlev);
     const int cost = (anyb ? wl : 0) + (nu > 0 ? chunk + kShareCost : 0);
+    const int steps = cost >= nlev ? max(shi - slo + 1, 0) : (anyb ? wl : 0) + (nu > 0 ? chunk : 0);
 
     if (cost >= nlev) {
         // every lane sweeps its whole range
@@ -916,6 +919,7 @@ __device__ __forceinline__ void shared_iteration(const typename Rec<ST>::T *win,
         level0_index<K, false>(w, a, x, idx2);
         estep<K, ST, false>(win, w, a, x, idx2, rec_f<ST>(win[idx2[0]]), best_j, wt2, invW2, cw2, s, with_obj);
     }
+    return steps;
 }
 
 // Descriptor pair of storage ST as a pair of record storage RS (RS == ST,
@@ -1030,14 +1034,17 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
     search_range(a, work, s.mu, slo, shi);
 
     const int block_id = blockIdx.y * gridDim.x + blockIdx.x;
+    unsigned long long steps = 0;   // level steps of this wave's sweeps (diagnostics)
+    const bool any_work = __ballot(work) != 0;
     for (int it = 0; it < a.n_iters; ++it) {
         const bool with_obj = a.want_obj || it == a.n_iters - 1;
         if constexpr (SW == kSweepShared && !FRAC) {
-            shared_iteration<K, RS, SYM>(win, w, a, x, x0, work, jlo, jhi, slo, shi, Pc, s, with_obj);
+            steps += shared_iteration<K, RS, SYM>(win, w, a, x, x0, work, jlo, jhi, slo, shi, Pc, s, with_obj);
         } else {
             if (work)
                 em_iteration<K, RS, FRAC, SW == kSweepExhaustive, SYM>(win, w, a, x, jlo, jhi, slo, shi, Pc, s,
                                                                         with_obj);
+            steps += any_work ? max(shi - slo + 1, 0) : 0;
         }
         if (!with_obj) continue;
         // ---- FP64 block sum of the objective ----
@@ -1052,6 +1059,7 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
         }
         __syncthreads();
     }
+    if (a.sweep_count && (tid & 63) == 0) atomicAdd(a.sweep_count, steps);
     if (active && a.n_iters > 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) a.q[(size_t)a.perm[k] * HW + pix] = s.q[k];

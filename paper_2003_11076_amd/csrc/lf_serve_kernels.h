@@ -140,7 +140,7 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
     search_range(a, work, s.mu, slo, shi);
     for (int it = 0; it < a.n_iters; ++it) {
         if constexpr (KIND == kServeSharedSym || KIND == kServeShared) {
-            shared_iteration<K, ST, SYM>(win, w, a, x, x0, work, jlo, jhi, slo, shi, Pc, s, false);
+            (void)shared_iteration<K, ST, SYM>(win, w, a, x, x0, work, jlo, jhi, slo, shi, Pc, s, false);
         } else {
             if (work) em_iteration<K, ST, FRAC, false, false>(win, w, a, x, jlo, jhi, slo, shi, Pc, s, false);
         }

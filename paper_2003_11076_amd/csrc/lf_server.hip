@@ -162,6 +162,7 @@ struct lf_server {
     std::vector<SrvStream> streams;
     std::deque<SrvFrame *> pending;
     int inflight = 0;             // batches admitted and not yet finished
+    bool hold = false;            // admission held (lf_server_hold)
     int64_t use_clock = 0;
     std::mutex mu;
     std::condition_variable cv, cv_idle;
@@ -399,7 +400,7 @@ void worker_main(lf_server *s, int wi) {
                     b.push_back(f);
                 }
                 if (!b.empty()) break;
-            } else {
+            } else if (!s->hold) {
                 form_batch(s, b);
                 if (!b.empty()) break;
             }
@@ -626,9 +627,20 @@ lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, c
     return LF_OK;
 }
 
+lf_status lf_server_hold(lf_server *s, int32_t hold) {
+    if (!s) return set_error(LF_EINVAL, "server is NULL");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->hold = hold != 0;
+    }
+    s->cv.notify_all();
+    return LF_OK;
+}
+
 lf_status lf_server_drain(lf_server *s) {
     if (!s) return set_error(LF_EINVAL, "server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
+    s->hold = false;   // a held queue could never drain
     s->cv.notify_all();
     s->cv_idle.wait(lk, [&] { return s->pending.empty() && s->inflight == 0; });
     if (s->sticky != LF_OK) return set_error(s->sticky, "%s", s->sticky_msg.c_str());
