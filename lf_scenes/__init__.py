@@ -26,7 +26,7 @@ import numpy as np
 
 __all__ = [
     "Frame", "SceneSpec", "make_frame", "workload_spec", "WORKLOAD_NAMES", "WORKLOADS",
-    "serving_stream_spec", "rng_for",
+    "serving_stream_spec", "rng_for", "frame_arrays",
 ]
 
 # Largest |G| of a 3x3 Sobel response of L = R+G+B (4 * 765), and the scale
@@ -510,3 +510,10 @@ def serving_stream_spec(stream: int, frame: int, scale: float = 1.0) -> SceneSpe
                      dyn_disp=(int(0.4 * D), int(0.8 * D)), dyn_cover=(0.10, 0.45),
                      noise_sigma=2.0 / 255.0, sp_model="blurflip", n_T=max(20, H * W // 1536),
                      seed=40000 + 100 * stream, dyn_shift=2.0 * frame)
+
+
+def frame_arrays(spec: SceneSpec):
+    """(views, S_P, mu_T, beta) of make_frame(spec): the arrays a caller of
+    the library needs, small enough to hand back from a worker process."""
+    fr = make_frame(spec)
+    return fr.views, fr.S_P, fr.mu_T, float(fr.beta)

@@ -14,7 +14,10 @@ comparing element by element:
     |a1 - a0| < 1e-3, the decision taken in different precisions; enumerated
     hard labels: exact except where the two largest labeling log weights are
     within 1e-3);
-  * per-pixel objective: |diff| <= 1e-5 * max(|L|, 1) on pixels with matching d;
+  * per-pixel objective: |diff| <= 1e-5 * max(A, 1) on pixels with matching d,
+    A = |ln prior| + sum_k (max(|a1_k|, |a0_k|) + ln 2) the magnitude of its
+    addends (>= |L|; the FP32 rounding error scales with the addends, which
+    cancel in the sum);
   * variants (window, dynamic-only): d also exempt where mu_T puts a level
     within 1e-4 of the window's edge or half-way between two levels.
 """
@@ -60,6 +63,15 @@ class Case:
     mu_T: np.ndarray
     n_iters: int = 1
     flags: int = 0          # LF_PRIOR_WINDOW / LF_DYNAMIC_ONLY (the variants), passed to both sides
+
+    @classmethod
+    def from_arrays(cls, spec, views, S_P, mu_T, beta, storage=None, mode="soft", **over):
+        c = cls(spec.K, spec.H, spec.W, spec.ref, tuple(f32(b) for b in spec.baselines), f32(spec.d_min),
+                f32(spec.d_step), spec.D, f32(beta), float("nan"), f32(spec.gamma), f32(spec.sigma), f32(spec.tau),
+                storage or spec.storage, mode, views, S_P.astype(np.float32), mu_T.astype(np.float32), spec.n_iters)
+        for k, v in over.items():
+            setattr(c, k, v)
+        return c
 
     @classmethod
     def from_frame(cls, fr, storage=None, mode="soft", **over):
@@ -247,12 +259,52 @@ def compare_iteration(case, ref, ref_soft, q_gpu, d_gpu, L_gpu, rows=None, label
     else:
         qmax = float(qd[:, same].max()) if same.any() else 0.0
         assert qmax <= TOL_Q, f"{label}: q max-abs {qmax:.3g} > {TOL_Q}"
-    Ld = np.abs(L_gpu.astype(np.float64) - ref["L"]) / np.maximum(np.abs(ref["L"]), 1.0)
+    # the objective's FP32 rounding error grows with the magnitude of its
+    # addends (the log prior and each view's static and dynamic log weights),
+    # which cancel in the sum: relative to that magnitude (never below |L|)
+    if case.mode in ("soft", "hard") and "q_in" in ref:
+        scale = objective_scale(case, ref["f"], ref["rho"], ref["omr"], ref["q_in"], ref["d_idx"], rows)
+    else:
+        scale = np.abs(ref["L"])
+    Ld = np.abs(L_gpu.astype(np.float64) - ref["L"]) / np.maximum(scale, 1.0)
     Lmax = float(Ld[same].max()) if same.any() else 0.0
     assert Lmax <= TOL_L, f"{label}: objective rel diff {Lmax:.3g} > {TOL_L}"
     n = int(sel.sum())
     return {"pixels": n, "near_ties": int(tie.sum()), "d_mismatch_at_ties": int((sel & ~d_ok).sum()),
             "q_maxabs": float(qd[:, same].max()) if same.any() else 0.0, "L_maxrel": Lmax}
+
+
+def objective_scale(case, f, rho, omr, q_in, d_idx, rows):
+    """Per pixel, |ln prior(d)| + sum_k (max(|a1_k|, |a0_k|) + ln 2) at the
+    oracle's level d, with a1_k = ln rho_k + lambda - beta/K |f_k - m|^2
+    (m the M-step mean from the weights q_in) and a0_k = ln(1 - rho_k): the
+    magnitude of the objective's addends (infinite log weights are exact on
+    both sides and left out).  Never below |L|."""
+    y0, y1 = rows if rows is not None else (0, case.H)
+    K, W = case.K, case.W
+    lam = O.lam_of(case.oracle_params())
+    bp = case.beta / K
+    out = np.zeros((case.H, W))
+    xs = np.arange(W, dtype=np.float64)
+    two_s2 = 2.0 * float(case.sigma) ** 2
+    for y in range(y0, y1):
+        d = case.d_min + d_idx[y].astype(np.float64) * case.d_step
+        g = np.empty((K, W, 2))
+        for k in range(K):
+            for c in range(2):
+                g[k, :, c] = np.interp(np.clip(xs - case.baselines[k] * d, 0, W - 1), xs, f[k, y, :, c])
+        wt = q_in[:, y]
+        Q = wt.sum(axis=0)
+        wt = np.where(Q > 0, wt, 1.0)
+        m = (wt[..., None] * g).sum(axis=0) / wt.sum(axis=0)[:, None]
+        e = ((g - m[None]) ** 2).sum(axis=-1)
+        with np.errstate(divide="ignore"):
+            a1 = np.log(rho[:, y]) + lam - bp * e
+            a0 = np.log(omr[:, y])
+        fin = lambda a: np.where(np.isfinite(a), np.abs(a), 0.0)
+        prior = np.log(case.gamma + np.exp(-(d - case.mu_T[y].astype(np.float64)) ** 2 / two_s2))
+        out[y] = np.abs(prior) + (np.maximum(fin(a1), fin(a0)) + np.log(2.0)).sum(axis=0)
+    return out
 
 
 def enum_top_gap(case, f, rho, omr, d_idx, rows):
@@ -283,8 +335,12 @@ def enum_top_gap(case, f, rho, omr, d_idx, rows):
     return gap
 
 
-def teacher_forced(case: Case, n_iters: int, rows=None, device_inputs=True, check_refocus=True):
-    """Per-iteration parity of the GPU library against the oracle (see module doc)."""
+def teacher_forced(case: Case, n_iters: int, rows=None, device_inputs=True, check_refocus=True, q_warm=None,
+                   expect=None):
+    """Per-iteration parity of the GPU library against the oracle (see module doc).
+    q_warm: first weights (a warm start) instead of the threshold.  expect:
+    (rgb, d_idx, q) another GPU path produced for the same frame, which must
+    equal this chain's final state bit for bit on the whole frame."""
     op = case.oracle_params()
     y0, y1 = rows if rows is not None else (0, case.H)
     orows = (max(0, y0 - 1), min(case.H, y1 + 1))
@@ -292,22 +348,25 @@ def teacher_forced(case: Case, n_iters: int, rows=None, device_inputs=True, chec
     pr = O.ray_prior(op, case.S_P, case.mu_T, rows=(y0, y1))
     rho_o, q0_o = pr
     omr_o = pr.omr
-    run = DeviceRun(case, device_inputs=device_inputs)
+    run = DeviceRun(case, device_inputs=device_inputs, q_warm=q_warm)
     try:
         f_g, rho_g = run.intermediates()
         assert np.array_equal(f_g[:, y0:y1], f_o[:, y0:y1]), "descriptors differ"
         rdiff = np.abs(rho_g[:, y0:y1].astype(np.float64) - rho_o[:, y0:y1]).max()
         assert rdiff <= TOL_RHO, f"rho max-abs {rdiff:.3g}"
         q_prev, _, _ = run.state(with_d=False)
-        near_tau = np.abs(rho_o - case.tau) < 1e-6
-        bad = (q_prev[:, y0:y1] != q0_o[:, y0:y1]) & ~near_tau[:, y0:y1]
-        assert not bad.any(), "first weights differ off the threshold"
+        if q_warm is not None:
+            assert np.array_equal(q_prev, np.asarray(q_warm, np.float32)), "warm start not taken as given"
+        else:
+            near_tau = np.abs(rho_o - case.tau) < 1e-6
+            bad = (q_prev[:, y0:y1] != q0_o[:, y0:y1]) & ~near_tau[:, y0:y1]
+            assert not bad.any(), "first weights differ off the threshold"
         stats = []
         for t in range(n_iters):
             run.iterate(1)
             q_g, d_g, L_g = run.state()
             ref = O.em_iteration(op, f_o, rho_o, case.mu_T, q_prev.astype(np.float64), rows=(y0, y1), omr=omr_o)
-            ref.update(f=f_o, rho=rho_o, omr=omr_o)
+            ref.update(f=f_o, rho=rho_o, omr=omr_o, q_in=q_prev.astype(np.float64))
             ref_soft = ref
             if case.mode == "hard":
                 ref_soft = O.em_iteration(case.oracle_params(mode="soft"), f_o, rho_o, case.mu_T,
@@ -324,6 +383,42 @@ def teacher_forced(case: Case, n_iters: int, rows=None, device_inputs=True, chec
             rmax = float(rd[cmp].max()) if cmp.any() else 0.0
             assert rmax <= TOL_RGB, f"refocus max-abs {rmax:.3g}"
             stats.append({"refocus_maxabs": rmax})
+            if expect is not None:
+                for name, a, b in zip(("rgb", "d_idx", "q"), expect, (rgb_g, d_g, q_g)):
+                    assert np.array_equal(np.asarray(a), b), f"{name} differs from the other path's"
         return stats
     finally:
         run.close()
+
+
+# ---------------------------------------------------------------------------
+# Workload frames and row bands
+# ---------------------------------------------------------------------------
+
+_FRAMES = {}
+
+
+def workload_frame(name):
+    """The workload's seeded frame, generated once per test session."""
+    import lf_scenes as S
+    if name not in _FRAMES:
+        _FRAMES[name] = S.make_frame(S.workload_spec(name))
+    return _FRAMES[name]
+
+
+def row_bands(case, n=8):
+    """Four bands of n rows: the top edge, the bottom edge, the band whose
+    reference rays are most often dynamic by the threshold (through a moving
+    object), and the middle of the frame."""
+    H = case.H
+    n = min(n, H)
+    dyn = (case.S_P[case.ref] < case.tau).mean(axis=1)
+    run = np.convolve(dyn, np.ones(n), mode="valid")
+    yd = int(np.argmax(run))
+    ym = max(0, min(H - n, H // 2 - n // 2))
+    bands = [(0, n), (H - n, H), (yd, yd + n), (ym, ym + n)]
+    out = []
+    for b in bands:
+        if b not in out:
+            out.append(b)
+    return out

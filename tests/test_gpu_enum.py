@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import lf_scenes as S
-from lfcase import Case, DeviceRun, random_case, teacher_forced
+from lfcase import Case, DeviceRun, random_case, teacher_forced, workload_frame
 
 pytestmark = pytest.mark.gpu
 
@@ -48,7 +48,7 @@ def test_small_enumeration_teacher_forced(K, H, W, D, b, dmin, dstep, st, mode):
 
 
 def test_large_enumeration_sampled_rows():
-    case = Case.from_frame(S.make_frame(S.workload_spec("large")), storage="bf16", mode="enum_soft")
+    case = Case.from_frame(workload_frame("large"), storage="bf16", mode="enum_soft")
     _say("large 1920x1080 K=9 D=192 bf16 enum_soft teacher-forced x2, rows 536..539")
     teacher_forced(case, 2, rows=(536, 539))
 

@@ -10,7 +10,7 @@ import pytest
 
 import lf_scenes as S
 import oracle as O
-from lfcase import Case, DeviceRun, random_case, teacher_forced, near_tie
+from lfcase import Case, DeviceRun, random_case, teacher_forced, near_tie, row_bands, workload_frame
 
 pytestmark = pytest.mark.gpu
 
@@ -57,24 +57,36 @@ def test_small_cases_teacher_forced(K, H, W, D, b, dmin, dstep, st, mode):
 
 
 def test_plain_full_size_fp32():
-    fr = S.make_frame(S.workload_spec("plain"))
+    fr = workload_frame("plain")
     case = Case.from_frame(fr, storage="f32")
     _say("plain 640x480 K=5 D=64 fp32 soft teacher-forced x10 (full frame)")
     teacher_forced(case, 10)
 
 
 def test_precision_fp16_sampled_rows():
-    fr = S.make_frame(S.workload_spec("precision"))
+    fr = workload_frame("precision")
     case = Case.from_frame(fr, storage="f16")
-    _say("precision 1280x960 K=5 D=128 fp16 teacher-forced x10, rows 472..488")
-    teacher_forced(case, 10, rows=(472, 488))
+    for band in row_bands(case) + [(472, 488)]:
+        _say(f"precision 1280x960 K=5 D=128 fp16 teacher-forced x10, rows {band[0]}..{band[1]}")
+        teacher_forced(case, 10, rows=band)
 
 
 def test_large_bf16_sampled_rows():
-    fr = S.make_frame(S.workload_spec("large"))
+    fr = workload_frame("large")
     case = Case.from_frame(fr, storage="bf16")
-    _say("large 1920x1080 K=9 D=192 bf16 teacher-forced x12, rows 530..542")
-    teacher_forced(case, 12, rows=(530, 542))
+    for band in row_bands(case) + [(530, 542)]:
+        _say(f"large 1920x1080 K=9 D=192 bf16 teacher-forced x12, rows {band[0]}..{band[1]}")
+        teacher_forced(case, 12, rows=band)
+
+
+def test_large_fp32_sampled_rows():
+    """The large frames in FP32 storage, as the plain context the server's
+    BF16 streams are compared with runs them."""
+    fr = workload_frame("large")
+    case = Case.from_frame(fr, storage="f32")
+    for band in row_bands(case)[:2]:
+        _say(f"large 1920x1080 K=9 D=192 fp32 teacher-forced x12, rows {band[0]}..{band[1]}")
+        teacher_forced(case, 12, rows=band)
 
 
 def test_resume_is_bitwise(small_frame):
@@ -291,7 +303,7 @@ def test_pruned_sweep_matches_exhaustive_on_scenes(workload):
     the levels that can still win and the workgroups sweep those pixels in
     narrow windows: every iteration's levels, weights and objective are the
     exhaustive sweep's, bit for bit."""
-    fr = S.make_frame(S.workload_spec(workload))
+    fr = workload_frame(workload)
     case = Case.from_frame(fr)
     _say(f"{workload} {case.W}x{case.H} K={case.K} D={case.D} {case.storage}: pruned fast vs exhaustive, "
          f"{case.n_iters} iterations")
@@ -320,7 +332,7 @@ def test_pruned_sweep_edges_match_exhaustive(small_frame, label, mu_shift, sigma
 @pytest.mark.parametrize("variant", ["dynamic-only", "window"])
 def test_pruned_sweep_variants_match_exhaustive_on_scene(variant):
     import paper_2003_11076_amd as LF
-    fr = S.make_frame(S.workload_spec("plain"))
+    fr = workload_frame("plain")
     case = Case.from_frame(fr)
     flag = LF.LF_DYNAMIC_ONLY if variant == "dynamic-only" else LF.LF_PRIOR_WINDOW
     _say(f"plain {variant}: pruned fast vs exhaustive, 10 iterations")
@@ -330,7 +342,7 @@ def test_pruned_sweep_variants_match_exhaustive_on_scene(variant):
 def test_precision_fp16_error_against_unquantised_oracle():
     """Reported, not a parity bound: FP16 storage end to end (10 free-running
     iterations) against the FP64 oracle on unrounded inputs, rows 472..488."""
-    fr = S.make_frame(S.workload_spec("precision"))
+    fr = workload_frame("precision")
     case = Case.from_frame(fr, storage="f16")
     _say("precision fp16 end to end vs the unquantised FP64 oracle, rows 472..488")
     run = DeviceRun(case)
