@@ -4,6 +4,7 @@
 #include "lf_frame_kernels.h"
 #include "lf_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -134,6 +135,20 @@ size_t em_window_pairs(const lf_params *p, const Geometry &g, int tile) {
         }
     }
     return tot;
+}
+
+// Positions of the widest single view window of a tile of `tile` pixels.
+size_t em_window_widest(const lf_params *p, const Geometry &g, int tile) {
+    size_t widest = 0;
+    for (int k = 0; k < p->K; ++k) {
+        lf_params one = *p;
+        one.K = 1;
+        one.baselines[0] = p->baselines[k];
+        Geometry g1 = g;
+        g1.bi[0] = g.bi[k];
+        widest = std::max(widest, em_window_pairs(&one, g1, tile));
+    }
+    return widest;
 }
 
 size_t pair_bytes(int storage) { return storage == LF_F32 ? 8 : 4; }

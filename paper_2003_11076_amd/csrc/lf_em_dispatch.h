@@ -11,15 +11,15 @@ namespace lfem {
 template <int K, int ST, int SW>
 static EmKernel pick_em_fast(bool sym, bool enumerate) {
     if constexpr (SW == kSweepShared) {
-        // The shared sweep keeps more state per lane: four waves per SIMD up
-        // to six views (a few spills outside the sweep), the compiler's own
-        // register count above that (measured: both faster than five and
-        // three waves with the spills those caps force), except for the
-        // enumeration E-step of seven to nine views, whose 2^K loop gains
-        // more from three waves than the sweep loses
+        // The shared sweep keeps more state per lane: three waves per SIMD
+        // (168 VGPRs, no spills) up to six views, measured faster than four
+        // waves with the spills a 128-VGPR cap forces (plain workload 12 %,
+        // precision 5 %); the compiler's own register count above that,
+        // except for the enumeration E-step of seven to nine views, whose
+        // 2^K loop gains more from three waves than the sweep loses
         if constexpr (K <= 6) {
-            return sym ? (EmKernel)lf_em_kernel_w4<K, ST, false, SW, true>
-                       : (EmKernel)lf_em_kernel_w4<K, ST, false, SW, false>;
+            return sym ? (EmKernel)lf_em_kernel_w3<K, ST, false, SW, true>
+                       : (EmKernel)lf_em_kernel_w3<K, ST, false, SW, false>;
         } else if constexpr (K <= 9) {
             if (enumerate)
                 return sym ? (EmKernel)lf_em_kernel_w3<K, ST, false, SW, true>

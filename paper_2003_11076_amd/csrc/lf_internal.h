@@ -79,6 +79,7 @@ lf_status validate_host_values(const lf_params *p, const float *S_P, const float
 float derived_lambda(const lf_params *p);
 Geometry make_geometry(const lf_params *p);
 size_t em_window_pairs(const lf_params *p, const Geometry &g, int tile);
+size_t em_window_widest(const lf_params *p, const Geometry &g, int tile);
 size_t pair_bytes(int storage);
 size_t rec_bytes(int storage);
 int choose_tile(const lf_params *p, const Geometry &g, size_t lds_limit, size_t lds_per_cu, int vgprs,

@@ -4,7 +4,7 @@
 // frames of one kernel key: the same storage format, view count and sweep
 // kind, any size and level count.  Block b finds its frame through the
 // batch's tile prefix table.  Each block runs the whole method for one row
-// tile of kServeTile pixels of one frame, with nothing written to HBM in
+// tile of serve_tile_width(K) pixels of one frame, with nothing written to HBM in
 // between:
 //   descriptors of the tile's windows, from three staged rows of R+G+B
 //   (Sec. III-C) -> ray prior of each pixel's rays (Sec. III-B) -> n EM
@@ -18,7 +18,11 @@
 
 namespace lfem {
 
-constexpr int kServeTile = 128;
+// Row-tile width (the block size) per view count: 128 pixels up to six
+// views, 256 above, where the wider disparity halo of a 128-pixel tile's
+// windows would hold the LDS of a CU to fewer waves than the registers allow.
+__host__ __device__ constexpr int serve_tile_width(int K) { return K <= 6 ? 128 : 256; }
+constexpr int kServeTileMax = 256;
 constexpr int kServeMaxViews = 9;
 
 // Sweep kinds of the serve kernel instances (one launch per kind):
@@ -48,7 +52,8 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
     const EmArgs &a = job.em;
     const int tid = threadIdx.x;
     const int y = tile / job.tiles_x;
-    const int x0 = (tile - y * job.tiles_x) * kServeTile;
+    constexpr int TILE = serve_tile_width(K);
+    const int x0 = (tile - y * job.tiles_x) * TILE;
     const int x = x0 + tid;
     const int W = a.W, H = a.H;
     const bool active = x < W;
@@ -59,44 +64,36 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
     int total;
     view_windows<K, FRAC>(a, x0, w, total);
     R *win = reinterpret_cast<R *>(lds);
+    // intensity rows of one view at a time, after the records
     int16_t *lsum = reinterpret_cast<int16_t *>(lds + (size_t)total * sizeof(R));
 
-    // 1) rows y-1, y, y+1 of R+G+B over each window's columns (+1 border)
-    int c0[K], nc[K], loff[K];
-    int lo = 0;
+    // descriptor records of every window position (replicated border), view
+    // by view: rows y-1, y, y+1 of R+G+B over the window's columns (+1
+    // border), then the 3x3 Sobel responses
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int ulo = clampi(w[k].umin, 0, W - 1), uhi = clampi(w[k].umin + w[k].len - 1, 0, W - 1);
-        c0[k] = max(ulo - 1, 0);
-        nc[k] = min(uhi + 1, W - 1) - c0[k] + 1;
-        loff[k] = lo;
-        lo += 3 * nc[k];
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
+        const int c0 = max(ulo - 1, 0);
+        const int nc = min(uhi + 1, W - 1) - c0 + 1;
         const uint8_t *v = job.views + (size_t)a.perm[k] * HW * 3;
-        for (int i = tid; i < 3 * nc[k]; i += kServeTile) {
-            const int r = i / nc[k], c = c0[k] + (i - r * nc[k]);
+        for (int i = tid; i < 3 * nc; i += TILE) {
+            const int r = i / nc, c = c0 + (i - r * nc);
             const int yy = clampi(y + r - 1, 0, H - 1);
             const uint8_t *px = v + ((size_t)yy * W + c) * 3;
-            lsum[loff[k] + i] = (int16_t)((int)px[0] + (int)px[1] + (int)px[2]);
+            lsum[i] = (int16_t)((int)px[0] + (int)px[1] + (int)px[2]);
         }
-    }
-    __syncthreads();
-    // 2) descriptor records of every window position (replicated border)
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int16_t *L0 = lsum + loff[k], *L1 = L0 + nc[k], *L2 = L1 + nc[k];
-        for (int p = tid; p < w[k].len; p += kServeTile) {
+        __syncthreads();
+        const int16_t *L0 = lsum, *L1 = L0 + nc, *L2 = L1 + nc;
+        for (int p = tid; p < w[k].len; p += TILE) {
             const int uc = clampi(w[k].umin + p, 0, W - 1);
-            const int cl = max(uc - 1, 0) - c0[k], cm = uc - c0[k], cr = min(uc + 1, W - 1) - c0[k];
+            const int cl = max(uc - 1, 0) - c0, cm = uc - c0, cr = min(uc + 1, W - 1) - c0;
             const int gx = (L0[cr] - L0[cl]) + 2 * (L1[cr] - L1[cl]) + (L2[cr] - L2[cl]);
             const int gy = (L2[cl] - L0[cl]) + 2 * (L2[cm] - L0[cm]) + (L2[cr] - L0[cr]);
             const float sc = 1.0f / 4096.0f;
             win[win_index(w[k], p)] = make_rec<ST>(make_pair<ST>((float)gx * sc, (float)gy * sc));
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     // 3) ray prior and first weights of each of the pixel's rays
     Lane<K> s;
@@ -215,25 +212,25 @@ __device__ __forceinline__ void serve_entry(const ServeJob *__restrict__ jobs, i
 }
 
 // Register budgets as the plain context's instances: the shared sweep at
-// four waves per SIMD up to six views and the compiler's own count above;
+// three waves per SIMD up to six views and the compiler's own count above;
 // the per-lane sweep at five (up to five FP16/BF16 views), four (up to six)
 // or three waves (up to nine).
 template <int K, int ST, int KIND>
-__global__ __launch_bounds__(kServeTile) void lf_serve_kernel(const ServeJob *__restrict__ jobs, int n_jobs) {
+__global__ __launch_bounds__(kServeTileMax) void lf_serve_kernel(const ServeJob *__restrict__ jobs, int n_jobs) {
     serve_entry<K, ST, KIND>(jobs, n_jobs);
 }
 template <int K, int ST, int KIND>
-__global__ __launch_bounds__(kServeTile) __attribute__((amdgpu_waves_per_eu(5, 8))) void lf_serve_kernel_w5(
+__global__ __launch_bounds__(kServeTileMax) __attribute__((amdgpu_waves_per_eu(5, 8))) void lf_serve_kernel_w5(
     const ServeJob *__restrict__ jobs, int n_jobs) {
     serve_entry<K, ST, KIND>(jobs, n_jobs);
 }
 template <int K, int ST, int KIND>
-__global__ __launch_bounds__(kServeTile) __attribute__((amdgpu_waves_per_eu(4, 8))) void lf_serve_kernel_w4(
+__global__ __launch_bounds__(kServeTileMax) __attribute__((amdgpu_waves_per_eu(4, 8))) void lf_serve_kernel_w4(
     const ServeJob *__restrict__ jobs, int n_jobs) {
     serve_entry<K, ST, KIND>(jobs, n_jobs);
 }
 template <int K, int ST, int KIND>
-__global__ __launch_bounds__(kServeTile) __attribute__((amdgpu_waves_per_eu(3, 8))) void lf_serve_kernel_w3(
+__global__ __launch_bounds__(kServeTileMax) __attribute__((amdgpu_waves_per_eu(3, 8))) void lf_serve_kernel_w3(
     const ServeJob *__restrict__ jobs, int n_jobs) {
     serve_entry<K, ST, KIND>(jobs, n_jobs);
 }
@@ -243,7 +240,7 @@ using ServeKernel = void (*)(const ServeJob *, int);
 template <int K, int ST, int KIND>
 ServeKernel serve_instance() {
     if constexpr (KIND == kServeSharedSym || KIND == kServeShared) {
-        if constexpr (K <= 6) return lf_serve_kernel_w4<K, ST, KIND>;
+        if constexpr (K <= 6) return lf_serve_kernel_w3<K, ST, KIND>;
         else return lf_serve_kernel<K, ST, KIND>;
     } else {
         if constexpr (K <= 5 && ST != 0) return lf_serve_kernel_w5<K, ST, KIND>;

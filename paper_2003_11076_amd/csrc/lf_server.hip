@@ -179,9 +179,13 @@ struct lf_server {
 
 namespace {
 
+// LDS of a tile: the descriptor records of every view's window, then three
+// int16 rows of intensity sums of one window at a time (+1 column of border
+// on each side).
 size_t frame_lds(const lf_params &p, const Geometry &g) {
-    const size_t pairs = em_window_pairs(&p, g, kServeTile);
-    return pairs * rec_bytes(p.storage) + 2 * 3 * (pairs + 2 * (size_t)p.K) + 64;
+    const size_t pairs = em_window_pairs(&p, g, serve_tile_width(p.K));
+    const size_t widest = em_window_widest(&p, g, serve_tile_width(p.K));
+    return pairs * rec_bytes(p.storage) + 2 * 3 * (widest + 2) + 64;
 }
 
 int frame_kind(const lf_params &p, const Geometry &g) {
@@ -273,7 +277,7 @@ bool run_batch(lf_server *s, SrvWorker &wk, std::vector<SrvFrame *> &b, std::str
         ServeJob &J = hj[i];
         std::memset(&J, 0, sizeof J);
         J.em = make_em_args(&p, f->g, f->lambda);
-        J.em.tile = kServeTile;
+        J.em.tile = serve_tile_width(p.K);
         J.em.n_iters = s->n_iters;
         J.views = f->dev_in ? f->views : reinterpret_cast<const uint8_t *>(d + f->o_views);
         J.S_P = f->dev_in ? f->S_P : reinterpret_cast<const float *>(d + f->o_sp);
@@ -308,7 +312,7 @@ bool run_batch(lf_server *s, SrvWorker &wk, std::vector<SrvFrame *> &b, std::str
             err = "no kernel instance for the frame";
             return false;
         }
-        hipLaunchKernelGGL(k, dim3(tiles), dim3(kServeTile), lds, st, dj, (int)nj);
+        hipLaunchKernelGGL(k, dim3(tiles), dim3(serve_tile_width(b[0]->p.K)), lds, st, dj, (int)nj);
         e = hipGetLastError();
     }
     for (size_t i = 0; i < nj && e == hipSuccess; ++i) {
@@ -545,7 +549,7 @@ lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, c
     f->q_out = q_out;
     f->done = done;
     f->user = user;
-    f->tiles_x = (p->W + kServeTile - 1) / kServeTile;
+    f->tiles_x = (p->W + serve_tile_width(p->K) - 1) / serve_tile_width(p->K);
     f->n_tiles = f->tiles_x * p->H;
     f->lds = frame_lds(*p, f->g);
     if (f->lds > s->lds_limit) {
