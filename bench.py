@@ -783,6 +783,8 @@ def main():
         "latency_frames": m["latency_frames"],
         "frames_per_s": m["frames_per_s"],
         "em_ms_timed_region": m["em_ms_timed_region"],
+        "em_busy_ms_per_step": m["em_busy_ms_per_step"],
+        "em_ms_alone": m["em_ms_alone"],
         "roofline": m["roofline"],
     }
     if not args.no_forms:
