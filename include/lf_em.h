@@ -414,7 +414,9 @@ lf_status lf_server_create(lf_server **out, size_t hbm_budget_bytes, int32_t max
  *            the device and a frame with invalid values completes with
  *            LF_EINVAL), LF_OUTPUTS_ON_DEVICE (rgb_out, d_out, q_out are
  *            device memory, written by the kernel), LF_PRIOR_WINDOW,
- *            LF_DYNAMIC_ONLY.
+ *            LF_DYNAMIC_ONLY.  The server's HIP streams do not wait for the
+ *            caller's: device inputs must be complete, and device outputs
+ *            free of pending work of the caller, when the call is made.
  *   views, S_P, mu_T : inputs as lf_em_init; host inputs are checked and
  *            copied before return.
  *   rgb_out : float [H][W][3] (required); d_out int32 [H][W] (nullable);

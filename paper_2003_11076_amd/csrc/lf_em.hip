@@ -153,8 +153,9 @@ size_t em_window_widest(const lf_params *p, const Geometry &g, int tile) {
 
 size_t pair_bytes(int storage) { return storage == LF_F32 ? 8 : 4; }
 
-// LDS record of one staged position: the pair plus |f|^2 (FP32 padded to 16 B).
-size_t rec_bytes(int storage) { return storage == LF_F32 ? 16 : 8; }
+// LDS record of one staged position in the EM kernel: the pair plus |f|^2,
+// 8 bytes for every storage format (FP32 descriptors as binary16 or int16).
+size_t rec_bytes(int storage) { (void)storage; return 8; }
 
 // ---------------------------------------------------------------------------
 // Kernel dispatch over (K, storage, integer/fractional shifts, sweep kind).
@@ -212,8 +213,34 @@ hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *m
     return hipGetLastError();
 }
 
-// LDS a dynamic-only launch adds after the windows: 256 lane slots and 4 counts
-static constexpr size_t kSlotsBytes = 260 * 4;
+// Dynamic-only work list: items of up to 64 dynamic reference pixels of a
+// row within `span` columns (the widest of 256, 192, 128, 64 whose view
+// windows fit a block's LDS), one wave each.
+DynPlan dyn_plan(const lf_params *p, const Geometry &g, size_t lds_limit) {
+    DynPlan d{};
+    if (!(p->flags & LF_DYNAMIC_ONLY)) return d;
+    for (int w = 256; w >= 64; w -= 64) {
+        d.span = w;
+        d.lds = em_window_pairs(p, g, w) * rec_bytes(p->storage);
+        if (d.lds <= lds_limit) break;
+    }
+    d.per_row = p->W / 64 + p->W / d.span + 1;
+    d.max_items = p->H * d.per_row;
+    return d;
+}
+
+size_t dyn_rows_ints(const lf_params *p, const DynPlan &d) { return (size_t)p->H * (d.per_row + 1); }
+
+hipError_t launch_dyn_list(const lf_params *p, const EmArgs &a, const DynPlan &d, int *rows, int2 *items,
+                           int *n_items, hipStream_t s) {
+    int *counts = rows, *starts = rows + p->H;
+    hipLaunchKernelGGL(lf_dyn_rows_kernel, dim3(p->H), dim3(64), 0, s, a, d.per_row, counts, starts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lf_dyn_items_kernel, dim3(1), dim3(256), 0, s, counts, starts, p->H, d.per_row, items,
+                       n_items);
+    return hipGetLastError();
+}
 
 
 EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
@@ -271,14 +298,19 @@ EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
     return a;
 }
 
-hipError_t launch_em(const lf_params *p, const Geometry &g, EmArgs a, int tile, size_t lds, hipStream_t s) {
+// Row tiles (grid (ceil(W/tile), H)), or with a dynamic-only work list one
+// wave per item (grid d.max_items; blocks past the list's length exit).
+hipError_t launch_em(const lf_params *p, const Geometry &g, EmArgs a, int tile, size_t lds, hipStream_t s,
+                     const DynPlan *d) {
     EmKernel kern = pick_em(p, g);
     a.tile = tile;
-    if (a.dyn_only) {
-        a.lds_slots = (int)((lds + 15) / 16 * 16);
-        lds = (size_t)a.lds_slots + kSlotsBytes;
-    }
     dim3 block(tile), grid((p->W + tile - 1) / tile, p->H);
+    if (a.items) {
+        a.seg_w = d->span;
+        block = dim3(64);
+        grid = dim3(d->max_items);
+        lds = d->lds;
+    }
     a.n_blocks = grid.x * grid.y;
     hipLaunchKernelGGL(kern, grid, block, lds, s, a);
     return hipGetLastError();
@@ -363,8 +395,7 @@ int choose_tile(const lf_params *p, const Geometry &g, size_t lds_limit, size_t 
     *lds_out = em_window_pairs(p, g, 64) * rec_bytes(p->storage);
     for (int tile = 64; tile <= 256; tile += 64) {
         if (tile > 64 && tile - 64 >= p->W) break;   // wider than the frame
-        const size_t lds = em_window_pairs(p, g, tile) * rec_bytes(p->storage) + 64 +
-                           ((p->flags & LF_DYNAMIC_ONLY) ? kSlotsBytes + 16 : 0);
+        const size_t lds = em_window_pairs(p, g, tile) * rec_bytes(p->storage) + 64;
         if (lds > lds_limit) continue;
         const int wb = tile / 64;
         const int blocks_lds = (int)(lds_per_cu / lds);
@@ -444,6 +475,10 @@ struct lf_ctx {
     double *obj;
     uint32_t *bad;
     unsigned long long *sweep;  // level-step counter of lf_em_sweep_count
+    DynPlan dyn;            // dynamic-only work list (span 0: none)
+    int *dyn_rows;          // [H] items per row, then [H][per_row] their first columns
+    int2 *dyn_items;        // [max_items] (row, first column)
+    int *dyn_n;             // number of items
     double *h_obj;          // pinned
     uint32_t *h_bad;        // pinned
     bool check_pending;     // deferred value check of device inputs not yet read
@@ -463,6 +498,12 @@ static lf_status ctx_alloc(lf_ctx *c) {
     lf_status st0 = em_launch_shape(&p, c->g, c->device, &c->tile, &c->lds);
     if (st0 != LF_OK) return st0;
     c->n_blocks = ((p.W + c->tile - 1) / c->tile) * p.H;
+    {
+        int v = 0;
+        LF_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device), "device attribute");
+        c->dyn = dyn_plan(&p, c->g, (size_t)v);
+        if (c->dyn.span) c->n_blocks = c->dyn.max_items;
+    }
     ArenaPlan plan;
     if (!dev_in) {
         plan.add(&c->views_own, KHW * 3);
@@ -479,6 +520,11 @@ static lf_status ctx_alloc(lf_ctx *c) {
     plan.add(&c->obj, (size_t)kMaxItersPerLaunch * c->n_blocks * 8);
     plan.add(&c->bad, 256);
     plan.add(&c->sweep, 256);
+    if (c->dyn.span) {
+        plan.add(&c->dyn_rows, dyn_rows_ints(&p, c->dyn) * 4);
+        plan.add(&c->dyn_items, (size_t)c->dyn.max_items * 8);
+        plan.add(&c->dyn_n, 256);
+    }
     if (!dev_out) {
         plan.add(&c->rgb, HW * 12);
         plan.add(&c->hole, HW);
@@ -521,6 +567,16 @@ static lf_status ctx_load(lf_ctx *c, const uint8_t *views, const float *S_P, con
     LF_HIP(launch_descriptors(&p, c->views, c->feat, c->stream), "descriptor launch");
     LF_HIP(launch_ray_prior(&p, sp, mu, qw, c->rho, c->omr, c->q, c->bad, dev_in ? 1 : 0, c->stream),
            "ray prior launch");
+    if (c->dyn.span) {
+        EmArgs da = make_em_args(&p, c->g, c->lambda);
+        da.rho = c->rho;
+        da.mu_T = mu;
+        da.d_idx = c->d_idx;
+        da.lpix = c->lpix;
+        da.seg_w = c->dyn.span;
+        LF_HIP(launch_dyn_list(&p, da, c->dyn, c->dyn_rows, c->dyn_items, c->dyn_n, c->stream),
+               "dynamic-only work list");
+    }
     if (dev_in) {
         LF_HIP(hipMemcpyAsync(c->h_bad, c->bad, 4, hipMemcpyDeviceToHost, c->stream), "copy counter");
         if (p.flags & LF_DEFERRED_CHECK) {
@@ -654,13 +710,17 @@ static lf_status iterate(lf_ctx *c, int32_t n_iters, double *objective, unsigned
     a.d_idx = c->d_idx;
     a.lpix = c->lpix;
     a.obj = c->obj;
+    if (c->dyn.span) {
+        a.items = c->dyn_items;
+        a.n_items = c->dyn_n;
+    }
     int done = 0;
     while (done < n_iters) {
         const int n = std::min(kMaxItersPerLaunch, n_iters - done);
         a.n_iters = n;
         a.seed_from_d = (c->iters + done) > 0;   // start the sweep at the last level
         a.want_obj = objective != nullptr;      // else only the last iteration's (kept as L_pix)
-        LF_HIP(launch_em(&c->p, c->g, a, c->tile, c->lds, c->stream), "EM launch");
+        LF_HIP(launch_em(&c->p, c->g, a, c->tile, c->lds, c->stream, &c->dyn), "EM launch");
         if (objective) {
             LF_HIP(hipMemcpyAsync(c->h_obj, c->obj, (size_t)n * c->n_blocks * 8, hipMemcpyDeviceToHost, c->stream),
                    "copy objective");

@@ -177,7 +177,9 @@ struct EmArgs {
     float margin_c;       // absolute slack of the bound
     float win_half;       // > 0: the M-step searches only |d - mu| <= win_half
     int dyn_only;         // 1: only pixels with rho_ref < tau are reconstructed
-    int lds_slots;        // dynamic-only: byte offset of 260 ints of LDS after the windows
+    const int2 *items;    // dynamic-only work list: (row, first column), or null for row tiles
+    const int *n_items;   // its length (device)
+    int seg_w;            // dynamic-only: columns an item's pixels may spread over (a multiple of 64, <= 256)
     float d_absmax;       // max |d_j| over the levels
     float inv_step;       // 1 / d_step
     float c_t2;           // 2 sigma^2 ln 2
@@ -189,10 +191,13 @@ struct EmArgs {
 };
 
 // LDS record: descriptor pair at storage precision plus |f|^2 in FP32.
+// Record format 3 holds FP32 descriptors exactly in 8 bytes: every descriptor
+// is an integer Sobel response (|G| <= 3060) times 2^-12, kept as int16 G.
 template <int ST> struct Rec;
 template <> struct Rec<0> { using T = float4; };  // (Gx, Gy, |f|^2, unused)
 template <> struct Rec<1> { using T = float2; };  // (half2 bits, |f|^2)
 template <> struct Rec<2> { using T = float2; };  // (2 x bf16 bits, |f|^2)
+template <> struct Rec<3> { using T = float2; };  // (2 x int16 G bits, |f|^2), f = G * 2^-12
 
 template <int ST>
 __device__ __forceinline__ typename Rec<ST>::T make_rec(typename Pair<ST>::T v) {
@@ -206,7 +211,14 @@ __device__ __forceinline__ typename Rec<ST>::T make_rec(typename Pair<ST>::T v) 
 template <int ST>
 __device__ __forceinline__ float2 rec_f(const typename Rec<ST>::T &r) {
     if constexpr (ST == 0) return make_float2(r.x, r.y);
-    else {
+    else if constexpr (ST == 3) {
+        // G * 2^-12 by an exponent shift, not a product: the compiler fuses
+        // products with neighbouring additions, and the arithmetic after the
+        // fetch must have the same shape (and bits) as with the other formats
+        const uint32_t u = __float_as_uint(r.x);
+        return make_float2(__builtin_amdgcn_ldexpf((float)(int16_t)(u & 0xffffu), -12),
+                           __builtin_amdgcn_ldexpf((float)(int16_t)(u >> 16), -12));
+    } else {
         const uint32_t u = __float_as_uint(r.x);
         if constexpr (ST == 1) return widen(*reinterpret_cast<const __half2 *>(&u));
         else return widen(u);
@@ -226,7 +238,7 @@ struct Window {
 };
 
 template <int K, bool FRAC>
-__device__ __forceinline__ void view_windows(const EmArgs &a, int x0, Window (&w)[K], int &total) {
+__device__ __forceinline__ void view_windows(const EmArgs &a, int x0, int tw, Window (&w)[K], int &total) {
     int off = 0;
     const float d_max = a.d_min + (float)(a.D - 1) * a.d_step;
     const int dmax_i = a.dmin_i + (a.D - 1) * a.dstep_i;
@@ -236,11 +248,11 @@ __device__ __forceinline__ void view_windows(const EmArgs &a, int x0, Window (&w
         if (FRAC) {
             const float s0 = a.b[k] * a.d_min, s1 = a.b[k] * d_max;
             umin = (int)floorf((float)x0 - fmaxf(s0, s1)) - 2;
-            umax = (int)floorf((float)(x0 + a.tile - 1) - fminf(s0, s1)) + 3;
+            umax = (int)floorf((float)(x0 + tw - 1) - fminf(s0, s1)) + 3;
         } else {
             const int s0 = a.bi[k] * a.dmin_i, s1 = a.bi[k] * dmax_i;
             umin = x0 - max(s0, s1);
-            umax = x0 + a.tile - 1 - min(s0, s1);
+            umax = x0 + tw - 1 - min(s0, s1);
         }
         w[k].umin = umin;
         w[k].off = off;
@@ -935,21 +947,34 @@ __device__ __forceinline__ typename Pair<RS>::T to_record_pair(typename Pair<ST>
 
 __device__ __forceinline__ bool exact_in_half(float v) { return __half2float(__float2half_rn(v)) == v; }
 
+// LDS record of a descriptor pair of storage ST in record format RS (RS ==
+// ST; FP32 values exact in binary16 as RS = 1; any FP32 values as RS = 3).
+template <int RS, int ST>
+__device__ __forceinline__ typename Rec<RS>::T stage_rec(typename Pair<ST>::T v) {
+    if constexpr (RS == 3) {
+        const float2 f = widen(v);
+        const int gx = (int)(f.x * 4096.0f), gy = (int)(f.y * 4096.0f);   // exact: |G| <= 3060
+        const uint32_t bits = ((uint32_t)gx & 0xffffu) | ((uint32_t)gy << 16);
+        return make_float2(__uint_as_float(bits), fmaf(f.x, f.x, f.y * f.y));
+    } else {
+        return make_rec<RS>(to_record_pair<RS, ST>(v));
+    }
+}
+
 // The kernel body: descriptors of storage ST staged as records of storage RS.
 template <int K, int ST, int RS, bool FRAC, int SW, bool SYM>
-__device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw, double *red) {
+__device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw, double *red, int y, int x0, int tw,
+                                        int xc, int block_id) {
     using R = typename Rec<RS>::T;
     using P = typename Pair<ST>::T;
     R *win = reinterpret_cast<R *>(lds_raw);
 
-    const int y = blockIdx.y;
-    const int x0 = blockIdx.x * a.tile;
     const int tid = threadIdx.x;
     const size_t HW = (size_t)a.H * a.W;
 
     Window w[K];
     int total;
-    view_windows<K, FRAC>(a, x0, w, total);
+    view_windows<K, FRAC>(a, x0, tw, w, total);
 
     // Stage the windows (replicated border outside the image) with |f|^2.
     const P *feat = reinterpret_cast<const P *>(a.feat);
@@ -957,47 +982,11 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
     for (int k = 0; k < K; ++k) {
         const P *row = feat + ((size_t)a.perm[k] * a.H + y) * a.W;
         for (int p = tid; p < w[k].len; p += blockDim.x)
-            win[win_index(w[k], p)] = make_rec<RS>(to_record_pair<RS, ST>(row[clampi(w[k].umin + p, 0, a.W - 1)]));
+            win[win_index(w[k], p)] = stage_rec<RS, ST>(row[clampi(w[k].umin + p, 0, a.W - 1)]);
     }
-
-    // Column of the tile this lane works on: its own, or with dynamic-only
-    // the tile's dynamic reference pixels, packed into the first lanes when
-    // that frees at least half of the busy waves (waves left without work
-    // skip the iterations).
-    int xc = tid;
-    if (a.dyn_only) {
-        const int xo = x0 + tid;
-        bool mine = false;
-        if (xo < a.W) {
-            const size_t po = (size_t)y * a.W + xo;
-            mine = a.rho[(size_t)a.perm[0] * HW + po] < a.tau;
-            if (!mine && a.n_iters > 0) {   // static reference ray: not reconstructed
-                a.d_idx[po] = nearest_level(a, a.mu_T[po]);
-                a.lpix[po] = 0.0f;
-            }
-        }
-        int *slots = reinterpret_cast<int *>(lds_raw + a.lds_slots);
-        int *counts = slots + 256;
-        const unsigned long long m = __ballot(mine);
-        const int lane = tid & 63, wv = tid >> 6;
-        if (lane == 0) counts[wv] = __popcll(m);
-        __syncthreads();
-        int base = 0, n = 0;
-        for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) {
-            if (i < wv) base += counts[i];
-            n += counts[i];
-        }
-        // pack only when it at least halves the busy waves: packed lanes read
-        // scattered columns of the windows, which costs LDS bank conflicts
-        int busy = 0;
-        for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) busy += counts[i] > 0;
-        const bool pack = 2 * ((n + 63) / 64) <= busy;
-        if (pack && mine) slots[base + __popcll(m & ((1ull << lane) - 1ull))] = tid;
-        __syncthreads();
-        xc = pack ? (tid < n ? slots[tid] : -1) : (mine ? tid : -1);
-    } else {
-        __syncthreads();
-    }
+    __syncthreads();
+    // the lane's pixel x0 + xc (xc < 0: none); with dynamic-only every
+    // pixel of the work list is reconstructed
     const int x = x0 + xc;
     const bool active = xc >= 0 && x < a.W;
     const size_t pix = (size_t)y * a.W + (active ? x : 0);
@@ -1033,7 +1022,6 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
     prior_window(a, work, s.mu, jlo, jhi);
     search_range(a, work, s.mu, slo, shi);
 
-    const int block_id = blockIdx.y * gridDim.x + blockIdx.x;
     unsigned long long steps = 0;   // level steps of this wave's sweeps (diagnostics)
     const bool any_work = __ballot(work) != 0;
     for (int it = 0; it < a.n_iters; ++it) {
@@ -1070,30 +1058,71 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
 
 // EM kernel.  FP32 descriptors whose staged windows are all exact in
 // binary16 (|G| <= 2048 for the Sobel responses, the usual case) are staged
-// as binary16 records: the same values, read as 8 bytes instead of 12 per
-// record, and the same FP32 arithmetic, so the results are the same bits.
+// as binary16 records, the others as int16 Sobel responses: the same values
+// in 8 bytes per record either way, and the same FP32 arithmetic, so the
+// results are the same bits.
 template <int K, int ST, bool FRAC, int SW, bool SYM>
 __device__ __forceinline__ void em_entry(const EmArgs &a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double red[8];
+    __shared__ int slots[64];
+    int y, x0, tw, xc, block_id;
+    if (a.items) {
+        // dynamic-only work item (one wave): the first up to 64 dynamic
+        // reference pixels (rho_ref < tau) of a row from the item's first
+        // column on, within seg_w columns of it, one per lane; the tile
+        // spans the first to the last of them
+        block_id = blockIdx.x;
+        if (block_id >= *a.n_items) {
+            // past the list: this block's objective partials are zero
+            if (threadIdx.x == 0)
+                for (int it = 0; it < a.n_iters; ++it)
+                    if (a.want_obj || it == a.n_iters - 1) a.obj[(size_t)it * a.n_blocks + block_id] = 0.0;
+            return;
+        }
+        const int2 item = a.items[block_id];
+        y = item.x;
+        const int first = item.y, lane = threadIdx.x;
+        const float *rho_ref = a.rho + (size_t)a.perm[0] * a.H * a.W + (size_t)y * a.W;
+        int before = 0;
+        for (int c = 0; c < a.seg_w; c += 64) {
+            const int col = first + c + lane;
+            const bool dyn = col < a.W && rho_ref[col] < a.tau;
+            const uint64_t m = __ballot(dyn);
+            const int rank = before + __popcll(m & ((1ull << lane) - 1ull));
+            if (dyn && rank < 64) slots[rank] = col;
+            before += __popcll(m);
+        }
+        const int cnt = min(before, 64);   // >= 1: the first column is dynamic
+        __syncthreads();
+        x0 = slots[0];
+        tw = slots[cnt - 1] - x0 + 1;
+        xc = lane < cnt ? slots[lane] - x0 : -1;
+    } else {
+        y = blockIdx.y;
+        x0 = blockIdx.x * a.tile;
+        tw = a.tile;
+        xc = threadIdx.x;
+        block_id = blockIdx.y * gridDim.x + blockIdx.x;
+    }
     if constexpr (ST == 0) {
         Window w[K];
         int total;
-        view_windows<K, FRAC>(a, blockIdx.x * a.tile, w, total);
+        view_windows<K, FRAC>(a, x0, tw, w, total);
         const float2 *feat = reinterpret_cast<const float2 *>(a.feat);
         bool exact = true;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const float2 *row = feat + ((size_t)a.perm[k] * a.H + blockIdx.y) * a.W;
+            const float2 *row = feat + ((size_t)a.perm[k] * a.H + y) * a.W;
             for (int p = threadIdx.x; p < w[k].len; p += blockDim.x) {
                 const float2 v = row[clampi(w[k].umin + p, 0, a.W - 1)];
                 exact = exact && exact_in_half(v.x) && exact_in_half(v.y);
             }
         }
-        if (__syncthreads_and(exact)) em_body<K, 0, 1, FRAC, SW, SYM>(a, lds_raw, red);
-        else em_body<K, 0, 0, FRAC, SW, SYM>(a, lds_raw, red);
+        if (__syncthreads_and(exact)) em_body<K, 0, 1, FRAC, SW, SYM>(a, lds_raw, red, y, x0, tw, xc, block_id);
+        else em_body<K, 0, 3, FRAC, SW, SYM>(a, lds_raw, red, y, x0, tw, xc, block_id);
     } else {
-        em_body<K, ST, ST, FRAC, SW, SYM>(a, lds_raw, red);
+        em_body<K, ST, ST, FRAC, SW, SYM>(a, lds_raw, red, y, x0, tw, xc, block_id);
     }
 }
 

@@ -83,6 +83,82 @@ __global__ __launch_bounds__(256) void lf_ray_prior_kernel(PriorArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Dynamic-only work list (reconstruction of the dynamic reference pixels
+// only, rho_ref < tau).  A work item is one wave: the next up to 64 dynamic
+// pixels of a row that lie within `span` columns of the item's first one
+// (span = a.seg_w, a multiple of 64, so that the item's view windows fit the
+// LDS).  The items of a row are cut greedily from left to right, so a row of
+// W columns has at most floor(W/64) items of 64 pixels plus floor((W-1)/span)
+// closed by the span, plus the last: per_row = W/64 + W/span + 1 bounds them.
+// grid H, one wave per row: the row's item starts (columns) and their
+// number; the pixels not reconstructed take the level nearest mu_T and
+// objective 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void lf_dyn_rows_kernel(EmArgs a, int per_row, int *__restrict__ counts,
+                                                         int *__restrict__ starts) {
+    const int y = blockIdx.x, lane = threadIdx.x;
+    const float *rho_ref = a.rho + (size_t)a.perm[0] * a.H * a.W + (size_t)y * a.W;
+    int *row_starts = starts + (size_t)y * per_row;
+    int n_items = 0, first = 0, n = 0;   // wave-uniform
+    for (int c0 = 0; c0 < a.W; c0 += 64) {
+        const int col = c0 + lane;
+        const bool in = col < a.W;
+        const bool dyn = in && rho_ref[col] < a.tau;
+        if (in && !dyn) {
+            const size_t pix = (size_t)y * a.W + col;
+            a.d_idx[pix] = nearest_level(a, a.mu_T[pix]);
+            a.lpix[pix] = 0.0f;
+        }
+        uint64_t m = __ballot(dyn);
+        while (m) {
+            const int cb = c0 + __builtin_ctzll(m);
+            m &= m - 1;
+            if (n > 0 && (n == 64 || cb - first >= a.seg_w)) {
+                if (lane == 0 && n_items < per_row) row_starts[n_items] = first;
+                ++n_items;
+                n = 0;
+            }
+            if (n == 0) first = cb;
+            ++n;
+        }
+    }
+    if (n > 0) {
+        if (lane == 0 && n_items < per_row) row_starts[n_items] = first;
+        ++n_items;
+    }
+    if (lane == 0) counts[y] = min(n_items, per_row);
+}
+
+// One block: exclusive scan of the rows' item counts, then the list in row
+// order as (row, first column).
+__global__ __launch_bounds__(256) void lf_dyn_items_kernel(const int *__restrict__ counts,
+                                                           const int *__restrict__ starts, int H, int per_row,
+                                                           int2 *__restrict__ items, int *__restrict__ n_items) {
+    __shared__ int part[256];
+    const int t = threadIdx.x, per = (H + 255) / 256;
+    const int beg = min(t * per, H), end = min(beg + per, H);
+    int sum = 0;
+    for (int y = beg; y < end; ++y) sum += counts[y];
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int i = 0; i < 256; ++i) {
+            const int v = part[i];
+            part[i] = acc;
+            acc += v;
+        }
+        *n_items = acc;
+    }
+    __syncthreads();
+    int off = part[t];
+    for (int y = beg; y < end; ++y) {
+        const int c = counts[y];
+        for (int i = 0; i < c; ++i) items[off++] = make_int2(y, starts[(size_t)y * per_row + i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Refocus (Eq. 2).  grid (ceil(W/blockDim), H).
 // ---------------------------------------------------------------------------
 struct RefocusArgs {

@@ -89,7 +89,20 @@ hipError_t launch_descriptors(const lf_params *p, const uint8_t *views, void *fe
 hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *mu_T, const float *q_warm,
                             float *rho, float *omr, float *q, uint32_t *bad, int check, hipStream_t s);
 hipError_t launch_median3(const lf_params *p, const float *in, float *out, hipStream_t s);
-hipError_t launch_em(const lf_params *p, const Geometry &g, EmArgs a, int tile, size_t lds, hipStream_t s);
+// Dynamic-only work list of a frame (span == 0: not dynamic-only).
+struct DynPlan {
+    int span;        // columns an item's pixels may spread over (multiple of 64)
+    int per_row;     // bound on a row's items
+    int max_items;   // H * per_row
+    size_t lds;      // block LDS of an item's windows
+};
+DynPlan dyn_plan(const lf_params *p, const Geometry &g, size_t lds_limit);
+// Ints of the per-row scratch of the list: H counts and H * per_row starts.
+size_t dyn_rows_ints(const lf_params *p, const DynPlan &d);
+hipError_t launch_dyn_list(const lf_params *p, const EmArgs &a, const DynPlan &d, int *rows, int2 *items,
+                           int *n_items, hipStream_t s);
+hipError_t launch_em(const lf_params *p, const Geometry &g, EmArgs a, int tile, size_t lds, hipStream_t s,
+                     const DynPlan *d);
 hipError_t launch_refocus_frame(const lf_params *p, const Geometry &g, const uint8_t *views, const int32_t *d_idx,
                                 const float *q, const float *rho, float *rgb, uint8_t *hole, float *rgb_med,
                                 int median, int32_t *d_out, float *q_out, hipStream_t s);

@@ -44,12 +44,12 @@ static lf_status scratch_address(int device, unsigned char **out) {
 
 // Byte ranges of the frame's intermediate buffers inside the scratch array.
 struct NoallocPlan {
-    size_t feat, rho, omr, lpix, obj, rgb_med, bad, total;
+    size_t feat, rho, omr, lpix, obj, rgb_med, bad, dyn_rows, dyn_items, dyn_n, total;
 };
 
 static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static NoallocPlan noalloc_plan(const lf_params *p, int n_blocks, int n_iters, int median) {
+static NoallocPlan noalloc_plan(const lf_params *p, int n_blocks, int n_iters, int median, const DynPlan &d) {
     const size_t HW = (size_t)p->H * p->W, KHW = HW * p->K;
     NoallocPlan pl{};
     size_t o = 0;
@@ -65,6 +65,11 @@ static NoallocPlan noalloc_plan(const lf_params *p, int n_blocks, int n_iters, i
     pl.obj = carve((size_t)std::min(n_iters, kMaxItersPerLaunch) * n_blocks * 8);
     pl.rgb_med = median ? carve(HW * 12) : 0;
     pl.bad = carve(4);
+    if (d.span) {
+        pl.dyn_rows = carve(dyn_rows_ints(p, d) * 4);
+        pl.dyn_items = carve((size_t)d.max_items * 8);
+        pl.dyn_n = carve(4);
+    }
     pl.total = o;
     return pl;
 }
@@ -104,8 +109,11 @@ extern "C" lf_status lf_em_frame_noalloc(const lf_params *p, const uint8_t *view
     size_t lds = 0;
     st = em_launch_shape(&pp, g, device, &tile, &lds);
     if (st != LF_OK) return st;
-    const int n_blocks = ((pp.W + tile - 1) / tile) * pp.H;
-    const NoallocPlan pl = noalloc_plan(&pp, n_blocks, n_iters, median);
+    int lds_limit = 0;
+    LF_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device), "device attribute");
+    const DynPlan dyn = dyn_plan(&pp, g, (size_t)lds_limit);
+    const int n_blocks = dyn.span ? dyn.max_items : ((pp.W + tile - 1) / tile) * pp.H;
+    const NoallocPlan pl = noalloc_plan(&pp, n_blocks, n_iters, median, dyn);
     if (pl.total > LF_NOALLOC_SCRATCH_BYTES)
         return set_error(LF_EINVAL, "frame needs %zu bytes of scratch, above the fixed %zu", pl.total,
                          (size_t)LF_NOALLOC_SCRATCH_BYTES);
@@ -125,6 +133,19 @@ extern "C" lf_status lf_em_frame_noalloc(const lf_params *p, const uint8_t *view
     LF_HIP(launch_ray_prior(&pp, S_P, mu_T, q_warm, rho, omr, q, bad, 1, s), "ray prior launch");
 
     EmArgs a = make_em_args(&pp, g, derived_lambda(&pp));
+    if (dyn.span) {
+        EmArgs da = a;
+        da.rho = rho;
+        da.mu_T = mu_T;
+        da.d_idx = d_idx;
+        da.lpix = lpix;
+        da.seg_w = dyn.span;
+        LF_HIP(launch_dyn_list(&pp, da, dyn, reinterpret_cast<int *>(base + pl.dyn_rows),
+                               reinterpret_cast<int2 *>(base + pl.dyn_items), reinterpret_cast<int *>(base + pl.dyn_n), s),
+               "dynamic-only work list");
+        a.items = reinterpret_cast<const int2 *>(base + pl.dyn_items);
+        a.n_items = reinterpret_cast<const int *>(base + pl.dyn_n);
+    }
     a.feat = feat;
     a.rho = rho;
     a.omr = omr;
@@ -138,7 +159,7 @@ extern "C" lf_status lf_em_frame_noalloc(const lf_params *p, const uint8_t *view
         a.n_iters = n;
         a.seed_from_d = done > 0;
         a.want_obj = objective != nullptr;
-        LF_HIP(launch_em(&pp, g, a, tile, lds, s), "EM launch");
+        LF_HIP(launch_em(&pp, g, a, tile, lds, s, &dyn), "EM launch");
         if (objective) LF_HIP(launch_objective_sum(obj, n_blocks, n, objective + done, s), "objective launch");
         done += n;
     }

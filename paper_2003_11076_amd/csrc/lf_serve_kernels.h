@@ -62,7 +62,7 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
 
     Window w[K];
     int total;
-    view_windows<K, FRAC>(a, x0, w, total);
+    view_windows<K, FRAC>(a, x0, TILE, w, total);
     R *win = reinterpret_cast<R *>(lds);
     // intensity rows of one view at a time, after the records
     int16_t *lsum = reinterpret_cast<int16_t *>(lds + (size_t)total * sizeof(R));

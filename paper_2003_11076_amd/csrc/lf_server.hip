@@ -185,7 +185,7 @@ namespace {
 size_t frame_lds(const lf_params &p, const Geometry &g) {
     const size_t pairs = em_window_pairs(&p, g, serve_tile_width(p.K));
     const size_t widest = em_window_widest(&p, g, serve_tile_width(p.K));
-    return pairs * rec_bytes(p.storage) + 2 * 3 * (widest + 2) + 64;
+    return pairs * (size_t)(p.storage == LF_F32 ? 16 : 8) + 2 * 3 * (widest + 2) + 64;
 }
 
 int frame_kind(const lf_params &p, const Geometry &g) {

@@ -385,7 +385,10 @@ def teacher_forced(case: Case, n_iters: int, rows=None, device_inputs=True, chec
             stats.append({"refocus_maxabs": rmax})
             if expect is not None:
                 for name, a, b in zip(("rgb", "d_idx", "q"), expect, (rgb_g, d_g, q_g)):
-                    assert np.array_equal(np.asarray(a), b), f"{name} differs from the other path's"
+                    a = np.asarray(a)
+                    bad = np.argwhere(a != b)
+                    assert not len(bad), f"{name} differs from the other path's at {len(bad)} places, " \
+                                         f"first {bad[:3].tolist()}: {a[tuple(bad[0])]} vs {b[tuple(bad[0])]}"
         return stats
     finally:
         run.close()

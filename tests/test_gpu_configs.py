@@ -70,6 +70,9 @@ def test_serving_mix_shapes_against_the_oracle():
                      torch.zeros((sp.K, sp.H, sp.W), device=dev))
                 keep.append(ins)
                 outs[s, f] = o
+                # the server's streams do not wait for torch's: the copies and
+                # fills above must be done before the frame is submitted
+                torch.cuda.synchronize()
                 LF.lf_submit_frame(srv, s, p, *ins, *o, cb)
         LF.lf_server_drain(srv)
     finally:

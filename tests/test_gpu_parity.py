@@ -56,6 +56,27 @@ def test_small_cases_teacher_forced(K, H, W, D, b, dmin, dstep, st, mode):
     teacher_forced(case, 3)
 
 
+def _sobel_beyond_binary16(views):
+    """Whether some 3x3 Sobel response of R+G+B (replicated border) is not
+    exact in binary16 (|G| > 2048 and odd)."""
+    L = np.pad(views.astype(np.int64).sum(-1), ((0, 0), (1, 1), (1, 1)), mode="edge")
+    gx = (L[:, :-2, 2:] - L[:, :-2, :-2]) + 2 * (L[:, 1:-1, 2:] - L[:, 1:-1, :-2]) + (L[:, 2:, 2:] - L[:, 2:, :-2])
+    gy = (L[:, 2:, :-2] - L[:, :-2, :-2]) + 2 * (L[:, 2:, 1:-1] - L[:, :-2, 1:-1]) + (L[:, 2:, 2:] - L[:, :-2, 2:])
+    g = np.concatenate([gx.ravel(), gy.ravel()])
+    return bool(np.any((np.abs(g) > 2048) & (g % 2 != 0)))
+
+
+@pytest.mark.parametrize("K,b,dstep", [(5, None, 1), (4, [-1.5, 0, 0.5, 2.25], 0.5)])
+def test_fp32_descriptors_beyond_binary16(K, b, dstep):
+    """Binary views (0 or 255 per channel): Sobel responses up to 3060, many
+    of them not exact in binary16, so FP32 descriptors take the int16 records."""
+    case = random_case(K, 4, 150, 20, baselines=b, d_step=dstep, storage="f32", seed=31 + K)
+    case.views = np.where(case.views >= 128, 255, 0).astype(np.uint8)
+    assert _sobel_beyond_binary16(case.views)
+    _say(f"binary views K={K} 4x150 D=20 fp32 b={b}: int16 records")
+    teacher_forced(case, 3)
+
+
 def test_plain_full_size_fp32():
     fr = workload_frame("plain")
     case = Case.from_frame(fr, storage="f32")

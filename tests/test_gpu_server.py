@@ -88,10 +88,14 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("kw", CASES)
+@pytest.mark.parametrize("kw", CASES + [dict(K=5, H=6, W=150, D=20, storage="f32", binary=True)])
 def test_server_equals_plain_context(kw):
     kw = dict(kw)
+    binary = kw.pop("binary", False)
     case = random_case(kw.pop("K"), kw.pop("H"), kw.pop("W"), kw.pop("D"), seed=11, **kw)
+    if binary:
+        # Sobel responses beyond binary16: FP32 descriptors as int16 records
+        case.views = np.where(case.views >= 128, 255, 0).astype(np.uint8)
     _say(f"server vs plain context K={case.K} {case.H}x{case.W} D={case.D} {case.storage} {case.mode}")
     with Server(n_iters=3) as srv:
         fid, (rgb, d, q) = srv.submit(0, case)
@@ -289,6 +293,7 @@ def test_device_inputs_and_outputs_equal_host_ones():
             o = (torch.full((c.H, c.W, 3), -1.0, device=dev), torch.full((c.H, c.W), -1, dtype=torch.int32, device=dev),
                  torch.full((c.K, c.H, c.W), -1.0, device=dev))
             keep.append((ins, o))
+            torch.cuda.synchronize()       # the server's streams do not wait for torch's
             LF.lf_submit_frame(srv.srv, 0 if c.K == 5 else 1, c.api_params(flags), *ins, *o, srv._cb)
         srv.drain()
         torch.cuda.synchronize()
@@ -317,6 +322,7 @@ def test_invalid_device_inputs_fail_the_frame_only():
             ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (good.views, sp, good.mu_T)]
             o = torch.zeros((good.H, good.W, 3), device=dev)
             keep.append((ins, o))
+            torch.cuda.synchronize()       # the server's streams do not wait for torch's
             fids.append(LF.lf_submit_frame(srv.srv, i, good.api_params(flags), *ins, o, None, None, srv._cb))
         srv.drain()
         st = srv.stats()

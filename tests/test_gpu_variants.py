@@ -79,6 +79,41 @@ def test_dynamic_only_equals_plain_on_dynamic_pixels():
     assert not h1[~dyn].any()
 
 
+def test_dynamic_only_work_list_shapes():
+    """Rows whose dynamic pixels cut into work items in every way: a whole
+    dynamic row (items of 64), pixels 100 columns apart (items closed by the
+    span), a dense run then a lone pixel in the last column, one dynamic pixel
+    at column 0, no dynamic pixel.  Bitwise equal to the plain path on the
+    dynamic pixels, level nearest mu_T and objective 0 on the others; and the
+    oracle's dynamic-only run, teacher-forced."""
+    case = random_case(5, 5, 600, 24, storage="f16", seed=41)
+    tau = float(case.tau)
+    sp = case.S_P.copy()
+    ref = case.ref
+    sp[ref] = np.float32(min(tau + 0.2, 1.0))
+    sp[ref, 0, :] = 0.1
+    sp[ref, 1, ::100] = 0.1
+    sp[ref, 2, 150:350] = 0.1
+    sp[ref, 2, -1] = 0.1
+    sp[ref, 3, 0] = 0.1
+    case.S_P = sp
+    _say("dynamic-only work list shapes 600x5 K=5 D=24 f16")
+    (rgb0, d0, q0, h0), L0 = _run(case, 0)
+    (rgb1, d1, q1, h1), L1 = _run(case, DYN)
+    run = DeviceRun(case)
+    _, rho = run.intermediates()
+    run.close()
+    dyn = rho[ref] < np.float32(case.tau)
+    assert dyn[0].all() and dyn[1].sum() == 6 and dyn[2].sum() == 201 and dyn[3].sum() == 1 and not dyn[4].any()
+    assert np.array_equal(d1[dyn], d0[dyn]) and np.array_equal(q1[:, dyn], q0[:, dyn])
+    assert np.array_equal(L1[dyn], L0[dyn]) and np.all(L1[~dyn] == 0)
+    d_min, d_step = float(case.d_min), float(case.d_step)
+    near = np.clip(np.ceil((case.mu_T.astype(np.float64) - d_min) / d_step - 0.5), 0, case.D - 1).astype(np.int32)
+    assert np.array_equal(d1[~dyn], near[~dyn])
+    case.flags = DYN
+    teacher_forced(case, 3)
+
+
 def test_window_covering_all_levels_is_the_plain_sweep():
     """With 3 sigma wider than the level range the window holds every level:
     same bits as the plain sweep (fast and exhaustive)."""
