@@ -304,18 +304,25 @@ def form_leg(args, LF, torch, arrs, storage, steps, warmup, n_streams, mode="sof
     }
 
 
-def variant_legs(LF, torch, arrs, storage, reps=20):
-    """EM launch time of the same frame with the paper's speed levers and
-    E-step forms: the search window around mu_T, dynamic reference pixels
-    only, both, and the enumeration E-step."""
-    spec, _, _, _, beta = arrs
+def variant_legs(LF, torch, arrs, storage, reps=20, names=None):
+    """EM launch time of the same frame, one launch at a time on an idle GPU,
+    plain and with the paper's speed levers and E-step forms: the search
+    window around mu_T, dynamic reference pixels only, both, and the
+    enumeration E-step."""
+    spec, _, sp_host, _, beta = arrs
     dev = torch.device("cuda:0")
     views, sp, mu = _to_dev(torch, arrs, dev)
     stream = torch.cuda.current_stream()
-    legs = [("window_3sigma", "soft", LF.LF_PRIOR_WINDOW), ("dynamic_only", "soft", LF.LF_DYNAMIC_ONLY),
+    legs = [("plain", "soft", 0), ("window_3sigma", "soft", LF.LF_PRIOR_WINDOW),
+            ("dynamic_only", "soft", LF.LF_DYNAMIC_ONLY),
             ("window_and_dynamic_only", "soft", LF.LF_PRIOR_WINDOW | LF.LF_DYNAMIC_ONLY),
             ("enumeration_soft", "enum_soft", 0), ("enumeration_hard", "enum_hard", 0)]
-    out = {}
+    if names is not None:
+        legs = [leg for leg in legs if leg[0] in names]
+    out = {"workload": spec.name,
+           # reference pixels whose static prior is below tau (the reference
+           # view's ray lands on its own pixel, so rho_ref is S_P there)
+           "dynamic_fraction": float(np.mean(sp_host[spec.ref] < np.float32(spec.tau)))}
     dev_flags = LF.LF_INPUTS_ON_DEVICE | LF.LF_OUTPUTS_ON_DEVICE
     for name, mode, flags in legs:
         ctx = LF.lf_em_init(_params(LF, spec, beta, storage, mode, dev_flags | flags), views, sp, mu,
@@ -332,6 +339,8 @@ def variant_legs(LF, torch, arrs, storage, reps=20):
                 ts.append(e0.elapsed_time(e1))
         LF.lf_em_destroy(ctx)
         out[name] = {"em_ms": float(np.median(ts)), "mode": mode}
+    if "plain" in out and "dynamic_only" in out:
+        out["dynamic_only_time_share"] = out["dynamic_only"]["em_ms"] / out["plain"]["em_ms"]
     return out
 
 
@@ -352,6 +361,9 @@ class Frames:
             flags = (LF.LF_INPUTS_ON_DEVICE | LF.LF_OUTPUTS_ON_DEVICE) if device_io else 0
             ins = _to_dev(torch, arrs, dev) if device_io else (views, sp, mu)
             self.items.append((spec, _params(LF, spec, beta, storage, "soft", flags), ins))
+        # the server's streams do not wait for torch's: the input copies are
+        # complete before any frame is submitted
+        torch.cuda.synchronize()
         self.ring = ring
         self.rings = {}
 
@@ -797,7 +809,9 @@ def main():
     if not args.no_variants:
         log(args, "timing the variants (search window, dynamic-only, enumeration)")
         out["variants"] = variant_legs(LF, torch, main_arrs, storage)
-        out["variants"]["plain_em_ms"] = m["roofline"]["kernel_ms"]
+        if "precision" in inputs:
+            out["variants"]["dynamic_only_precision"] = variant_legs(
+                LF, torch, inputs["precision"][0], "f16", reps=10, names=("plain", "dynamic_only"))
     if not args.no_serving:
         log(args, "serving the headline frame through the FP16 frame server (device buffers)")
         sw = serve_same_workload(args, LF, torch, main_arrs)

@@ -6,9 +6,11 @@
 // piecewise-linearly over a Delaunay triangulation of the points.
 //
 // Device: integer Sobel responses, the matching of every grid point of every
-// pass (one lane per point, all levels), and the raster of the triangulation.
-// Host (native C++): assembling, filtering and sorting the points, and the
-// triangulation (incremental Delaunay with exact integer predicates).
+// pass (one lane per point, all levels), the transfer of the other views'
+// points with one point per reference pixel, the consistency filter, the
+// ordering of the points by (y, u), and the raster of the triangulation.
+// Host (native C++): the four corners and the triangulation (incremental
+// Delaunay with exact integer predicates).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -145,6 +147,172 @@ __global__ __launch_bounds__(128) void lf_support_match_kernel(MatchArgs m) {
     m.level[i] = j_out;
 }
 
+// ---------------------------------------------------------------------------
+// Candidate points.  Every point lies on a grid row (y = step/2 + iy * step):
+// the reference's points at their grid column, the other views' points
+// moved along the row.  Per-row maps [ny][W] hold each reference pixel's
+// candidate (level, or -1, and view); no pixel holds two, since reference
+// points need S_P_ref >= tau and moved points S_P_ref < tau, and moved points
+// that land on one pixel keep the first (lowest pass, i.e. view, then grid
+// order): the smallest key pass * n_grid + grid index claims the pixel.
+// ---------------------------------------------------------------------------
+struct CandArgs {
+    const int32_t *lev;       // [n_pass][n_grid] matched level or -1
+    const float *sp_ref;      // S_P of the reference view [H][W]
+    unsigned long long *claim;  // [ny][W] smallest key of a point moved there
+    int32_t *level;           // [ny][W] candidate level or -1
+    int32_t *view;            // [ny][W] candidate's view
+    int W, nx, ny, step, n_grid, dmin_i, dstep_i;
+    float tau;
+    int pass_view[LF_MAX_VIEWS];   // view of each pass (pass 0: the reference)
+    int pass_bi[LF_MAX_VIEWS];     // its integer baseline
+};
+
+// grid (ceil(n_grid/256)), block 256: the reference's points (pass 0)
+__global__ __launch_bounds__(256) void lf_cand_ref_kernel(CandArgs c) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= c.n_grid) return;
+    const int j = c.lev[i];
+    if (j < 0) return;
+    const int ix = i % c.nx, iy = i / c.nx;
+    const size_t m = (size_t)iy * c.W + c.step / 2 + ix * c.step;
+    c.level[m] = j;
+    c.view[m] = c.pass_view[0];
+}
+
+// The reference pixel a point of pass ps >= 1 moves to, or -1: inside the
+// frame and dynamic in the reference (S_P_ref < tau).
+__device__ __forceinline__ long moved_pixel(const CandArgs &c, int ps, int i, int &j) {
+    j = c.lev[(size_t)ps * c.n_grid + i];
+    if (j < 0) return -1;
+    const int ix = i % c.nx, iy = i / c.nx;
+    const int x = c.step / 2 + ix * c.step, y = c.step / 2 + iy * c.step;
+    const long u = (long)x + (long)c.pass_bi[ps] * ((long)c.dmin_i + (long)j * c.dstep_i);
+    if (u < 0 || u >= c.W) return -1;
+    if (!(c.sp_ref[(size_t)y * c.W + u] < c.tau)) return -1;
+    return (long)iy * c.W + u;
+}
+
+// grid (ceil(n_grid/256), n_pass - 1), block 256
+__global__ __launch_bounds__(256) void lf_cand_claim_kernel(CandArgs c) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, ps = blockIdx.y + 1;
+    if (i >= c.n_grid) return;
+    int j;
+    const long m = moved_pixel(c, ps, i, j);
+    if (m >= 0) atomicMin(&c.claim[m], (unsigned long long)ps * c.n_grid + i);
+}
+
+// grid as lf_cand_claim_kernel, after it
+__global__ __launch_bounds__(256) void lf_cand_moved_kernel(CandArgs c) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, ps = blockIdx.y + 1;
+    if (i >= c.n_grid) return;
+    int j;
+    const long m = moved_pixel(c, ps, i, j);
+    if (m >= 0 && c.claim[m] == (unsigned long long)ps * c.n_grid + i) {
+        c.level[m] = j;
+        c.view[m] = c.pass_view[ps];
+    }
+}
+
+// Ordered compaction of a per-row map's entries (level >= 0) into points
+// (u, y, level, view), by row then column.  grid (ny), block 256: the count
+// of each row.
+__global__ __launch_bounds__(256) void lf_row_count_kernel(const int32_t *__restrict__ level, int W,
+                                                           int32_t *__restrict__ row_n) {
+    __shared__ int part[4];
+    const int iy = blockIdx.x, t = threadIdx.x;
+    int n = 0;
+    for (int x = t; x < W; x += 256) n += level[(size_t)iy * W + x] >= 0;
+    part[t >> 6] = 0;
+    __syncthreads();
+    atomicAdd(&part[t >> 6], n);
+    __syncthreads();
+    if (t == 0) row_n[iy] = part[0] + part[1] + part[2] + part[3];
+}
+
+// One block: row_start[iy] = sum of row_n[0 .. iy), row_start[ny] the total.
+__global__ __launch_bounds__(1024) void lf_row_scan_kernel(const int32_t *__restrict__ row_n, int ny,
+                                                           int32_t *__restrict__ row_start) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x, per = (ny + 1023) / 1024;
+    const int beg = min(t * per, ny), end = min(beg + per, ny);
+    int sum = 0;
+    for (int i = beg; i < end; ++i) sum += row_n[i];
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int i = 0; i < 1024; ++i) {
+            const int v = part[i];
+            part[i] = acc;
+            acc += v;
+        }
+        row_start[ny] = acc;
+    }
+    __syncthreads();
+    int off = part[t];
+    for (int i = beg; i < end; ++i) {
+        row_start[i] = off;
+        off += row_n[i];
+    }
+}
+
+// grid (ny), block 256: each row's entries in column order from row_start.
+__global__ __launch_bounds__(256) void lf_row_write_kernel(const int32_t *__restrict__ level,
+                                                           const int32_t *__restrict__ view, int W, int step,
+                                                           const int32_t *__restrict__ row_start,
+                                                           int4 *__restrict__ out) {
+    __shared__ int part[4];
+    const int iy = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int y = step / 2 + iy * step;
+    int base = row_start[iy];
+    for (int x0 = 0; x0 < W; x0 += 256) {
+        const int x = x0 + t;
+        const size_t m = (size_t)iy * W + x;
+        const bool on = x < W && level[m] >= 0;
+        const uint64_t b = __ballot(on);
+        if (lane == 0) part[wv] = __popcll(b);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int k = 0; k < 4; ++k) {
+            before += k < wv ? part[k] : 0;
+            total += part[k];
+        }
+        if (on) out[base + before + __popcll(b & ((1ull << lane) - 1ull))] = make_int4(x, y, level[m], view[m]);
+        base += total;
+        __syncthreads();
+    }
+}
+
+// Consistency (one lane per candidate, candidates ordered by row then
+// column): a candidate is kept with at least incon_min other candidates
+// within R pixels in x and y and incon_levels levels.  The kept ones go to
+// the per-row map `kept` (level, else -1).  grid (ceil(cap/256)); lanes past
+// the number of candidates exit.
+__global__ __launch_bounds__(256) void lf_consistency_kernel(const int4 *__restrict__ cand,
+                                                             const int32_t *__restrict__ row_start, int ny, int W,
+                                                             int step, int R, int L, int n_min,
+                                                             int32_t *__restrict__ kept) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= row_start[ny]) return;
+    const int4 c = cand[i];
+    const int iy = (c.y - step / 2) / step;
+    int cnt = 0;
+    const int r_rows = R / step;
+    for (int iy2 = max(iy - r_rows, 0); iy2 <= min(iy + r_rows, ny - 1) && cnt < n_min; ++iy2) {
+        // first candidate of the row with u >= c.x - R
+        int lo = row_start[iy2], hi = row_start[iy2 + 1];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cand[mid].x < c.x - R) lo = mid + 1;
+            else hi = mid;
+        }
+        for (int k = lo; k < row_start[iy2 + 1] && cand[k].x <= c.x + R && cnt < n_min; ++k)
+            cnt += k != i && abs(cand[k].z - c.z) <= L;
+    }
+    if (cnt >= n_min) kept[(size_t)iy * W + c.x] = c.z;
+}
+
 // Raster of the triangulation: the lowest-index triangle containing each
 // pixel (edges included), found with an atomic min so the result does not
 // depend on the order of arrival.  grid (n_tri), block 256.
@@ -251,12 +419,37 @@ struct Tri {
     bool alive;
 };
 
+// Position of (x, y) along the Hilbert curve over a 2^15 x 2^15 grid (the
+// published bit-by-bit construction: quadrant digit, then the rotation and
+// reflection of the sub-square).
+inline uint64_t hilbert_index(uint32_t x, uint32_t y) {
+    const uint32_t n = 1u << 15;
+    uint64_t d = 0;
+    for (uint32_t s = n / 2; s > 0; s /= 2) {
+        const uint32_t rx = (x & s) ? 1 : 0, ry = (y & s) ? 1 : 0;
+        d += (uint64_t)s * s * ((3 * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = n - 1 - x;
+                y = n - 1 - y;
+            }
+            std::swap(x, y);
+        }
+    }
+    return d;
+}
+
 class Delaunay {
   public:
     std::vector<P2> P;
     std::vector<Tri> T;
     int n_real = 0;
 
+    // Points are inserted along the Hilbert curve: consecutive points are
+    // near each other, so the walk to the next point is short and each
+    // cavity small (row order would leave a long front of triangles on the
+    // far vertices, each cavity growing with the row).  Where points are
+    // cocircular the order decides which of the valid triangulations comes out.
     void run(const std::vector<P2> &pts) {
         n_real = (int)pts.size();
         P = pts;
@@ -265,11 +458,21 @@ class Delaunay {
         P.push_back({3 * L, -L});
         P.push_back({-L, 3 * L});
         T.clear();
+        T.reserve((size_t)6 * n_real + 16);
         T.push_back({{n_real, n_real + 1, n_real + 2}, {-1, -1, -1}, true});
+        std::vector<std::pair<uint64_t, int>> order(n_real);
+        for (int i = 0; i < n_real; ++i) order[i] = {hilbert_index((uint32_t)P[i].x, (uint32_t)P[i].y), i};
+        std::sort(order.begin(), order.end());
         int last = 0;
         std::vector<int> bad, stack;
         std::vector<char> mark;
-        for (int i = 0; i < n_real; ++i) {
+        struct Edge {
+            int a, b, outer;
+        };
+        std::vector<Edge> edges;
+        std::vector<std::pair<int, int>> by_a;
+        for (int oi = 0; oi < n_real; ++oi) {
+            const int i = order[oi].second;
             const int t0 = locate(P[i], last);
             if (t0 < 0) continue;   // a duplicate point
             // cavity: triangles whose circumcircle strictly holds the point
@@ -292,10 +495,7 @@ class Delaunay {
                 }
             }
             // boundary edges of the cavity, each with its outer neighbour
-            struct Edge {
-                int a, b, outer;
-            };
-            std::vector<Edge> edges;
+            edges.clear();
             for (int t : bad)
                 for (int e = 0; e < 3; ++e) {
                     const int nb = T[t].n[e];
@@ -320,11 +520,8 @@ class Delaunay {
             }
             // link the fan: triangle (a, b, i) meets (b, c, i) across edge b-i
             // (opposite a) and (z, a, i) across edge i-a (opposite b)
-            std::vector<std::pair<int, int>> by_a(edges.size()), by_b(edges.size());
-            for (size_t k = 0; k < edges.size(); ++k) {
-                by_a[k] = {edges[k].a, base + (int)k};
-                by_b[k] = {edges[k].b, base + (int)k};
-            }
+            by_a.resize(edges.size());
+            for (size_t k = 0; k < edges.size(); ++k) by_a[k] = {edges[k].a, base + (int)k};
             std::sort(by_a.begin(), by_a.end());
             for (size_t k = 0; k < edges.size(); ++k) {
                 Tri &t = T[base + (int)k];
@@ -511,60 +708,77 @@ extern "C" lf_status lf_build_prior(const lf_params *p, const lf_support_params 
             LF_HIP(hipGetLastError(), "support match launch");
         }
     }
-    std::vector<int32_t> lev(pass_view.size() * n_grid);
-    std::vector<float> sp_ref(HW);
-    if (!lev.empty())
-        LF_HIP(hipMemcpyAsync(lev.data(), b_lev.p, lev.size() * 4, hipMemcpyDeviceToHost, s), "copy");
-    LF_HIP(hipMemcpyAsync(sp_ref.data(), d_sp + (size_t)p->ref * HW, HW * 4, hipMemcpyDeviceToHost, s), "copy");
-    LF_HIP(hipStreamSynchronize(s), "synchronize");
-
-    // candidates: reference points, then transferred points (lowest view,
-    // then grid order, wins a reference pixel)
-    std::vector<int4> cand;
-    std::vector<char> taken(HW, 0);
-    const float tau = p->tau_init;
-    for (size_t ps = 0; ps < pass_view.size(); ++ps) {
-        const int a = pass_view[ps];
-        for (int iy = 0; iy < ny; ++iy)
-            for (int ix = 0; ix < nx; ++ix) {
-                const int j = lev[ps * n_grid + (size_t)iy * nx + ix];
-                if (j < 0) continue;
-                const int x = step / 2 + ix * step, y = step / 2 + iy * step;
-                if (ps == 0) {
-                    cand.push_back(make_int4(x, y, j, a));
-                    continue;
-                }
-                const int u = x + g.bi[a] * (g.dmin_i + j * g.dstep_i);
-                if (u < 0 || u >= W) continue;
-                if (!(sp_ref[(size_t)y * W + u] < tau)) continue;
-                if (taken[(size_t)y * W + u]) continue;
-                taken[(size_t)y * W + u] = 1;
-                cand.push_back(make_int4(u, y, j, a));
-            }
+    // candidates (per-row maps), their ordered list, the consistency filter
+    // and the ordered list of the points kept, on the device
+    const int n_pass = (int)pass_view.size();
+    const size_t n_map = (size_t)std::max(ny, 0) * W;
+    const size_t cap = std::max<size_t>(n_grid * n_pass, 1);
+    DevBuf b_claim, b_level, b_view, b_kept, b_rown, b_rows, b_cand, b_pts0;
+    LF_HIP(hipMalloc(&b_claim.p, std::max<size_t>(n_map, 1) * 8), "allocation");
+    LF_HIP(hipMalloc(&b_level.p, std::max<size_t>(n_map, 1) * 4), "allocation");
+    LF_HIP(hipMalloc(&b_view.p, std::max<size_t>(n_map, 1) * 4), "allocation");
+    LF_HIP(hipMalloc(&b_kept.p, std::max<size_t>(n_map, 1) * 4), "allocation");
+    LF_HIP(hipMalloc(&b_rown.p, (size_t)(std::max(ny, 0) + 1) * 4), "allocation");
+    LF_HIP(hipMalloc(&b_rows.p, (size_t)(std::max(ny, 0) + 1) * 4), "allocation");
+    LF_HIP(hipMalloc(&b_cand.p, cap * sizeof(int4)), "allocation");
+    LF_HIP(hipMalloc(&b_pts0.p, cap * sizeof(int4)), "allocation");
+    int32_t n_pts0 = 0;
+    if (n_grid > 0) {
+        const unsigned fill_blocks = (unsigned)((n_map + 255) / 256);
+        // -1 in every int32 half: the claim keys start at the largest value
+        hipLaunchKernelGGL(lf_prior_fill_kernel, dim3(2 * fill_blocks), dim3(256), 0, s, (int32_t *)b_claim.p,
+                           2 * n_map, -1);
+        hipLaunchKernelGGL(lf_prior_fill_kernel, dim3(fill_blocks), dim3(256), 0, s, (int32_t *)b_level.p, n_map, -1);
+        hipLaunchKernelGGL(lf_prior_fill_kernel, dim3(fill_blocks), dim3(256), 0, s, (int32_t *)b_kept.p, n_map, -1);
+        LF_HIP(hipGetLastError(), "fill launch");
+        CandArgs c{};
+        c.lev = (const int32_t *)b_lev.p;
+        c.sp_ref = d_sp + (size_t)p->ref * HW;
+        c.claim = (unsigned long long *)b_claim.p;
+        c.level = (int32_t *)b_level.p;
+        c.view = (int32_t *)b_view.p;
+        c.W = W;
+        c.nx = nx;
+        c.ny = ny;
+        c.step = step;
+        c.n_grid = (int)n_grid;
+        c.dmin_i = g.dmin_i;
+        c.dstep_i = g.dstep_i;
+        c.tau = p->tau_init;
+        for (int ps = 0; ps < n_pass; ++ps) {
+            c.pass_view[ps] = pass_view[ps];
+            c.pass_bi[ps] = g.bi[pass_view[ps]];
+        }
+        const unsigned gb = (unsigned)((n_grid + 255) / 256);
+        hipLaunchKernelGGL(lf_cand_ref_kernel, dim3(gb), dim3(256), 0, s, c);
+        if (n_pass > 1) {
+            hipLaunchKernelGGL(lf_cand_claim_kernel, dim3(gb, n_pass - 1), dim3(256), 0, s, c);
+            hipLaunchKernelGGL(lf_cand_moved_kernel, dim3(gb, n_pass - 1), dim3(256), 0, s, c);
+        }
+        LF_HIP(hipGetLastError(), "candidate launch");
+        int32_t *rown = (int32_t *)b_rown.p, *rows = (int32_t *)b_rows.p;
+        hipLaunchKernelGGL(lf_row_count_kernel, dim3(ny), dim3(256), 0, s, (const int32_t *)b_level.p, W, rown);
+        hipLaunchKernelGGL(lf_row_scan_kernel, dim3(1), dim3(1024), 0, s, rown, ny, rows);
+        hipLaunchKernelGGL(lf_row_write_kernel, dim3(ny), dim3(256), 0, s, (const int32_t *)b_level.p,
+                           (const int32_t *)b_view.p, W, step, rows, (int4 *)b_cand.p);
+        hipLaunchKernelGGL(lf_consistency_kernel, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s,
+                           (const int4 *)b_cand.p, rows, ny, W, step, sp->incon_radius, sp->incon_levels,
+                           sp->incon_min, (int32_t *)b_kept.p);
+        LF_HIP(hipGetLastError(), "candidate list launch");
+        // the points kept, ordered by (y, u) (the same row maps, counted again)
+        hipLaunchKernelGGL(lf_row_count_kernel, dim3(ny), dim3(256), 0, s, (const int32_t *)b_kept.p, W, rown);
+        hipLaunchKernelGGL(lf_row_scan_kernel, dim3(1), dim3(1024), 0, s, rown, ny, rows);
+        hipLaunchKernelGGL(lf_row_write_kernel, dim3(ny), dim3(256), 0, s, (const int32_t *)b_kept.p,
+                           (const int32_t *)b_view.p, W, step, rows, (int4 *)b_pts0.p);
+        LF_HIP(hipGetLastError(), "point list launch");
+        LF_HIP(hipMemcpyAsync(&n_pts0, rows + ny, 4, hipMemcpyDeviceToHost, s), "copy");
+        LF_HIP(hipStreamSynchronize(s), "synchronize");
     }
-    // consistency: enough neighbours within the radius with close levels
-    // (bins of the radius' size; the 3x3 bins around a point hold them all)
-    const int R = sp->incon_radius, bs = std::max(R, 1);
-    const int bx = W / bs + 1, by = H / bs + 1;
-    std::vector<std::vector<int>> bins((size_t)bx * by);
-    for (size_t i = 0; i < cand.size(); ++i) bins[(size_t)(cand[i].y / bs) * bx + cand[i].x / bs].push_back((int)i);
-    std::vector<int4> pts;
-    for (size_t i = 0; i < cand.size(); ++i) {
-        const int4 c = cand[i];
-        int cnt = 0;
-        for (int yy = c.y / bs - 1; yy <= c.y / bs + 1; ++yy)
-            for (int xx = c.x / bs - 1; xx <= c.x / bs + 1; ++xx) {
-                if (yy < 0 || yy >= by || xx < 0 || xx >= bx) continue;
-                for (int o : bins[(size_t)yy * bx + xx]) {
-                    if (o == (int)i) continue;
-                    const int4 d = cand[o];
-                    if (std::abs(d.x - c.x) <= R && std::abs(d.y - c.y) <= R && std::abs(d.z - c.z) <= sp->incon_levels)
-                        ++cnt;
-                }
-            }
-        if (cnt >= sp->incon_min) pts.push_back(c);
+    std::vector<int4> pts(n_pts0);
+    if (n_pts0 > 0) {
+        LF_HIP(hipMemcpyAsync(pts.data(), b_pts0.p, (size_t)n_pts0 * sizeof(int4), hipMemcpyDeviceToHost, s), "copy");
+        LF_HIP(hipStreamSynchronize(s), "synchronize");
     }
-    std::sort(pts.begin(), pts.end(), [](const int4 &a, const int4 &b) { return a.y != b.y ? a.y < b.y : a.x < b.x; });
     // the image corners at the level of the nearest point
     if (!pts.empty()) {
         const size_t n0 = pts.size();

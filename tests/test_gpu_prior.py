@@ -71,3 +71,66 @@ def test_prior_small_asymmetric():
     fr = S.make_frame(spec)
     _say("build prior 100x60 K=5 reference at the end of the array")
     _run(spec, fr, True)
+
+
+def _points_only(K, H, W, b, D, ref, views, S_P, **spkw):
+    """The GPU's points for a synthetic scene against the oracle's (support
+    points with the corners), exact."""
+    import torch
+    import paper_2003_11076_amd as LF
+    p = LF.make_params(K, H, W, ref, b, 0.0, 1.0, D, 100.0)
+    sp = LF.make_support_params(**spkw)
+    mu = np.zeros((H, W), np.float32)
+    cap = (W // 5 + 1) * (H // 5 + 1) * K + 8
+    pts, tris, n_p, n_t = LF.lf_build_prior(p, sp, views, S_P, mu, cap, 4 * cap + 16,
+                                            hip_stream=torch.cuda.current_stream().cuda_stream)
+    op = O.make_params(K, H, W, ref, [f32(v) for v in b], f32(0.0), f32(1.0), D, f32(100.0))
+    want = O.prior_corners(op, O.support_points(op, O.make_support_params(**spkw), views, S_P))
+    assert np.array_equal(pts, want)
+    return pts
+
+
+def test_prior_points_moved_onto_one_pixel():
+    """Every non-reference view's grid points land on the same reference
+    pixels (plane at a multiple of the grid step): one point per pixel, from
+    the lowest view, as the oracle."""
+    from test_oracle_pins import _plane_views
+    rng = np.random.default_rng(74)
+    K, H, W, D, d0 = 5, 40, 100, 16, 5
+    b = [-2.0, -1.0, 0.0, 1.0, 2.0]
+    views = _plane_views(K, H, W, b, d0, rng)
+    views[2, 10:30, 40:70] = rng.integers(0, 256, size=(20, 30, 3))
+    S_P = np.ones((K, H, W), np.float32)
+    S_P[2, 10:30, 40:70] = 0.0
+    _say("prior: moved points colliding on reference pixels, K=5 100x40")
+    pts = _points_only(K, H, W, b, D, 2, views, S_P)
+    assert (pts[:, 3] == 0).sum() > 20
+
+
+@pytest.mark.parametrize("incon_levels,incon_min", [(2, 8), (2, 12), (1, 8), (3, 12), (2, 0)])
+def test_prior_consistency_bounds(incon_levels, incon_min):
+    """Two planes exactly incon_levels apart and minimum counts around the
+    number of neighbours: the consistency filter's bounds, as the oracle."""
+    rng = np.random.default_rng(73)
+    K, H, W, D = 3, 40, 90, 16
+    b = [-1.0, 0.0, 1.0]
+    pad = 12
+    tex = rng.integers(0, 256, size=(H, W + 2 * pad, 3))
+    views = np.zeros((K, H, W, 3), np.uint8)
+    for k in range(K):
+        for x in range(W):
+            d = 4 if x < W // 2 else 6
+            views[k, :, x] = tex[:, pad + x + int(b[k]) * d]
+    ones = np.ones((K, H, W), np.float32)
+    _say(f"prior: consistency incon_levels={incon_levels} incon_min={incon_min}")
+    _points_only(K, H, W, b, D, 1, views, ones, incon_levels=incon_levels, incon_min=incon_min)
+
+
+def test_prior_wide_consistency_radius():
+    """A consistency radius of several grid rows (the device scans each row
+    in range by binary search)."""
+    fr = S.make_frame(S.workload_spec("small"))
+    spec = fr.spec
+    _say("prior: small_frame with incon_radius=23, incon_min=30")
+    _points_only(spec.K, spec.H, spec.W, list(spec.baselines), spec.D, spec.ref, fr.views, fr.S_P,
+                 incon_radius=23, incon_min=30)
