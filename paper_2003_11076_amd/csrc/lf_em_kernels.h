@@ -371,6 +371,7 @@ struct Lane {
     float mu;      // prior disparity
     float L;       // objective after the last E-step
     int best_j;    // level of the last M-step (seed of the next sweep)
+    int c;         // level nearest mu (constant over the iterations)
     int idx0[K];   // level-0 LDS record index of each view (integer shifts)
 };
 
@@ -846,7 +847,7 @@ __device__ __forceinline__ int shared_iteration(const typename Rec<ST>::T *win, 
     // bounded windows: the wave's widest extents below and above each lane's
     // nearest level c to mu, so that neighbouring lanes (whose c mostly
     // agree) read neighbouring LDS records
-    const int c = nearest_level(a, s.mu);
+    const int c = s.c;
     const int el = __builtin_amdgcn_readfirstlane(wave_max(bnd ? max(c - jl, 0) : 0));
     const int er = __builtin_amdgcn_readfirstlane(wave_max(bnd ? max(jh - c, 0) : 0));
     const int wl = el + er + 1;
@@ -889,6 +890,7 @@ __device__ __forceinline__ int shared_iteration(const typename Rec<ST>::T *win, 
 #pragma unroll
             for (int k = 0; k < K; ++k) hwt[k] = __shfl(wt[k], src, 64);
             const float hinvW = __shfl(invW, src, 64), hcw = __shfl(cw, src, 64), hmu = __shfl(s.mu, src, 64);
+            const int hc = __shfl(s.c, src, 64);
             float hE = __shfl(best_E, src, 64);
             int hj = __shfl(best_j, src, 64);
             // every shuffle runs on the whole wave: a lane shuffle reads
@@ -901,7 +903,7 @@ __device__ __forceinline__ int shared_iteration(const typename Rec<ST>::T *win, 
             const int jb = min((lane / U) * chunk, a.D - chunk);
             // upper bound of the prior over the chunk: its value at the
             // chunk's level nearest mu, plus the evaluation's error
-            const int jn = min(max(nearest_level(a, hmu), jb), jb + chunk - 1);
+            const int jn = min(max(hc, jb), jb + chunk - 1);
             const float pn = log_prior(a, jn, hmu);
             const float phi = pn + 1e-5f * (1.0f + fabsf(pn));
             int ib[K];
@@ -995,11 +997,13 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
     s.mu = 0.0f;
     s.L = 0.0f;
     s.best_j = 0;
+    s.c = 0;
     s.f0 = make_float2(0.0f, 0.0f);
     s.n0 = 0.0f;
     bool work = active;   // pixel reconstructed (all of them unless dynamic-only)
     if (active) {
         s.mu = a.mu_T[pix];
+        s.c = nearest_level(a, s.mu);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const size_t i = (size_t)a.perm[k] * HW + pix;
@@ -1008,7 +1012,7 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
             s.la[k] = (r > 0.0f ? logf(r) : -INFINITY) + a.lambda;   // ln rho + lambda
             s.lb[k] = (om > 0.0f ? logf(om) : -INFINITY);            // ln(1 - rho)
         }
-        s.best_j = (a.seed_from_d && work) ? a.d_idx[pix] : nearest_level(a, s.mu);
+        s.best_j = (a.seed_from_d && work) ? a.d_idx[pix] : s.c;
 #pragma unroll
         for (int k = 0; k < K; ++k) s.idx0[k] = FRAC ? 0 : lane_index0(w[k], a.bi[k], a.dmin_i, x);
         fetch<K, RS, FRAC>(win, w[0], a, 0, x, 0, s.idx0[0], s.f0, s.n0);

@@ -100,6 +100,7 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
     s.mu = 0.0f;
     s.L = 0.0f;
     s.best_j = 0;
+    s.c = 0;
     s.f0 = make_float2(0.0f, 0.0f);
     s.n0 = 0.0f;
     bool work = active;   // pixel reconstructed (all of them unless dynamic-only)
@@ -121,7 +122,8 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
             }
         }
         if (nbad) atomicAdd(job.bad, nbad);
-        s.best_j = nearest_level(a, s.mu);
+        s.c = nearest_level(a, s.mu);
+        s.best_j = s.c;
 #pragma unroll
         for (int k = 0; k < K; ++k) s.idx0[k] = FRAC ? 0 : lane_index0(w[k], a.bi[k], a.dmin_i, x);
         fetch<K, ST, FRAC>(win, w[0], a, 0, x, 0, s.idx0[0], s.f0, s.n0);
