@@ -18,11 +18,27 @@
 
 namespace lfem {
 
-// Row-tile width (the block size) per view count: 128 pixels up to six
-// views, 256 above, where the wider disparity halo of a 128-pixel tile's
-// windows would hold the LDS of a CU to fewer waves than the registers allow.
-__host__ __device__ constexpr int serve_tile_width(int K) { return K <= 6 ? 128 : 256; }
-constexpr int kServeTileMax = 256;
+// Row-tile width (the block size): 128 pixels, two waves.  Blocks of four
+// waves (256 pixels) hold their LDS until their slowest wave ends, which
+// measured a fifth slower with nine views.
+__host__ __device__ constexpr int serve_tile_width(int K) { return (void)K, 128; }
+constexpr int kServeTileMax = 128;
+// A view's R+G+B rows are staged inside its own record window, and its
+// records held in registers (this many per lane) until every lane has read
+// the rows, for windows up to kServeHold tiles wide; wider ones stage the
+// rows in a scratch area after the records.
+constexpr int kServeHold = 8;
+
+// LDS record of a descriptor pair of storage ST as the serve kernel stages it:
+// FP32 pairs as int16 Sobel responses (exact), the others as stored; the plain
+// context's binary16 and int16 records of FP32 pairs decode to the same values.
+template <int ST> constexpr int serve_rec_format() { return ST == 0 ? 3 : ST; }
+
+template <int ST>
+__device__ __forceinline__ typename Rec<serve_rec_format<ST>()>::T serve_rec(int gx, int gy) {
+    const float sc = 1.0f / 4096.0f;  // exact: |G| <= 3060
+    return stage_rec<serve_rec_format<ST>(), ST>(make_pair<ST>((float)gx * sc, (float)gy * sc));
+}
 constexpr int kServeMaxViews = 9;
 
 // Sweep kinds of the serve kernel instances (one launch per kind):
@@ -48,7 +64,8 @@ template <int K, int ST, int KIND>
 __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsigned char *lds) {
     constexpr bool FRAC = KIND == kServeFrac;
     constexpr bool SYM = KIND == kServeSharedSym;
-    using R = typename Rec<ST>::T;
+    constexpr int RS = serve_rec_format<ST>();
+    using R = typename Rec<RS>::T;
     const EmArgs &a = job.em;
     const int tid = threadIdx.x;
     const int y = tile / job.tiles_x;
@@ -64,17 +81,21 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
     int total;
     view_windows<K, FRAC>(a, x0, TILE, w, total);
     R *win = reinterpret_cast<R *>(lds);
-    // intensity rows of one view at a time, after the records
-    int16_t *lsum = reinterpret_cast<int16_t *>(lds + (size_t)total * sizeof(R));
+    // rows of windows too wide to stage in place: after the records
+    int16_t *scratch_rows = reinterpret_cast<int16_t *>(lds + (size_t)total * sizeof(R));
 
     // descriptor records of every window position (replicated border), view
     // by view: rows y-1, y, y+1 of R+G+B over the window's columns (+1
-    // border), then the 3x3 Sobel responses
+    // border), then the 3x3 Sobel responses.  The rows take 6 (len + 2)
+    // bytes, the window's records 8 len (len >= the tile width), so a
+    // window holds its own rows while its records wait in registers.
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int ulo = clampi(w[k].umin, 0, W - 1), uhi = clampi(w[k].umin + w[k].len - 1, 0, W - 1);
         const int c0 = max(ulo - 1, 0);
         const int nc = min(uhi + 1, W - 1) - c0 + 1;
+        const bool in_place = w[k].len <= kServeHold * TILE;   // uniform
+        int16_t *lsum = in_place ? reinterpret_cast<int16_t *>(win + w[k].off) : scratch_rows;
         const uint8_t *v = job.views + (size_t)a.perm[k] * HW * 3;
         for (int i = tid; i < 3 * nc; i += TILE) {
             const int r = i / nc, c = c0 + (i - r * nc);
@@ -84,13 +105,28 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
         }
         __syncthreads();
         const int16_t *L0 = lsum, *L1 = L0 + nc, *L2 = L1 + nc;
-        for (int p = tid; p < w[k].len; p += TILE) {
+        auto record = [&](int p) {
             const int uc = clampi(w[k].umin + p, 0, W - 1);
             const int cl = max(uc - 1, 0) - c0, cm = uc - c0, cr = min(uc + 1, W - 1) - c0;
             const int gx = (L0[cr] - L0[cl]) + 2 * (L1[cr] - L1[cl]) + (L2[cr] - L2[cl]);
             const int gy = (L2[cl] - L0[cl]) + 2 * (L2[cm] - L0[cm]) + (L2[cr] - L0[cr]);
-            const float sc = 1.0f / 4096.0f;
-            win[win_index(w[k], p)] = make_rec<ST>(make_pair<ST>((float)gx * sc, (float)gy * sc));
+            return serve_rec<ST>(gx, gy);
+        };
+        if (in_place) {
+            R hold[kServeHold];
+#pragma unroll
+            for (int i = 0; i < kServeHold; ++i) {
+                const int p = tid + i * TILE;
+                if (p < w[k].len) hold[i] = record(p);
+            }
+            __syncthreads();   // every lane has read the rows before they are overwritten
+#pragma unroll
+            for (int i = 0; i < kServeHold; ++i) {
+                const int p = tid + i * TILE;
+                if (p < w[k].len) win[win_index(w[k], p)] = hold[i];
+            }
+        } else {
+            for (int p = tid; p < w[k].len; p += TILE) win[win_index(w[k], p)] = record(p);
         }
         __syncthreads();
     }
@@ -126,7 +162,7 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
         s.best_j = s.c;
 #pragma unroll
         for (int k = 0; k < K; ++k) s.idx0[k] = FRAC ? 0 : lane_index0(w[k], a.bi[k], a.dmin_i, x);
-        fetch<K, ST, FRAC>(win, w[0], a, 0, x, 0, s.idx0[0], s.f0, s.n0);
+        fetch<K, RS, FRAC>(win, w[0], a, 0, x, 0, s.idx0[0], s.f0, s.n0);
     } else {
 #pragma unroll
         for (int k = 0; k < K; ++k) s.q[k] = s.la[k] = s.lb[k] = 0.0f;
@@ -139,9 +175,9 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
     search_range(a, work, s.mu, slo, shi);
     for (int it = 0; it < a.n_iters; ++it) {
         if constexpr (KIND == kServeSharedSym || KIND == kServeShared) {
-            (void)shared_iteration<K, ST, SYM>(win, w, a, x, x0, work, jlo, jhi, slo, shi, Pc, s, false);
+            (void)shared_iteration<K, RS, SYM>(win, w, a, x, x0, work, jlo, jhi, slo, shi, Pc, s, false);
         } else {
-            if (work) em_iteration<K, ST, FRAC, false, false>(win, w, a, x, jlo, jhi, slo, shi, Pc, s, false);
+            if (work) em_iteration<K, RS, FRAC, false, false>(win, w, a, x, jlo, jhi, slo, shi, Pc, s, false);
         }
     }
 

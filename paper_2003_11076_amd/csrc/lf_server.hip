@@ -183,9 +183,13 @@ namespace {
 // int16 rows of intensity sums of one window at a time (+1 column of border
 // on each side).
 size_t frame_lds(const lf_params &p, const Geometry &g) {
-    const size_t pairs = em_window_pairs(&p, g, serve_tile_width(p.K));
-    const size_t widest = em_window_widest(&p, g, serve_tile_width(p.K));
-    return pairs * (size_t)(p.storage == LF_F32 ? 16 : 8) + 2 * 3 * (widest + 2) + 64;
+    const int tile = serve_tile_width(p.K);
+    const size_t pairs = em_window_pairs(&p, g, tile);
+    const size_t widest = em_window_widest(&p, g, tile);
+    // 8-byte records; the R+G+B rows of windows wider than kServeHold tiles
+    // go to a scratch area after them, the others are staged in place
+    const size_t rows = widest > (size_t)kServeHold * tile ? 2 * 3 * (widest + 2) : 0;
+    return pairs * 8 + rows + 64;
 }
 
 int frame_kind(const lf_params &p, const Geometry &g) {
