@@ -342,10 +342,13 @@ typedef struct {
  * parameters, frames above 16384), LF_ENOMEM, LF_EDEVICE.
  */
 /*
- * lf_triangulate -- the Delaunay triangulation lf_build_prior uses, on the
- * host: incremental insertion in the given order with exact integer
- * predicates (a point on a circumcircle does not count as inside; points
- * already present are skipped).
+ * lf_triangulate -- a Delaunay triangulation of any point set on the host:
+ * incremental insertion along a Hilbert curve with exact integer predicates
+ * (a point on a circumcircle does not count as inside; points already
+ * present are skipped).  lf_build_prior triangulates its points on the
+ * device (row strips and side pockets, then rounds of edge flips) and uses
+ * this one only if the flip rounds do not settle; where points are
+ * cocircular the two may pick different valid triangulations.
  *   xy     : int32 [n][2] points, coordinates in [0, 16383].
  *   tris   : int32 [max_tris][3] counter-clockwise indices or NULL;
  *            n_tris (nullable) receives the count.

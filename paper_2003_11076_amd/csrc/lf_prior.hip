@@ -8,10 +8,13 @@
 // Device: integer Sobel responses, the matching of every grid point of every
 // pass (one lane per point, all levels), the transfer of the other views'
 // points with one point per reference pixel, the consistency filter, the
-// ordering of the points by (y, u), and the raster of the triangulation.
-// Host (native C++): the four corners and the triangulation (incremental
-// Delaunay with exact integer predicates).
+// ordering of the points by (y, u), the Delaunay triangulation (row strips
+// and side pockets, then rounds of parallel edge flips) and its raster.
+// Host (native C++): the four corners (nearest point of each), the rows'
+// bounds, and the incremental Delaunay triangulation behind lf_triangulate
+// (also the fallback should the flip rounds not settle).
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <climits>
@@ -19,6 +22,7 @@
 #include <cstring>
 #include <vector>
 
+#include "lf_delaunay.h"
 #include "lf_em.h"
 #include "lf_internal.h"
 
@@ -31,6 +35,12 @@ namespace lfem {
     } while (0)
 
 __device__ __forceinline__ int pclamp(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+// Flip rounds of the device triangulation before the host takes over (every
+// round flips at least one edge; the scenes here settle in 5 to 25).
+constexpr int kMaxFlipRounds = 4096;
+// Flip rounds queued between two reads of the illegal-edge count.
+constexpr int kRoundsPerCheck = 8;
 
 // Integer Sobel responses (Gx, Gy) of L = R+G+B, replicated border.
 // grid (ceil(W/256), H, K); g is [K][H][W].
@@ -311,6 +321,151 @@ __global__ __launch_bounds__(256) void lf_consistency_kernel(const int4 *__restr
             cnt += k != i && abs(cand[k].z - c.z) <= L;
     }
     if (cnt >= n_min) kept[(size_t)iy * W + c.x] = c.z;
+}
+
+// ---------------------------------------------------------------------------
+// Delaunay triangulation on the device (see lf_delaunay.h).  Points P in
+// their output order; `order` lists them by (y, x) and row_start bounds the
+// rows in it.
+// ---------------------------------------------------------------------------
+
+// One lane per strip between rows s and s + 1; the strips' triangles are
+// stored in row order: strip s starts at sum over s' < s of
+// (n_s' + n_s'+1 - 2) = row_start[s] + row_start[s+1] - row_start[1] - 2 s.
+__global__ __launch_bounds__(64) void lf_dt_strips_kernel(const dt::Pt *__restrict__ P, const int *__restrict__ order,
+                                                          const int *__restrict__ row_start, int n_rows,
+                                                          int3 *__restrict__ tris) {
+    const int st = blockIdx.x * blockDim.x + threadIdx.x;
+    if (st >= n_rows - 1) return;
+    int k = row_start[st] + row_start[st + 1] - row_start[1] - 2 * st;
+    dt::zip_strip(P, order + row_start[st], row_start[st + 1] - row_start[st], order + row_start[st + 1],
+                  row_start[st + 2] - row_start[st + 1], [&](int a, int b, int c) { tris[k++] = make_int3(a, b, c); });
+}
+
+// One lane: the left and the right side pocket after the strips (from
+// `base`), at most `cap` triangles in all; the count goes to *n_out.  `work`
+// holds 4 n_rows ints.
+__global__ __launch_bounds__(64) void lf_dt_pockets_kernel(const dt::Pt *__restrict__ P, const int *__restrict__ order,
+                                                           const int *__restrict__ row_start, int n_rows, int W,
+                                                           int *__restrict__ work, int3 *__restrict__ tris, int base,
+                                                           int cap, int *__restrict__ n_out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int k = base;
+    int *C = work;
+    auto emit = [&](int a, int b, int c) {
+        if (k < cap) tris[k] = make_int3(a, b, c);
+        ++k;
+    };
+    for (int r = 0; r < n_rows; ++r) C[r] = order[row_start[r]];
+    dt::side_pocket(P, C, n_rows, 0, -1, work + n_rows, emit);
+    for (int r = 0; r < n_rows; ++r) C[r] = order[row_start[r + 1] - 1];
+    dt::side_pocket(P, C, n_rows, W - 1, 1, work + n_rows, emit);
+    *n_out = k;
+}
+
+// Flip rounds.  Edge e of triangle t (the edge opposite its vertex e) has the
+// key min * n + max of its end points and the value 3 t + e; after sorting by
+// key the two sides of an interior edge are neighbours.
+__device__ __forceinline__ int tri_vertex(const int3 &v, int e) { return e == 0 ? v.x : (e == 1 ? v.y : v.z); }
+
+__global__ __launch_bounds__(256) void lf_dt_edges_kernel(const int3 *__restrict__ tris, int T, int n,
+                                                          unsigned long long *__restrict__ keys,
+                                                          int *__restrict__ vals) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * T) return;
+    const int3 v = tris[i / 3];
+    const int e = i % 3;
+    const int a = tri_vertex(v, (e + 1) % 3), b = tri_vertex(v, (e + 2) % 3);
+    keys[i] = (unsigned long long)min(a, b) * (unsigned long long)n + (unsigned long long)max(a, b);
+    vals[i] = i;
+}
+
+// Neighbour links: after sorting the edges by key, the two sides of an
+// interior edge are neighbours; nb[3 t + e] = 3 u + f links edge e of t
+// with edge f of u (-1: an edge of the hull).
+__global__ __launch_bounds__(256) void lf_dt_links_kernel(const unsigned long long *__restrict__ keys,
+                                                          const int *__restrict__ vals, int m,
+                                                          int *__restrict__ nb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m - 1 || keys[i] != keys[i + 1]) return;
+    nb[vals[i]] = vals[i + 1];
+    nb[vals[i + 1]] = vals[i];
+}
+
+// The triangles a flip of edge te rewrites: its two triangles and their four
+// outer neighbours (-1 where the outer edge is on the hull).
+__device__ __forceinline__ void flip_parts(const int *nb, int te, int other, int (&tri)[6]) {
+    const int t = te / 3, e = te % 3, u = other / 3, f = other % 3;
+    tri[0] = t;
+    tri[1] = u;
+    const int o[4] = {nb[3 * t + (e + 1) % 3], nb[3 * t + (e + 2) % 3], nb[3 * u + (f + 1) % 3],
+                      nb[3 * u + (f + 2) % 3]};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tri[2 + k] = o[k] < 0 ? -1 : o[k] / 3;
+}
+
+// One round, part 1 (one lane per edge slot, each interior edge taken from
+// its lower slot): an edge whose opposite vertex across it lies strictly
+// inside its triangle's circumcircle is illegal; it claims, by an atomic
+// minimum of its slot, the six triangles its flip rewrites.  The lowest
+// illegal edge wins all of its claims, so every round flips at least one
+// edge, and the flips that win theirs touch disjoint triangles.
+__global__ __launch_bounds__(256) void lf_dt_mark_kernel(const int3 *__restrict__ tris, const dt::Pt *__restrict__ P,
+                                                         const int *__restrict__ nb, int m,
+                                                         int *__restrict__ claim, uint8_t *__restrict__ flag,
+                                                         int *__restrict__ count) {
+    const int te = blockIdx.x * blockDim.x + threadIdx.x;
+    if (te >= m) return;
+    flag[te] = 0;
+    const int other = nb[te];
+    if (other < te) return;   // a hull edge (-1), or taken from the other side
+    const int t = te / 3, u = other / 3, f = other % 3;
+    const int3 vt = tris[t];
+    const int d = tri_vertex(tris[u], f);
+    if (dt::incircle(P[vt.x], P[vt.y], P[vt.z], P[d]) <= 0) return;
+    flag[te] = 1;
+    atomicAdd(count, 1);
+    int tri[6];
+    flip_parts(nb, te, other, tri);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        if (tri[k] >= 0) atomicMin(&claim[tri[k]], te);
+}
+
+// Part 2: the edges that won all their claims flip.  Edge (b, c) of
+// t = (a, b, c) and u = (d, c, b) becomes (a, d): t = (a, b, d) and
+// u = (a, d, c), both with positive orientation (an illegal edge's
+// quadrilateral is convex), and the links of the six triangles follow.
+__global__ __launch_bounds__(256) void lf_dt_flip_kernel(int3 *__restrict__ tris, int *__restrict__ nb,
+                                                         const uint8_t *__restrict__ flag,
+                                                         const int *__restrict__ claim, int m) {
+    const int te = blockIdx.x * blockDim.x + threadIdx.x;
+    if (te >= m || !flag[te]) return;
+    const int other = nb[te];
+    int tri[6];
+    flip_parts(nb, te, other, tri);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        if (tri[k] >= 0 && claim[tri[k]] != te) return;
+    const int t = te / 3, e = te % 3, u = other / 3, f = other % 3;
+    const int3 vt = tris[t];
+    const int a = tri_vertex(vt, e), b = tri_vertex(vt, (e + 1) % 3), c = tri_vertex(vt, (e + 2) % 3);
+    const int d = tri_vertex(tris[u], f);
+    // outer neighbours: across (c, a) and (a, b) of t, (b, d) and (d, c) of u
+    const int n_ca = nb[3 * t + (e + 1) % 3], n_ab = nb[3 * t + (e + 2) % 3];
+    const int n_bd = nb[3 * u + (f + 1) % 3], n_dc = nb[3 * u + (f + 2) % 3];
+    tris[t] = make_int3(a, b, d);   // edges: 0 (b, d), 1 (d, a), 2 (a, b)
+    tris[u] = make_int3(a, d, c);   // edges: 0 (d, c), 1 (c, a), 2 (a, d)
+    nb[3 * t + 0] = n_bd;
+    nb[3 * t + 1] = 3 * u + 2;
+    nb[3 * t + 2] = n_ab;
+    nb[3 * u + 0] = n_dc;
+    nb[3 * u + 1] = n_ca;
+    nb[3 * u + 2] = 3 * t + 1;
+    if (n_bd >= 0) nb[n_bd] = 3 * t + 0;
+    if (n_ab >= 0) nb[n_ab] = 3 * t + 2;
+    if (n_dc >= 0) nb[n_dc] = 3 * u + 0;
+    if (n_ca >= 0) nb[n_ca] = 3 * u + 1;
 }
 
 // Raster of the triangulation: the lowest-index triangle containing each
@@ -799,29 +954,140 @@ extern "C" lf_status lf_build_prior(const lf_params *p, const lf_support_params 
             pts.push_back(make_int4(cx[c], cy[c], lv, -1));
         }
     }
-    // triangulation
-    std::vector<P2> pp(pts.size());
-    for (size_t i = 0; i < pts.size(); ++i) pp[i] = {pts[i].x, pts[i].y};
-    Delaunay dt;
-    dt.run(pp);
-    const std::vector<int> tv = dt.triangles();
-    const int n_tri = (int)(tv.size() / 3);
+    // triangulation on the device: rows of the points by (y, x) (the sorted
+    // points with the corners merged in), strips and side pockets, then flip
+    // rounds until no edge is illegal
+    const int n_pts = (int)pts.size();
+    DevBuf b_pts, b_tri, b_owner, b_mu;
+    LF_HIP(hipMalloc(&b_pts.p, std::max(n_pts, 1) * sizeof(int4)), "allocation");
+    if (n_pts) LF_HIP(hipMemcpyAsync(b_pts.p, pts.data(), n_pts * sizeof(int4), hipMemcpyHostToDevice, s), "copy");
+    std::vector<int> tv;   // triangles for the caller (host)
+    int n_tri = 0;
+    bool on_device = false;
+    if (n_pts >= 3 && W >= 2 && H >= 2) {
+        std::vector<int> order(n_pts);
+        auto by_yx = [&](int i, int j) { return pts[i].y != pts[j].y ? pts[i].y < pts[j].y : pts[i].x < pts[j].x; };
+        {
+            std::vector<int> real(n_pts0), corner(n_pts - n_pts0);
+            for (int i = 0; i < n_pts0; ++i) real[i] = i;
+            for (int i = n_pts0; i < n_pts; ++i) corner[i - n_pts0] = i;
+            std::merge(real.begin(), real.end(), corner.begin(), corner.end(), order.begin(), by_yx);
+        }
+        std::vector<int> row_start;
+        for (int i = 0; i < n_pts; ++i)
+            if (i == 0 || pts[order[i]].y != pts[order[i - 1]].y) row_start.push_back(i);
+        row_start.push_back(n_pts);
+        const int n_rows = (int)row_start.size() - 1;
+        // Euler: 2 n - h - 2 triangles, h the points on the frame's border
+        int h = 0;
+        for (const int4 &q : pts) h += q.x == 0 || q.x == W - 1 || q.y == 0 || q.y == H - 1;
+        const int T = 2 * n_pts - h - 2;
+        const int base = row_start[n_rows - 1] + row_start[n_rows] - row_start[1] - 2 * (n_rows - 1);
+        const int cap_tri = std::max(T, base);   // the strips' count never exceeds T; room for them regardless
+        std::vector<dt::Pt> P(n_pts);
+        for (int i = 0; i < n_pts; ++i) P[i] = {pts[i].x, pts[i].y};
+        const size_t m = (size_t)3 * T;
+        DevBuf b_P, b_order, b_rows, b_work, b_keys, b_keys2, b_vals, b_vals2, b_claim, b_flag, b_cnt, b_temp, b_nb;
+        LF_HIP(hipMalloc(&b_P.p, n_pts * sizeof(dt::Pt)), "allocation");
+        LF_HIP(hipMalloc(&b_order.p, n_pts * 4), "allocation");
+        LF_HIP(hipMalloc(&b_rows.p, (n_rows + 1) * 4), "allocation");
+        LF_HIP(hipMalloc(&b_work.p, (size_t)4 * n_rows * 4), "allocation");
+        LF_HIP(hipMalloc(&b_tri.p, std::max(cap_tri, 1) * sizeof(int3)), "allocation");
+        LF_HIP(hipMalloc(&b_keys.p, m * 8), "allocation");
+        LF_HIP(hipMalloc(&b_keys2.p, m * 8), "allocation");
+        LF_HIP(hipMalloc(&b_vals.p, m * 4), "allocation");
+        LF_HIP(hipMalloc(&b_vals2.p, m * 4), "allocation");
+        LF_HIP(hipMalloc(&b_claim.p, std::max(T, 1) * 4), "allocation");
+        LF_HIP(hipMalloc(&b_flag.p, m), "allocation");
+        LF_HIP(hipMalloc(&b_cnt.p, 16), "allocation");
+        LF_HIP(hipMemcpyAsync(b_P.p, P.data(), n_pts * sizeof(dt::Pt), hipMemcpyHostToDevice, s), "copy");
+        LF_HIP(hipMemcpyAsync(b_order.p, order.data(), n_pts * 4, hipMemcpyHostToDevice, s), "copy");
+        LF_HIP(hipMemcpyAsync(b_rows.p, row_start.data(), (n_rows + 1) * 4, hipMemcpyHostToDevice, s), "copy");
+        const dt::Pt *dP = (const dt::Pt *)b_P.p;
+        int3 *dtri = (int3 *)b_tri.p;
+        int *cnt = (int *)b_cnt.p;
+        if (n_rows > 1)
+            hipLaunchKernelGGL(lf_dt_strips_kernel, dim3((n_rows - 1 + 63) / 64), dim3(64), 0, s, dP,
+                               (const int *)b_order.p, (const int *)b_rows.p, n_rows, dtri);
+        hipLaunchKernelGGL(lf_dt_pockets_kernel, dim3(1), dim3(64), 0, s, dP, (const int *)b_order.p,
+                           (const int *)b_rows.p, n_rows, W, (int *)b_work.p, dtri, base, cap_tri, cnt + 1);
+        LF_HIP(hipGetLastError(), "triangulation launch");
+        int built = -1;
+        LF_HIP(hipMemcpyAsync(&built, cnt + 1, 4, hipMemcpyDeviceToHost, s), "copy");
+        LF_HIP(hipStreamSynchronize(s), "synchronize");
+        if (built == T && T > 0) {
+            // keys below n^2
+            int end_bit = 1;
+            while (end_bit < 64 && ((unsigned long long)n_pts * (unsigned long long)n_pts >> end_bit) != 0) ++end_bit;
+            size_t temp_bytes = 0;
+            unsigned long long *k0 = (unsigned long long *)b_keys.p, *k1 = (unsigned long long *)b_keys2.p;
+            int *v0 = (int *)b_vals.p, *v1 = (int *)b_vals2.p;
+            LF_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, k0, k1, v0, v1, (int)m, 0, end_bit, s),
+                   "sort size");
+            LF_HIP(hipMalloc(&b_temp.p, std::max<size_t>(temp_bytes, 1)), "allocation");
+            const unsigned eb = (unsigned)((m + 255) / 256);
+            // links, once: the edges sorted by key
+            LF_HIP(hipMalloc(&b_nb.p, m * 4), "allocation");
+            hipLaunchKernelGGL(lf_dt_edges_kernel, dim3(eb), dim3(256), 0, s, (const int3 *)dtri, T, n_pts, k0, v0);
+            LF_HIP(hipGetLastError(), "edge launch");
+            LF_HIP(hipcub::DeviceRadixSort::SortPairs(b_temp.p, temp_bytes, k0, k1, v0, v1, (int)m, 0, end_bit, s),
+                   "edge sort");
+            hipLaunchKernelGGL(lf_prior_fill_kernel, dim3(eb), dim3(256), 0, s, (int32_t *)b_nb.p, m, -1);
+            hipLaunchKernelGGL(lf_dt_links_kernel, dim3(eb), dim3(256), 0, s, (const unsigned long long *)k1,
+                               (const int *)v1, (int)m, (int *)b_nb.p);
+            LF_HIP(hipGetLastError(), "link launch");
+            // rounds of independent flips, the count of illegal edges read
+            // every kRoundsPerCheck rounds (rounds after the last flip find
+            // nothing to do)
+            const unsigned tb = (unsigned)((T + 255) / 256);
+            for (int round = 0; round < kMaxFlipRounds && !on_device; round += kRoundsPerCheck) {
+                for (int r = 0; r < kRoundsPerCheck; ++r) {
+                    hipLaunchKernelGGL(lf_prior_fill_kernel, dim3(tb), dim3(256), 0, s, (int32_t *)b_claim.p,
+                                       (size_t)T, INT_MAX);
+                    hipLaunchKernelGGL(lf_prior_fill_kernel, dim3(1), dim3(256), 0, s, (int32_t *)cnt, (size_t)1, 0);
+                    hipLaunchKernelGGL(lf_dt_mark_kernel, dim3(eb), dim3(256), 0, s, (const int3 *)dtri, dP,
+                                       (const int *)b_nb.p, (int)m, (int *)b_claim.p, (uint8_t *)b_flag.p, cnt);
+                    hipLaunchKernelGGL(lf_dt_flip_kernel, dim3(eb), dim3(256), 0, s, dtri, (int *)b_nb.p,
+                                       (const uint8_t *)b_flag.p, (const int *)b_claim.p, (int)m);
+                }
+                LF_HIP(hipGetLastError(), "flip launch");
+                int illegal = -1;
+                LF_HIP(hipMemcpyAsync(&illegal, cnt, 4, hipMemcpyDeviceToHost, s), "copy");
+                LF_HIP(hipStreamSynchronize(s), "synchronize");
+                on_device = illegal == 0;
+            }
+        }
+        if (on_device) {
+            n_tri = T;
+            tv.resize((size_t)3 * T);
+            LF_HIP(hipMemcpyAsync(tv.data(), dtri, (size_t)T * sizeof(int3), hipMemcpyDeviceToHost, s), "copy");
+            LF_HIP(hipStreamSynchronize(s), "synchronize");   // before the buffers of this block are freed
+        }
+    }
+    if (!on_device) {
+        // the host triangulation (no points, a degenerate frame, or flip
+        // rounds that did not settle within kMaxFlipRounds)
+        std::vector<P2> pp(pts.size());
+        for (size_t i = 0; i < pts.size(); ++i) pp[i] = {pts[i].x, pts[i].y};
+        Delaunay dtr;
+        dtr.run(pp);
+        tv = dtr.triangles();
+        n_tri = (int)(tv.size() / 3);
+        if (b_tri.p) {
+            (void)hipFree(b_tri.p);
+            b_tri.p = nullptr;
+        }
+        LF_HIP(hipMalloc(&b_tri.p, std::max(n_tri, 1) * sizeof(int3)), "allocation");
+        if (n_tri) LF_HIP(hipMemcpyAsync(b_tri.p, tv.data(), n_tri * sizeof(int3), hipMemcpyHostToDevice, s), "copy");
+    }
 
     // raster on the device
-    DevBuf b_pts, b_tri, b_owner, b_mu;
-    const int n_pts = (int)pts.size();
-    LF_HIP(hipMalloc(&b_pts.p, std::max(n_pts, 1) * sizeof(int4)), "allocation");
-    LF_HIP(hipMalloc(&b_tri.p, std::max(n_tri, 1) * sizeof(int3)), "allocation");
     LF_HIP(hipMalloc(&b_owner.p, HW * 4), "allocation");
     float *d_mu = mu_T;
     if (!dev_out) {
         LF_HIP(hipMalloc(&b_mu.p, HW * 4), "allocation");
         d_mu = (float *)b_mu.p;
     }
-    std::vector<int3> t3(n_tri);
-    for (int t = 0; t < n_tri; ++t) t3[t] = make_int3(tv[3 * t], tv[3 * t + 1], tv[3 * t + 2]);
-    if (n_pts) LF_HIP(hipMemcpyAsync(b_pts.p, pts.data(), n_pts * sizeof(int4), hipMemcpyHostToDevice, s), "copy");
-    if (n_tri) LF_HIP(hipMemcpyAsync(b_tri.p, t3.data(), n_tri * sizeof(int3), hipMemcpyHostToDevice, s), "copy");
     hipLaunchKernelGGL(lf_prior_fill_kernel, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s, (int32_t *)b_owner.p,
                        HW, INT_MAX);
     LF_HIP(hipGetLastError(), "fill launch");
