@@ -23,10 +23,11 @@ namespace lfem {
 // measured a fifth slower with nine views.
 __host__ __device__ constexpr int serve_tile_width(int K) { return (void)K, 128; }
 constexpr int kServeTileMax = 128;
-// A view's R+G+B rows are staged inside its own record window, and its
-// records held in registers (this many per lane) until every lane has read
-// the rows, for windows up to kServeHold tiles wide; wider ones stage the
-// rows in a scratch area after the records.
+// Where a frame's LDS would otherwise limit the blocks a CU holds, a view's
+// R+G+B rows are staged inside its own record window, and its records held
+// in registers (this many per lane) until every lane has read the rows, for
+// windows up to kServeHold tiles wide; other windows, and frames with LDS to
+// spare, stage the rows in a scratch area after the records.
 constexpr int kServeHold = 8;
 
 // LDS record of a descriptor pair of storage ST as the serve kernel stages it:
@@ -57,6 +58,7 @@ struct ServeJob {
     int warm;                // em.q holds the stream's previous weights (the first weights)
     int check;               // count S_P outside [0,1] and mu_T not finite into *bad
     int ref, tiles_x, tile_start, n_tiles;
+    int rows_in_place;       // stage each view's R+G+B rows inside its record window (else after the records)
     float tau;
 };
 
@@ -94,7 +96,7 @@ __device__ __forceinline__ void serve_tile(const ServeJob &job, int tile, unsign
         const int ulo = clampi(w[k].umin, 0, W - 1), uhi = clampi(w[k].umin + w[k].len - 1, 0, W - 1);
         const int c0 = max(ulo - 1, 0);
         const int nc = min(uhi + 1, W - 1) - c0 + 1;
-        const bool in_place = w[k].len <= kServeHold * TILE;   // uniform
+        const bool in_place = job.rows_in_place && w[k].len <= kServeHold * TILE;   // uniform
         int16_t *lsum = in_place ? reinterpret_cast<int16_t *>(win + w[k].off) : scratch_rows;
         const uint8_t *v = job.views + (size_t)a.perm[k] * HW * 3;
         for (int i = tid; i < 3 * nc; i += TILE) {

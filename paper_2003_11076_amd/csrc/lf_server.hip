@@ -121,6 +121,7 @@ struct SrvFrame {
     bool warm = false;
     int tiles_x = 0, n_tiles = 0;
     size_t lds = 0;
+    int rows_in_place = 0;   // R+G+B rows staged inside the record windows
     Clock::time_point t_submit, t_done;
     lf_status status = LF_OK;
 };
@@ -182,14 +183,24 @@ namespace {
 // LDS of a tile: the descriptor records of every view's window, then three
 // int16 rows of intensity sums of one window at a time (+1 column of border
 // on each side).
-size_t frame_lds(const lf_params &p, const Geometry &g) {
+// LDS of a frame's blocks (8-byte records), and whether its R+G+B rows are
+// staged in place: only when the scratch area after the records would leave
+// a CU's LDS (160 KiB) fewer blocks than its registers allow (six two-wave
+// blocks at three waves per SIMD up to six views, four above), since the
+// in-place staging costs a barrier and registers per view.
+size_t frame_lds(const lf_params &p, const Geometry &g, int *rows_in_place) {
     const int tile = serve_tile_width(p.K);
     const size_t pairs = em_window_pairs(&p, g, tile);
     const size_t widest = em_window_widest(&p, g, tile);
-    // 8-byte records; the R+G+B rows of windows wider than kServeHold tiles
-    // go to a scratch area after them, the others are staged in place
-    const size_t rows = widest > (size_t)kServeHold * tile ? 2 * 3 * (widest + 2) : 0;
-    return pairs * 8 + rows + 64;
+    const size_t rows = 2 * 3 * (widest + 2);
+    const size_t with_rows = pairs * 8 + rows + 64;
+    const size_t blocks = p.K <= 6 ? 6 : 4;
+    if ((size_t)160 * 1024 / with_rows >= blocks || widest > (size_t)kServeHold * tile) {
+        *rows_in_place = 0;
+        return with_rows;
+    }
+    *rows_in_place = 1;
+    return pairs * 8 + 64;
 }
 
 int frame_kind(const lf_params &p, const Geometry &g) {
@@ -293,6 +304,7 @@ bool run_batch(lf_server *s, SrvWorker &wk, std::vector<SrvFrame *> &b, std::str
         J.bad = dbad + i;
         J.warm = f->warm ? 1 : 0;
         J.check = f->dev_in ? 1 : 0;
+        J.rows_in_place = f->rows_in_place;
         J.ref = p.ref;
         J.tiles_x = f->tiles_x;
         J.tile_start = tiles;
@@ -555,7 +567,7 @@ lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, c
     f->user = user;
     f->tiles_x = (p->W + serve_tile_width(p->K) - 1) / serve_tile_width(p->K);
     f->n_tiles = f->tiles_x * p->H;
-    f->lds = frame_lds(*p, f->g);
+    f->lds = frame_lds(*p, f->g, &f->rows_in_place);
     if (f->lds > s->lds_limit) {
         delete f;
         return set_error(LF_EINVAL, "disparity halo needs %zu bytes of LDS per tile, more than %zu", f->lds,

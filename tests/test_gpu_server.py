@@ -85,6 +85,8 @@ CASES = [
     dict(K=7, H=5, W=129, D=40, storage="bf16"),
     dict(K=9, H=4, W=64, D=16, storage="f16", mode="hard"),
     dict(K=2, H=3, W=37, D=9, storage="f32", baselines=[0, 1]),
+    # nine views over 192 levels: rows staged inside the record windows
+    dict(K=9, H=3, W=150, D=192, storage="bf16"),
     # windows wider than the serve kernel stages in place (scratch rows)
     dict(K=9, H=3, W=150, D=240, storage="bf16"),
 ]
