@@ -964,7 +964,8 @@ __device__ __forceinline__ typename Rec<RS>::T stage_rec(typename Pair<ST>::T v)
 }
 
 // The kernel body: descriptors of storage ST staged as records of storage RS.
-template <int K, int ST, int RS, bool FRAC, int SW, bool SYM>
+// STAGED: the caller has staged the windows already (and synchronised).
+template <int K, int ST, int RS, bool FRAC, int SW, bool SYM, bool STAGED = false>
 __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw, double *red, int y, int x0, int tw,
                                         int xc, int block_id) {
     using R = typename Rec<RS>::T;
@@ -979,14 +980,17 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
     view_windows<K, FRAC>(a, x0, tw, w, total);
 
     // Stage the windows (replicated border outside the image) with |f|^2.
-    const P *feat = reinterpret_cast<const P *>(a.feat);
+    if constexpr (!STAGED) {
+        const P *feat = reinterpret_cast<const P *>(a.feat);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const P *row = feat + ((size_t)a.perm[k] * a.H + y) * a.W;
-        for (int p = tid; p < w[k].len; p += blockDim.x)
-            win[win_index(w[k], p)] = stage_rec<RS, ST>(row[clampi(w[k].umin + p, 0, a.W - 1)]);
+        for (int k = 0; k < K; ++k) {
+            const P *row = feat + ((size_t)a.perm[k] * a.H + y) * a.W;
+#pragma unroll 4
+            for (int p = tid; p < w[k].len; p += blockDim.x)
+                win[win_index(w[k], p)] = stage_rec<RS, ST>(row[clampi(w[k].umin + p, 0, a.W - 1)]);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     // the lane's pixel x0 + xc (xc < 0: none); with dynamic-only every
     // pixel of the work list is reconstructed
     const int x = x0 + xc;
@@ -1064,7 +1068,8 @@ __device__ __forceinline__ void em_body(const EmArgs &a, unsigned char *lds_raw,
 // binary16 (|G| <= 2048 for the Sobel responses, the usual case) are staged
 // as binary16 records, the others as int16 Sobel responses: the same values
 // in 8 bytes per record either way, and the same FP32 arithmetic, so the
-// results are the same bits.
+// results are the same bits.  The windows are staged as binary16 while their
+// values are checked, and staged again as int16 only when one is not exact.
 template <int K, int ST, bool FRAC, int SW, bool SYM>
 __device__ __forceinline__ void em_entry(const EmArgs &a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1114,17 +1119,24 @@ __device__ __forceinline__ void em_entry(const EmArgs &a) {
         int total;
         view_windows<K, FRAC>(a, x0, tw, w, total);
         const float2 *feat = reinterpret_cast<const float2 *>(a.feat);
+        typename Rec<1>::T *win = reinterpret_cast<typename Rec<1>::T *>(lds_raw);
         bool exact = true;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const float2 *row = feat + ((size_t)a.perm[k] * a.H + y) * a.W;
+#pragma unroll 4
             for (int p = threadIdx.x; p < w[k].len; p += blockDim.x) {
                 const float2 v = row[clampi(w[k].umin + p, 0, a.W - 1)];
                 exact = exact && exact_in_half(v.x) && exact_in_half(v.y);
+                win[win_index(w[k], p)] = stage_rec<1, 0>(v);
             }
         }
-        if (__syncthreads_and(exact)) em_body<K, 0, 1, FRAC, SW, SYM>(a, lds_raw, red, y, x0, tw, xc, block_id);
-        else em_body<K, 0, 3, FRAC, SW, SYM>(a, lds_raw, red, y, x0, tw, xc, block_id);
+        // (each lane restages its own positions, so no barrier is needed
+        // between the two stagings)
+        if (__syncthreads_and(exact))
+            em_body<K, 0, 1, FRAC, SW, SYM, true>(a, lds_raw, red, y, x0, tw, xc, block_id);
+        else
+            em_body<K, 0, 3, FRAC, SW, SYM>(a, lds_raw, red, y, x0, tw, xc, block_id);
     } else {
         em_body<K, ST, ST, FRAC, SW, SYM>(a, lds_raw, red, y, x0, tw, xc, block_id);
     }
