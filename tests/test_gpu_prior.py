@@ -134,3 +134,31 @@ def test_prior_wide_consistency_radius():
     _say("prior: small_frame with incon_radius=23, incon_min=30")
     _points_only(spec.K, spec.H, spec.W, list(spec.baselines), spec.D, spec.ref, fr.views, fr.S_P,
                  incon_radius=23, incon_min=30)
+
+
+def test_prior_device_buffers_equal_host_buffers():
+    """Views and S_P in device memory and mu_T written there: the points,
+    the triangles and mu_T of the host-buffer call, bit for bit."""
+    import torch
+    import paper_2003_11076_amd as LF
+    fr = S.make_frame(S.workload_spec("small"))
+    spec = fr.spec
+    K, H, W = spec.K, spec.H, spec.W
+    cap = (W // 5 + 1) * (H // 5 + 1) * K + 8
+    st = torch.cuda.current_stream().cuda_stream
+    _say("build prior small_frame: device buffers vs host buffers")
+    p = LF.make_params(K, H, W, spec.ref, spec.baselines, spec.d_min, spec.d_step, spec.D, fr.beta, tau_init=spec.tau)
+    mu_h = np.zeros((H, W), np.float32)
+    pts_h, tris_h, _, _ = LF.lf_build_prior(p, LF.make_support_params(), fr.views, fr.S_P, mu_h, cap, 4 * cap,
+                                            hip_stream=st)
+    dev = torch.device("cuda:0")
+    views, sp_d = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (fr.views, fr.S_P))
+    mu_d = torch.full((H, W), -1.0, device=dev)
+    torch.cuda.synchronize()
+    pd = LF.make_params(K, H, W, spec.ref, spec.baselines, spec.d_min, spec.d_step, spec.D, fr.beta,
+                        tau_init=spec.tau, flags=LF.LF_INPUTS_ON_DEVICE | LF.LF_OUTPUTS_ON_DEVICE)
+    pts_d, tris_d, _, _ = LF.lf_build_prior(pd, LF.make_support_params(), views, sp_d, mu_d, cap, 4 * cap,
+                                            hip_stream=st)
+    torch.cuda.synchronize()
+    assert np.array_equal(pts_h, pts_d) and np.array_equal(tris_h, tris_d)
+    assert np.array_equal(mu_h, mu_d.cpu().numpy())

@@ -114,6 +114,28 @@ def test_dynamic_only_work_list_shapes():
     teacher_forced(case, 3)
 
 
+@pytest.mark.parametrize("cover", ["none", "all"])
+def test_dynamic_only_with_no_or_every_pixel_dynamic(cover):
+    """No dynamic reference pixel: an empty work list (every EM block exits),
+    every pixel at the level nearest mu_T with objective 0 and its reference
+    colour.  Every pixel dynamic: the plain path's bits everywhere."""
+    case = random_case(5, 6, 300, 24, storage="bf16", seed=43)
+    sp = case.S_P.copy()
+    sp[case.ref] = np.float32(0.95) if cover == "none" else np.float32(0.05)
+    case.S_P = sp
+    _say(f"dynamic-only with {cover} of the reference pixels dynamic, 300x6 K=5 D=24 bf16")
+    (rgb0, d0, q0, h0), L0 = _run(case, 0)
+    (rgb1, d1, q1, h1), L1 = _run(case, DYN)
+    if cover == "all":
+        for a, b in ((rgb0, rgb1), (d0, d1), (q0, q1), (h0, h1), (L0, L1)):
+            assert np.array_equal(a, b)
+    else:
+        d_min, d_step = float(case.d_min), float(case.d_step)
+        near = np.clip(np.ceil((case.mu_T.astype(np.float64) - d_min) / d_step - 0.5), 0, case.D - 1)
+        assert np.array_equal(d1, near.astype(np.int32)) and np.all(L1 == 0) and not h1.any()
+        assert np.array_equal(rgb1, case.views[case.ref].astype(np.float32) / np.float32(255))
+
+
 def test_window_covering_all_levels_is_the_plain_sweep():
     """With 3 sigma wider than the level range the window holds every level:
     same bits as the plain sweep (fast and exhaustive)."""

@@ -38,8 +38,8 @@ def _outputs(torch, sp, dev):
             "hole": torch.full((sp.H, sp.W), 7, dtype=torch.uint8, device=dev)}
 
 
-def _context_path(LF, torch, fr, ins, n_iters, median, dev):
-    p = _params(LF, fr, LF.LF_INPUTS_ON_DEVICE | LF.LF_OUTPUTS_ON_DEVICE)
+def _context_path(LF, torch, fr, ins, n_iters, median, dev, extra=0):
+    p = _params(LF, fr, LF.LF_INPUTS_ON_DEVICE | LF.LF_OUTPUTS_ON_DEVICE | extra)
     out = _outputs(torch, fr.spec, dev)
     obj = np.zeros(n_iters)
     ctx = LF.lf_em_init(p, *ins, hip_stream=torch.cuda.current_stream().cuda_stream)
@@ -54,8 +54,8 @@ def _context_path(LF, torch, fr, ins, n_iters, median, dev):
     return res
 
 
-def _noalloc_path(LF, torch, fr, ins, n_iters, median, dev):
-    p = _params(LF, fr, 0)
+def _noalloc_path(LF, torch, fr, ins, n_iters, median, dev, extra=0):
+    p = _params(LF, fr, extra)
     out = _outputs(torch, fr.spec, dev)
     obj = torch.full((n_iters,), -1.0, dtype=torch.float64, device=dev)
     bad = torch.full((1,), 99, dtype=torch.int32, device=dev)
@@ -73,13 +73,17 @@ def test_noalloc_gives_the_bits_of_the_context_path_on_two_calls():
     import paper_2003_11076_amd as LF
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    cases = [("plain", 0), ("small", 3)]      # the second frame is smaller, with the median
-    for name, median in cases:
+    # the second frame is smaller, with the median; then both again with
+    # dynamic-only (its work list lives in the scratch array too)
+    dyn = LF.LF_DYNAMIC_ONLY
+    cases = [("plain", 0, 0), ("small", 3, 0), ("plain", 0, dyn), ("small", 3, dyn)]
+    for name, median, extra in cases:
         spec = S.workload_spec(name)
         fr, ins = _inputs(spec, dev)
-        _say(f"noalloc {spec.name} {spec.W}x{spec.H} K={spec.K} D={spec.D} I={spec.n_iters} median={median}")
-        ref = _context_path(LF, torch, fr, ins, spec.n_iters, median, dev)
-        got = _noalloc_path(LF, torch, fr, ins, spec.n_iters, median, dev)
+        _say(f"noalloc {spec.name} {spec.W}x{spec.H} K={spec.K} D={spec.D} I={spec.n_iters} median={median} "
+             f"flags={extra:#x}")
+        ref = _context_path(LF, torch, fr, ins, spec.n_iters, median, dev, extra)
+        got = _noalloc_path(LF, torch, fr, ins, spec.n_iters, median, dev, extra)
         assert got["bad"] == 0, got["bad"]
         for k in ("rgb", "d", "q", "hole", "obj"):
             assert np.array_equal(ref[k], got[k]), (name, k)
