@@ -83,7 +83,10 @@ typedef int32_t lf_status;
  *   threshold (rho_ref < tau_init) are reconstructed, as the paper refocuses
  *   only the dynamic pixels (Sec. III-F, IV-B).  Every other pixel keeps its
  *   first weights, takes the level nearest mu_T, adds nothing to the
- *   objective, and its refocused colour is its reference colour (hole = 0). */
+ *   objective, and its refocused colour is its reference colour (hole = 0).
+ *   The plain context builds a list of the dynamic pixels on the device
+ *   when the frame is loaded (lf_em_load) and runs EM over that list only;
+ *   the frame server masks the static pixels in its tiles instead. */
 #define LF_PRIOR_WINDOW       0x8u
 #define LF_DYNAMIC_ONLY       0x10u
 /* LF_DEFERRED_CHECK (with LF_INPUTS_ON_DEVICE): lf_em_load / lf_em_init
@@ -249,8 +252,9 @@ lf_status lf_em_intermediates(lf_ctx *c, void *feat, float *rho);
  * hipMalloc): one whole frame, the work of lf_em_init, lf_em_iterate(n_iters)
  * and lf_refocus with device inputs and outputs, giving the same bits, with
  * no allocation of any kind.  The intermediate buffers (descriptors, ray
- * prior, per-pixel objective, the objective's block sums, the median's input)
- * live in one fixed device array of LF_NOALLOC_SCRATCH_BYTES that each GPU
+ * prior, per-pixel objective, the objective's block sums, the median's input,
+ * the dynamic-only work list) live in one fixed device array of
+ * LF_NOALLOC_SCRATCH_BYTES that each GPU
  * holds from the library's first use on it until the process ends.
  *   p          : parameters as lf_em_init; the pointer flags are implied
  *                (every pointer below is device memory) and LF_DEFERRED_CHECK
