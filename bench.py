@@ -750,7 +750,7 @@ def cpu_baseline(args, arrs, storage, mode, budget_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+        print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}); "
               "the per-GPU work shards by row bands, see the design notes.", file=sys.stderr)
         sys.exit(2)
     inputs = make_inputs(args)
