@@ -99,7 +99,7 @@ def parse():
                     help="contexts (one HIP stream each) the timed frames are dealt to, round robin")
     ap.add_argument("--storage", default=None, choices=["f32", "f16", "bf16"])
     ap.add_argument("--mode", default="soft", choices=["soft", "hard"])
-    ap.add_argument("--latency-frames", type=int, default=100)
+    ap.add_argument("--latency-frames", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--quiet", action="store_true")
@@ -367,6 +367,14 @@ class Frames:
         self.ring = ring
         self.rings = {}
 
+    def preallocate(self, stream, spec):
+        """Allocates the stream's whole ring of output buffers, so that no
+        allocation (which can wait for the device) falls in a timed region."""
+        for seq in range(self.ring):
+            self.outputs(stream, spec, seq)
+        if self.device_io:
+            self.torch.cuda.synchronize()
+
     def outputs(self, stream, spec, seq):
         key = (stream, seq % self.ring)
         o = self.rings.get(key)
@@ -496,28 +504,39 @@ def drain_queue(drv):
             return
 
 
-def serve_same_workload(args, LF, torch, arrs, n_streams=8, per_stream=100):
+def _serving_switch_interval():
+    """The frame server calls back into Python from its worker threads; with
+    the interpreter's default 5 ms switch interval a callback can wait that
+    long for the GIL while the submitting thread runs, which is the driver's
+    delay, not the server's."""
+    sys.setswitchinterval(1e-4)
+
+
+def serve_same_workload(args, LF, torch, arrs, n_streams=8, per_stream=100, outstanding=2):
     """The headline frame through the FP16 frame server with device-resident
     inputs and outputs: saturation frames/s with n_streams camera streams in
-    a closed loop, and single-frame latency on an idle GPU."""
+    a closed loop (`outstanding` frames in flight per stream, so that the
+    host's submission of the next frame stays off the critical path), and
+    single-frame latency on an idle GPU."""
     spec = arrs[0]
     frames = Frames(LF, torch, [arrs], "f16", device_io=True)
     srv = LF.lf_server_create(2 << 30, n_streams, spec.n_iters, 64 << 20)
     drv = Driver(LF, srv, frames)
     try:
         for s in range(n_streams):                      # warm-up: one frame per stream
+            frames.preallocate(s, spec)
             drv.submit(s, 0)
         LF.lf_server_drain(srv)
         drain_queue(drv)
         idle = one_at_a_time(LF, srv, drv, 0, max(args.latency_frames, 100))
         drain_queue(drv)
-        wall, n, units = closed_loop(LF, srv, drv, [[0]] * n_streams, per_stream)
+        wall, n, units = closed_loop(LF, srv, drv, [[0]] * n_streams, per_stream, outstanding)
         LF.lf_server_drain(srv)
         sat = LF.lf_server_stats(srv)
         drv.check()
     finally:
         LF.lf_server_destroy(srv)
-    return {"storage": "f16", "io": "device", "camera_streams": n_streams, "outstanding_per_stream": 2,
+    return {"storage": "f16", "io": "device", "camera_streams": n_streams, "outstanding_per_stream": outstanding,
             "saturation": _stats_dict(sat, wall, n, units),
             "single_frame_latency": {"p50_ms": idle.p50_ms, "p99_ms": idle.p99_ms, "frames": int(idle.completed)}}
 
@@ -537,6 +556,7 @@ def serve_mix(args, LF, torch, mix, device_io, poisson_levels=(0.3, 0.5, 0.7, 0.
            "io": "device" if device_io else "host (PCIe copies included)", "hbm_budget_bytes": budget}
     try:
         for s in range(SERVE_STREAMS):                  # warm-up: one frame per stream
+            frames.preallocate(s, frames.items[2 * s][0])
             drv.submit(s, 2 * s)
         LF.lf_server_drain(srv)
         drain_queue(drv)
@@ -585,6 +605,8 @@ def large_concurrent(args, LF, torch, large, reps=5):
     spec = large[0][0]
     frames = Frames(LF, torch, large, "bf16", device_io=True, ring=2)
     n = len(large)
+    for s in range(n):
+        frames.preallocate(s, spec)
     srv = LF.lf_server_create(4 << 30, n, spec.n_iters, 64 << 20)
     drv = Driver(LF, srv, frames)
     try:
@@ -813,6 +835,7 @@ def main():
             out["variants"]["dynamic_only_precision"] = variant_legs(
                 LF, torch, inputs["precision"][0], "f16", reps=10, names=("plain", "dynamic_only"))
     if not args.no_serving:
+        _serving_switch_interval()
         log(args, "serving the headline frame through the FP16 frame server (device buffers)")
         sw = serve_same_workload(args, LF, torch, main_arrs)
         sw["vs_plain_fp32"] = {"frames_per_s_ratio": sw["saturation"]["frames_per_s"] / m["frames_per_s"],
