@@ -175,24 +175,10 @@ EmKernel pick_em(const lf_params *p, const Geometry &g) {
 // ---------------------------------------------------------------------------
 // Launch helpers shared by the plain context and the server.
 // ---------------------------------------------------------------------------
-hipError_t launch_descriptors(const lf_params *p, const uint8_t *views, void *feat, hipStream_t s) {
-    dim3 block(256), grid((p->W + 255) / 256, (p->H + kDescRows - 1) / kDescRows, p->K);
-    switch (p->storage) {
-        case LF_F32:
-            hipLaunchKernelGGL(lf_descriptors_kernel<0>, grid, block, 0, s, views, (float2 *)feat, p->H, p->W);
-            break;
-        case LF_F16:
-            hipLaunchKernelGGL(lf_descriptors_kernel<1>, grid, block, 0, s, views, (__half2 *)feat, p->H, p->W);
-            break;
-        default:
-            hipLaunchKernelGGL(lf_descriptors_kernel<2>, grid, block, 0, s, views, (uint32_t *)feat, p->H, p->W);
-            break;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *mu_T, const float *q_warm,
-                            float *rho, float *omr, float *q, uint32_t *bad, int check, hipStream_t s) {
+// The load pass (descriptors and ray prior, one launch).
+hipError_t launch_load(const lf_params *p, const uint8_t *views, void *feat, const float *S_P, const float *mu_T,
+                       const float *q_warm, float *rho, float *omr, float *q, uint32_t *bad, int check,
+                       hipStream_t s) {
     PriorArgs a{};
     a.S_P = S_P;
     a.mu_T = mu_T;
@@ -208,8 +194,18 @@ hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *m
     a.check = check;
     a.tau = p->tau_init;
     for (int k = 0; k < p->K; ++k) a.b[k] = p->baselines[k];
-    dim3 block(256), grid((p->W + 255) / 256, p->H, p->K);
-    hipLaunchKernelGGL(lf_ray_prior_kernel, grid, block, 0, s, a);
+    dim3 block(256), grid((p->W + 255) / 256, (p->H + kDescRows - 1) / kDescRows + p->H, p->K);
+    switch (p->storage) {
+        case LF_F32:
+            hipLaunchKernelGGL(lf_load_kernel<0>, grid, block, 0, s, views, (float2 *)feat, a);
+            break;
+        case LF_F16:
+            hipLaunchKernelGGL(lf_load_kernel<1>, grid, block, 0, s, views, (__half2 *)feat, a);
+            break;
+        default:
+            hipLaunchKernelGGL(lf_load_kernel<2>, grid, block, 0, s, views, (uint32_t *)feat, a);
+            break;
+    }
     return hipGetLastError();
 }
 
@@ -564,9 +560,8 @@ static lf_status ctx_load(lf_ctx *c, const uint8_t *views, const float *S_P, con
         // with a deferred check the counter stays set until it is reported
         if (!(p.flags & LF_DEFERRED_CHECK)) LF_HIP(hipMemsetAsync(c->bad, 0, 4, c->stream), "clear counter");
     }
-    LF_HIP(launch_descriptors(&p, c->views, c->feat, c->stream), "descriptor launch");
-    LF_HIP(launch_ray_prior(&p, sp, mu, qw, c->rho, c->omr, c->q, c->bad, dev_in ? 1 : 0, c->stream),
-           "ray prior launch");
+    LF_HIP(launch_load(&p, c->views, c->feat, sp, mu, qw, c->rho, c->omr, c->q, c->bad, dev_in ? 1 : 0, c->stream),
+           "load launch");
     if (c->dyn.span) {
         EmArgs da = make_em_args(&p, c->g, c->lambda);
         da.rho = c->rho;
@@ -578,10 +573,12 @@ static lf_status ctx_load(lf_ctx *c, const uint8_t *views, const float *S_P, con
                "dynamic-only work list");
     }
     if (dev_in) {
-        LF_HIP(hipMemcpyAsync(c->h_bad, c->bad, 4, hipMemcpyDeviceToHost, c->stream), "copy counter");
         if (p.flags & LF_DEFERRED_CHECK) {
-            c->check_pending = true;   // read by the next call that waits for the stream
+            // the counter is read by the next call that waits for the stream;
+            // no copy per frame
+            c->check_pending = true;
         } else {
+            LF_HIP(hipMemcpyAsync(c->h_bad, c->bad, 4, hipMemcpyDeviceToHost, c->stream), "copy counter");
             LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
             if (*c->h_bad) return set_error(LF_EINVAL, "%u input values invalid (S_P outside [0,1], mu_T not finite "
                                                       "or q_warm outside [0,1])", *c->h_bad);
@@ -685,6 +682,9 @@ lf_status lf_em_load(lf_ctx *c, const uint8_t *views, const float *S_P, const fl
 static lf_status deferred_check(lf_ctx *c) {
     if (!c->check_pending) return LF_OK;
     c->check_pending = false;
+    // the count of every frame loaded since the last report
+    LF_HIP(hipMemcpyAsync(c->h_bad, c->bad, 4, hipMemcpyDeviceToHost, c->stream), "copy counter");
+    LF_HIP(hipStreamSynchronize(c->stream), "synchronize");
     const uint32_t bad = *c->h_bad;
     if (!bad) return LF_OK;
     *c->h_bad = 0;

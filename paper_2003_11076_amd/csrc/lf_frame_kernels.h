@@ -1,8 +1,8 @@
 // Per-frame kernels around the EM iterations (gfx950):
-//   lf_descriptors_kernel  3x3 Sobel responses of R+G+B (Sec. III-C)
-//   lf_ray_prior_kernel    S_P of each view at the ray footprint of mu_T, its
-//                          complement, and the thresholded first weights
-//                          (Sec. III-B, III-F)
+//   lf_load_kernel         3x3 Sobel responses of R+G+B (Sec. III-C), and S_P
+//                          of each view at the ray footprint of mu_T, its
+//                          complement and the thresholded first weights
+//                          (Sec. III-B, III-F), in one launch
 //   lf_refocus_kernel      mean of the static rays (Eq. 2)
 //   lf_median3_kernel      3x3 per-channel median of the refocused image (Sec. III-E)
 //   lf_seg_*_kernel        per-view segmentation maps in each view's own grid (Sec. III-D)
@@ -14,19 +14,24 @@
 namespace lfem {
 
 // ---------------------------------------------------------------------------
-// Descriptors.  grid (ceil(W/256), ceil(H/kDescRows), K), block 256: each
-// block stages the intensity sums L = R+G+B of its kDescRows rows plus one
+// Load pass: the descriptors and the ray prior of a frame in one launch.
+// grid (ceil(W/256), ceil(H/kDescRows) + H, K), block 256: the blocks with
+// blockIdx.y below ceil(H/kDescRows) compute descriptors, the others the
+// ray prior of one row each (the two parts are independent).
+// ---------------------------------------------------------------------------
+
+// Descriptors of view k, rows y0 .. y0 + kDescRows - 1, columns x0 .. x0 +
+// 255: the block stages the intensity sums L = R+G+B of its rows plus one
 // row and one column of border on each side (replicated) in LDS, then every
 // lane takes the 3x3 Sobel responses of its column down the rows.
-// ---------------------------------------------------------------------------
 constexpr int kDescRows = 8;
 
 template <int ST>
-__global__ __launch_bounds__(256) void lf_descriptors_kernel(const uint8_t *__restrict__ views,
-                                                             typename Pair<ST>::T *__restrict__ feat,
-                                                             int H, int W) {
+__device__ __forceinline__ void descriptors_block(const uint8_t *__restrict__ views,
+                                                  typename Pair<ST>::T *__restrict__ feat, int H, int W, int k,
+                                                  int y0, int x0) {
     __shared__ int16_t L[kDescRows + 2][256 + 2];
-    const int k = blockIdx.z, y0 = blockIdx.y * kDescRows, x0 = blockIdx.x * 256, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const uint8_t *v = views + (size_t)k * H * W * 3;
     for (int i = tid; i < (kDescRows + 2) * 258; i += 256) {
         const int r = i / 258, c = i - r * 258;
@@ -46,9 +51,7 @@ __global__ __launch_bounds__(256) void lf_descriptors_kernel(const uint8_t *__re
     }
 }
 
-// ---------------------------------------------------------------------------
-// Ray prior and first weights.  grid (ceil(W/blockDim), H, K).
-// ---------------------------------------------------------------------------
+// Ray prior and first weights of view k, row y, columns x0 .. x0 + 255.
 struct PriorArgs {
     const float *S_P, *mu_T, *q_warm;
     float *rho, *omr, *q;   // static prior, dynamic prior 1 - rho, weights
@@ -58,9 +61,8 @@ struct PriorArgs {
     float b[kMaxViews];
 };
 
-__global__ __launch_bounds__(256) void lf_ray_prior_kernel(PriorArgs a) {
-    const int k = blockIdx.z, y = blockIdx.y;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void ray_prior_row(const PriorArgs &a, int k, int y, int x0) {
+    const int x = x0 + threadIdx.x;
     if (x >= a.W) return;
     const size_t pix = (size_t)y * a.W + x;
     const size_t i = (size_t)k * a.H * a.W + pix;
@@ -80,6 +82,15 @@ __global__ __launch_bounds__(256) void lf_ray_prior_kernel(PriorArgs a) {
         if (a.q_warm) nbad += !(q0 >= 0.0f && q0 <= 1.0f);
         if (nbad) atomicAdd(a.bad, nbad);
     }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void lf_load_kernel(const uint8_t *__restrict__ views,
+                                                      typename Pair<ST>::T *__restrict__ feat, PriorArgs a) {
+    const int nd = (a.H + kDescRows - 1) / kDescRows;
+    const int k = blockIdx.z, by = blockIdx.y, x0 = blockIdx.x * 256;
+    if (by < nd) descriptors_block<ST>(views, feat, a.H, a.W, k, by * kDescRows, x0);
+    else ray_prior_row(a, k, by - nd, x0);
 }
 
 // ---------------------------------------------------------------------------

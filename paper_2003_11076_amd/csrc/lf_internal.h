@@ -85,9 +85,10 @@ size_t rec_bytes(int storage);
 int choose_tile(const lf_params *p, const Geometry &g, size_t lds_limit, size_t lds_per_cu, int vgprs,
                 size_t *lds_out);
 
-hipError_t launch_descriptors(const lf_params *p, const uint8_t *views, void *feat, hipStream_t s);
-hipError_t launch_ray_prior(const lf_params *p, const float *S_P, const float *mu_T, const float *q_warm,
-                            float *rho, float *omr, float *q, uint32_t *bad, int check, hipStream_t s);
+// Descriptors and ray prior of a frame (one launch).
+hipError_t launch_load(const lf_params *p, const uint8_t *views, void *feat, const float *S_P, const float *mu_T,
+                       const float *q_warm, float *rho, float *omr, float *q, uint32_t *bad, int check,
+                       hipStream_t s);
 hipError_t launch_median3(const lf_params *p, const float *in, float *out, hipStream_t s);
 // Dynamic-only work list of a frame (span == 0: not dynamic-only).
 struct DynPlan {

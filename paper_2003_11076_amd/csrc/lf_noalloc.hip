@@ -129,8 +129,7 @@ extern "C" lf_status lf_em_frame_noalloc(const lf_params *p, const uint8_t *view
     // the count of invalid input values starts at zero (a fill kernel, not a
     // memset, so that the call can be captured in a graph)
     LF_HIP(launch_fill_u32(bad, 1, 0u, s), "clear counter");
-    LF_HIP(launch_descriptors(&pp, views, feat, s), "descriptor launch");
-    LF_HIP(launch_ray_prior(&pp, S_P, mu_T, q_warm, rho, omr, q, bad, 1, s), "ray prior launch");
+    LF_HIP(launch_load(&pp, views, feat, S_P, mu_T, q_warm, rho, omr, q, bad, 1, s), "load launch");
 
     EmArgs a = make_em_args(&pp, g, derived_lambda(&pp));
     if (dyn.span) {
