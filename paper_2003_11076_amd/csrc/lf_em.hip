@@ -211,7 +211,10 @@ hipError_t launch_load(const lf_params *p, const uint8_t *views, void *feat, con
 
 // Dynamic-only work list: items of up to 64 dynamic reference pixels of a
 // row within `span` columns (the widest of 256, 192, 128, 64 whose view
-// windows fit a block's LDS), one wave each.
+// windows fit a block's LDS), one wave each; with the shared sweep (integer
+// shifts, no search window, not the exhaustive sweep) also of at most
+// kItemUnbounded pixels predicted unbounded, within a budget of W/64 such
+// cuts per row.
 DynPlan dyn_plan(const lf_params *p, const Geometry &g, size_t lds_limit) {
     DynPlan d{};
     if (!(p->flags & LF_DYNAMIC_ONLY)) return d;
@@ -220,20 +223,22 @@ DynPlan dyn_plan(const lf_params *p, const Geometry &g, size_t lds_limit) {
         d.lds = em_window_pairs(p, g, w) * rec_bytes(p->storage);
         if (d.lds <= lds_limit) break;
     }
-    d.per_row = p->W / 64 + p->W / d.span + 1;
+    d.split = !g.frac && !(p->flags & (LF_EXHAUSTIVE_SWEEP | LF_PRIOR_WINDOW));
+    d.per_row = p->W / 64 + p->W / d.span + 1 + (d.split ? p->W / 64 : 0);
     d.max_items = p->H * d.per_row;
     return d;
 }
 
-size_t dyn_rows_ints(const lf_params *p, const DynPlan &d) { return (size_t)p->H * (d.per_row + 1); }
+size_t dyn_rows_ints(const lf_params *p, const DynPlan &d) { return (size_t)p->H * (2 * (size_t)d.per_row + 1); }
 
-hipError_t launch_dyn_list(const lf_params *p, const EmArgs &a, const DynPlan &d, int *rows, int2 *items,
+hipError_t launch_dyn_list(const lf_params *p, const EmArgs &a, const DynPlan &d, int *rows, int4 *items,
                            int *n_items, hipStream_t s) {
-    int *counts = rows, *starts = rows + p->H;
-    hipLaunchKernelGGL(lf_dyn_rows_kernel, dim3(p->H), dim3(64), 0, s, a, d.per_row, counts, starts);
+    int *counts = rows, *row_items = rows + p->H;
+    hipLaunchKernelGGL(lf_dyn_rows_kernel, dim3(p->H), dim3(64), 0, s, a, d.per_row, p->K, p->storage, d.split,
+                       counts, row_items);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(lf_dyn_items_kernel, dim3(1), dim3(256), 0, s, counts, starts, p->H, d.per_row, items,
+    hipLaunchKernelGGL(lf_dyn_items_kernel, dim3(1), dim3(256), 0, s, counts, row_items, p->H, d.per_row, items,
                        n_items);
     return hipGetLastError();
 }
@@ -473,7 +478,7 @@ struct lf_ctx {
     unsigned long long *sweep;  // level-step counter of lf_em_sweep_count
     DynPlan dyn;            // dynamic-only work list (span 0: none)
     int *dyn_rows;          // [H] items per row, then [H][per_row] their first columns
-    int2 *dyn_items;        // [max_items] (row, first column)
+    int4 *dyn_items;        // [max_items] (row, first column, pixels, 0)
     int *dyn_n;             // number of items
     double *h_obj;          // pinned
     uint32_t *h_bad;        // pinned
@@ -518,7 +523,7 @@ static lf_status ctx_alloc(lf_ctx *c) {
     plan.add(&c->sweep, 256);
     if (c->dyn.span) {
         plan.add(&c->dyn_rows, dyn_rows_ints(&p, c->dyn) * 4);
-        plan.add(&c->dyn_items, (size_t)c->dyn.max_items * 8);
+        plan.add(&c->dyn_items, (size_t)c->dyn.max_items * 16);
         plan.add(&c->dyn_n, 256);
     }
     if (!dev_out) {
@@ -564,7 +569,9 @@ static lf_status ctx_load(lf_ctx *c, const uint8_t *views, const float *S_P, con
            "load launch");
     if (c->dyn.span) {
         EmArgs da = make_em_args(&p, c->g, c->lambda);
+        da.feat = c->feat;
         da.rho = c->rho;
+        da.q = c->q;
         da.mu_T = mu;
         da.d_idx = c->d_idx;
         da.lpix = c->lpix;

@@ -177,7 +177,7 @@ struct EmArgs {
     float margin_c;       // absolute slack of the bound
     float win_half;       // > 0: the M-step searches only |d - mu| <= win_half
     int dyn_only;         // 1: only pixels with rho_ref < tau are reconstructed
-    const int2 *items;    // dynamic-only work list: (row, first column), or null for row tiles
+    const int4 *items;    // dynamic-only work list: (row, first column, pixels, 0), or null for row tiles
     const int *n_items;   // its length (device)
     int seg_w;            // dynamic-only: columns an item's pixels may spread over (a multiple of 64, <= 256)
     float d_absmax;       // max |d_j| over the levels
@@ -1077,8 +1077,8 @@ __device__ __forceinline__ void em_entry(const EmArgs &a) {
     __shared__ int slots[64];
     int y, x0, tw, xc, block_id;
     if (a.items) {
-        // dynamic-only work item (one wave): the first up to 64 dynamic
-        // reference pixels (rho_ref < tau) of a row from the item's first
+        // dynamic-only work item (one wave): the item's first up to 64
+        // dynamic reference pixels (rho_ref < tau) of a row from its first
         // column on, within seg_w columns of it, one per lane; the tile
         // spans the first to the last of them
         block_id = blockIdx.x;
@@ -1089,9 +1089,9 @@ __device__ __forceinline__ void em_entry(const EmArgs &a) {
                     if (a.want_obj || it == a.n_iters - 1) a.obj[(size_t)it * a.n_blocks + block_id] = 0.0;
             return;
         }
-        const int2 item = a.items[block_id];
+        const int4 item = a.items[block_id];
         y = item.x;
-        const int first = item.y, lane = threadIdx.x;
+        const int first = item.y, take = max(min(item.z, 64), 1), lane = threadIdx.x;
         const float *rho_ref = a.rho + (size_t)a.perm[0] * a.H * a.W + (size_t)y * a.W;
         int before = 0;
         for (int c = 0; c < a.seg_w; c += 64) {
@@ -1099,10 +1099,10 @@ __device__ __forceinline__ void em_entry(const EmArgs &a) {
             const bool dyn = col < a.W && rho_ref[col] < a.tau;
             const uint64_t m = __ballot(dyn);
             const int rank = before + __popcll(m & ((1ull << lane) - 1ull));
-            if (dyn && rank < 64) slots[rank] = col;
+            if (dyn && rank < take) slots[rank] = col;
             before += __popcll(m);
         }
-        const int cnt = min(before, 64);   // >= 1: the first column is dynamic
+        const int cnt = min(before, take);   // >= 1: the first column is dynamic
         __syncthreads();
         x0 = slots[0];
         tw = slots[cnt - 1] - x0 + 1;

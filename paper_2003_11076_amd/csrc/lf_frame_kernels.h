@@ -98,19 +98,71 @@ __global__ __launch_bounds__(256) void lf_load_kernel(const uint8_t *__restrict_
 // only, rho_ref < tau).  A work item is one wave: the next up to 64 dynamic
 // pixels of a row that lie within `span` columns of the item's first one
 // (span = a.seg_w, a multiple of 64, so that the item's view windows fit the
-// LDS).  The items of a row are cut greedily from left to right, so a row of
-// W columns has at most floor(W/64) items of 64 pixels plus floor((W-1)/span)
-// closed by the span, plus the last: per_row = W/64 + W/span + 1 bounds them.
-// grid H, one wave per row: the row's item starts (columns) and their
-// number; the pixels not reconstructed take the level nearest mu_T and
-// objective 0.
+// LDS), cut greedily from left to right.  With the shared sweep (split) an
+// item also holds at most kItemUnbounded pixels whose first sweep the prior
+// bound is predicted to leave unbounded (seed_bounded): the wave shares an
+// unbounded pixel's levels among lanes, cp = 64 / (their number) per pixel,
+// so an item with many of them sweeps whole level ranges, and it sets the
+// launch's time (the items all start at once).  A row of W columns then has
+// at most floor(W/64) items of 64 pixels, floor((W-1)/span) closed by the
+// span and one last item, plus, with split, at most W/64 closed by the
+// unbounded limit (a budget: the limit is not applied beyond it), which
+// per_row bounds.  grid H, one wave per row: the row's items (first column,
+// number of pixels) and their number; the pixels not reconstructed take
+// the level nearest mu_T and objective 0.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void lf_dyn_rows_kernel(EmArgs a, int per_row, int *__restrict__ counts,
-                                                         int *__restrict__ starts) {
+constexpr int kItemUnbounded = 16;
+
+__device__ __forceinline__ float2 load_pair(const void *feat, int storage, size_t i) {
+    if (storage == 0) return reinterpret_cast<const float2 *>(feat)[i];
+    if (storage == 1) return widen(reinterpret_cast<const __half2 *>(feat)[i]);
+    return widen(reinterpret_cast<const uint32_t *>(feat)[i]);
+}
+
+// Whether the prior bound leaves the first sweep of pixel (x, y) bounded:
+// its energy at the first seed (the level nearest mu_T, the weights the
+// frame was loaded with), in one-pass form from the descriptors in HBM,
+// against prior_interval.  A prediction of the sweep's own test, which
+// takes the exact energy from LDS; integer shifts.
+__device__ __forceinline__ bool seed_bounded(const EmArgs &a, int K, int storage, int y, int x) {
+    const size_t HW = (size_t)a.H * a.W, pix = (size_t)y * a.W + x;
+    const float mu = a.mu_T[pix];
+    const int j = nearest_level(a, mu);
+    float Q = 0.0f;
+    for (int k = 0; k < K; ++k) Q += a.q[(size_t)a.perm[k] * HW + pix];
+    const bool empty = !(Q > 0.0f);
+    float Wt = 0.0f, Ax = 0.0f, Ay = 0.0f, S = 0.0f;
+    for (int k = 0; k < K; ++k) {
+        const float w = empty ? 1.0f : a.q[(size_t)a.perm[k] * HW + pix];
+        const int u = clampi(x - a.bi[k] * (a.dmin_i + j * a.dstep_i), 0, a.W - 1);
+        const float2 f = load_pair(a.feat, storage, ((size_t)a.perm[k] * a.H + y) * a.W + u);
+        Wt += w;
+        Ax = fmaf(w, f.x, Ax);
+        Ay = fmaf(w, f.y, Ay);
+        S = fmaf(w, fmaf(f.x, f.x, f.y * f.y), S);
+    }
+    const float cw = empty ? 0.0f : a.beta_p;
+    const float C = fmaxf(S - (Ax * Ax + Ay * Ay) / Wt, 0.0f);
+    const float E = fmaf(cw, C, -log_prior(a, j, mu));
+    int jl, jh;
+    return prior_interval(a, E, mu, jl, jh);
+}
+
+// items of row y: items_row[2 i] = first column, items_row[2 i + 1] = pixels
+__global__ __launch_bounds__(64) void lf_dyn_rows_kernel(EmArgs a, int per_row, int K, int storage, int split,
+                                                         int *__restrict__ counts, int *__restrict__ rows) {
     const int y = blockIdx.x, lane = threadIdx.x;
     const float *rho_ref = a.rho + (size_t)a.perm[0] * a.H * a.W + (size_t)y * a.W;
-    int *row_starts = starts + (size_t)y * per_row;
-    int n_items = 0, first = 0, n = 0;   // wave-uniform
+    int *items_row = rows + (size_t)y * per_row * 2;
+    const int budget = split ? a.W / 64 : 0;
+    int n_items = 0, first = 0, n = 0, nu = 0, used = 0;   // wave-uniform
+    auto close = [&]() {
+        if (lane == 0 && n_items < per_row) {
+            items_row[2 * n_items] = first;
+            items_row[2 * n_items + 1] = n;
+        }
+        ++n_items;
+    };
     for (int c0 = 0; c0 < a.W; c0 += 64) {
         const int col = c0 + lane;
         const bool in = col < a.W;
@@ -120,31 +172,38 @@ __global__ __launch_bounds__(64) void lf_dyn_rows_kernel(EmArgs a, int per_row, 
             a.d_idx[pix] = nearest_level(a, a.mu_T[pix]);
             a.lpix[pix] = 0.0f;
         }
+        const bool unb = split && dyn && !seed_bounded(a, K, storage, y, col);
         uint64_t m = __ballot(dyn);
+        const uint64_t um = __ballot(unb);
         while (m) {
-            const int cb = c0 + __builtin_ctzll(m);
+            const int b = __builtin_ctzll(m);
+            const int cb = c0 + b;
             m &= m - 1;
-            if (n > 0 && (n == 64 || cb - first >= a.seg_w)) {
-                if (lane == 0 && n_items < per_row) row_starts[n_items] = first;
-                ++n_items;
-                n = 0;
+            const bool u = (um >> b) & 1ull;
+            if (n > 0) {
+                const bool full = n == 64 || cb - first >= a.seg_w;
+                const bool by_unb = !full && u && nu == kItemUnbounded && used < budget;
+                if (full || by_unb) {
+                    close();
+                    used += by_unb ? 1 : 0;
+                    n = 0;
+                    nu = 0;
+                }
             }
             if (n == 0) first = cb;
             ++n;
+            nu += u ? 1 : 0;
         }
     }
-    if (n > 0) {
-        if (lane == 0 && n_items < per_row) row_starts[n_items] = first;
-        ++n_items;
-    }
+    if (n > 0) close();
     if (lane == 0) counts[y] = min(n_items, per_row);
 }
 
 // One block: exclusive scan of the rows' item counts, then the list in row
-// order as (row, first column).
+// order as (row, first column, pixels).
 __global__ __launch_bounds__(256) void lf_dyn_items_kernel(const int *__restrict__ counts,
-                                                           const int *__restrict__ starts, int H, int per_row,
-                                                           int2 *__restrict__ items, int *__restrict__ n_items) {
+                                                           const int *__restrict__ rows, int H, int per_row,
+                                                           int4 *__restrict__ items, int *__restrict__ n_items) {
     __shared__ int part[256];
     const int t = threadIdx.x, per = (H + 255) / 256;
     const int beg = min(t * per, H), end = min(beg + per, H);
@@ -165,7 +224,8 @@ __global__ __launch_bounds__(256) void lf_dyn_items_kernel(const int *__restrict
     int off = part[t];
     for (int y = beg; y < end; ++y) {
         const int c = counts[y];
-        for (int i = 0; i < c; ++i) items[off++] = make_int2(y, starts[(size_t)y * per_row + i]);
+        const int *r = rows + (size_t)y * per_row * 2;
+        for (int i = 0; i < c; ++i) items[off++] = make_int4(y, r[2 * i], r[2 * i + 1], 0);
     }
 }
 

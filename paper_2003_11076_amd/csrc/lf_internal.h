@@ -93,14 +93,16 @@ hipError_t launch_median3(const lf_params *p, const float *in, float *out, hipSt
 // Dynamic-only work list of a frame (span == 0: not dynamic-only).
 struct DynPlan {
     int span;        // columns an item's pixels may spread over (multiple of 64)
+    int split;       // items also limited in pixels predicted unbounded (shared sweep)
     int per_row;     // bound on a row's items
     int max_items;   // H * per_row
     size_t lds;      // block LDS of an item's windows
 };
 DynPlan dyn_plan(const lf_params *p, const Geometry &g, size_t lds_limit);
-// Ints of the per-row scratch of the list: H counts and H * per_row starts.
+// Ints of the per-row scratch of the list: H counts and H * per_row items
+// (first column, pixels).
 size_t dyn_rows_ints(const lf_params *p, const DynPlan &d);
-hipError_t launch_dyn_list(const lf_params *p, const EmArgs &a, const DynPlan &d, int *rows, int2 *items,
+hipError_t launch_dyn_list(const lf_params *p, const EmArgs &a, const DynPlan &d, int *rows, int4 *items,
                            int *n_items, hipStream_t s);
 hipError_t launch_em(const lf_params *p, const Geometry &g, EmArgs a, int tile, size_t lds, hipStream_t s,
                      const DynPlan *d);

@@ -67,7 +67,7 @@ static NoallocPlan noalloc_plan(const lf_params *p, int n_blocks, int n_iters, i
     pl.bad = carve(4);
     if (d.span) {
         pl.dyn_rows = carve(dyn_rows_ints(p, d) * 4);
-        pl.dyn_items = carve((size_t)d.max_items * 8);
+        pl.dyn_items = carve((size_t)d.max_items * 16);
         pl.dyn_n = carve(4);
     }
     pl.total = o;
@@ -134,15 +134,17 @@ extern "C" lf_status lf_em_frame_noalloc(const lf_params *p, const uint8_t *view
     EmArgs a = make_em_args(&pp, g, derived_lambda(&pp));
     if (dyn.span) {
         EmArgs da = a;
+        da.feat = feat;
         da.rho = rho;
+        da.q = q;
         da.mu_T = mu_T;
         da.d_idx = d_idx;
         da.lpix = lpix;
         da.seg_w = dyn.span;
         LF_HIP(launch_dyn_list(&pp, da, dyn, reinterpret_cast<int *>(base + pl.dyn_rows),
-                               reinterpret_cast<int2 *>(base + pl.dyn_items), reinterpret_cast<int *>(base + pl.dyn_n), s),
+                               reinterpret_cast<int4 *>(base + pl.dyn_items), reinterpret_cast<int *>(base + pl.dyn_n), s),
                "dynamic-only work list");
-        a.items = reinterpret_cast<const int2 *>(base + pl.dyn_items);
+        a.items = reinterpret_cast<const int4 *>(base + pl.dyn_items);
         a.n_items = reinterpret_cast<const int *>(base + pl.dyn_n);
     }
     a.feat = feat;
