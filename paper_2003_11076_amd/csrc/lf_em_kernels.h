@@ -1108,11 +1108,23 @@ __device__ __forceinline__ void em_entry(const EmArgs &a) {
         tw = slots[cnt - 1] - x0 + 1;
         xc = lane < cnt ? slots[lane] - x0 : -1;
     } else {
-        y = blockIdx.y;
-        x0 = blockIdx.x * a.tile;
+        // row tile.  Blocks go to the 8 XCDs round robin (block lin to XCD
+        // lin % 8), each with its own L2, and the tiles of a row stage
+        // overlapping halo windows: so a row's tiles all go to one XCD (rows
+        // y with the same y mod 8 share one), in row order, and a tile's
+        // halo hits in the L2 its neighbours filled.  Rows past the last
+        // whole group of 8 keep the grid order.
+        const int gx = (int)gridDim.x, lin = (int)blockIdx.y * gx + (int)blockIdx.x;
+        int t = lin;
+        if (lin < ((int)gridDim.y / 8) * 8 * gx) {
+            const int k = lin >> 3;
+            t = ((lin & 7) + 8 * (k / gx)) * gx + k % gx;
+        }
+        y = t / gx;
+        x0 = (t - y * gx) * a.tile;
         tw = a.tile;
         xc = threadIdx.x;
-        block_id = blockIdx.y * gridDim.x + blockIdx.x;
+        block_id = t;
     }
     if constexpr (ST == 0) {
         Window w[K];
