@@ -248,7 +248,20 @@ __device__ __forceinline__ void serve_entry(const ServeJob *__restrict__ jobs, i
     while (j + 1 < n_jobs && (int)blockIdx.x >= jobs[j + 1].tile_start) ++j;
     j = __builtin_amdgcn_readfirstlane(j);
     const ServeJob &job = jobs[j];
-    serve_tile<K, ST, KIND>(job, (int)blockIdx.x - job.tile_start, lds);
+    // a frame's blocks start at a multiple of 8 (the blocks past its tiles
+    // are padding); as in the plain EM launch, all tiles of a row go to one
+    // XCD (block b to XCD b % 8), so that neighbouring tiles share their
+    // halo in that XCD's L2; rows past the last whole group of 8 keep the
+    // grid order
+    const int local = (int)blockIdx.x - job.tile_start;
+    if (local >= job.n_tiles) return;
+    const int gx = job.tiles_x;
+    int t = local;
+    if (local < (job.n_tiles / gx / 8) * 8 * gx) {
+        const int k = local >> 3;
+        t = ((local & 7) + 8 * (k / gx)) * gx + k % gx;
+    }
+    serve_tile<K, ST, KIND>(job, t, lds);
 }
 
 // Register budgets as the plain context's instances: the shared sweep at

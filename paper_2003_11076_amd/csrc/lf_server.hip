@@ -311,7 +311,7 @@ bool run_batch(lf_server *s, SrvWorker &wk, std::vector<SrvFrame *> &b, std::str
         J.n_tiles = f->n_tiles;
         J.tau = p.tau_init;
         hbad[i] = 0;
-        tiles += f->n_tiles;
+        tiles += (f->n_tiles + 7) & ~7;   // the next frame's blocks start at a multiple of 8
         lds = std::max(lds, f->lds);
         if (!f->dev_in) {
             e = hipMemcpyAsync(d + f->o_views, h + f->in_views, KHW * 3, hipMemcpyHostToDevice, st);

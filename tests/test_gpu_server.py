@@ -317,6 +317,7 @@ def test_invalid_device_inputs_fail_the_frame_only():
     good = random_case(3, 4, 64, 8, storage="f32", seed=7)
     bad_sp = good.S_P.copy()
     bad_sp[1, 2, 5] = 1.5
+    bad_sp[0, 0, 60] = -0.5   # a second row tile: the count adds up over the frame's tiles
     _say("server: invalid values in device inputs")
     flags = LF.LF_INPUTS_ON_DEVICE | LF.LF_OUTPUTS_ON_DEVICE
     keep = []
