@@ -27,6 +27,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <atomic>
 #include <thread>
 #include <vector>
 
@@ -137,6 +138,7 @@ struct SrvStream {
 
 constexpr size_t kMaxBatch = 16;
 constexpr int kWorkers = 4;
+constexpr int kIdleSpinUs = 200;   // an idle worker polls for new frames this long before sleeping
 
 struct SrvWorker {
     hipStream_t hs = nullptr;
@@ -167,6 +169,7 @@ struct lf_server {
     int64_t use_clock = 0;
     std::mutex mu;
     std::condition_variable cv, cv_idle;
+    std::atomic<int64_t> arrivals{0};   // frames submitted (read by idle workers without the lock)
     bool stop = false;
     int64_t next_id = 0;
     // statistics
@@ -409,6 +412,7 @@ void worker_main(lf_server *s, int wi) {
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         std::vector<SrvFrame *> b;
+        bool spun = false;
         for (;;) {
             if (s->sticky != LF_OK) {
                 // after a device failure every pending frame fails
@@ -425,6 +429,19 @@ void worker_main(lf_server *s, int wi) {
                 if (!b.empty()) break;
             }
             if (s->stop && s->pending.empty() && s->inflight == 0) return;
+            if (!spun) {
+                // a short spin before sleeping: a frame submitted within
+                // kIdleSpinUs of the worker going idle starts without the
+                // wake-up latency of the wait
+                spun = true;
+                const int64_t seen = s->arrivals.load(std::memory_order_relaxed);
+                lk.unlock();
+                const Clock::time_point until = Clock::now() + std::chrono::microseconds(kIdleSpinUs);
+                while (s->arrivals.load(std::memory_order_acquire) == seen && Clock::now() < until)
+                    std::this_thread::yield();
+                lk.lock();
+                continue;
+            }
             s->cv.wait(lk);
         }
         const bool failed_early = s->sticky != LF_OK;
@@ -641,6 +658,7 @@ lf_status lf_submit_frame(lf_server *s, int32_t stream_id, const lf_params *p, c
         }
         s->submitted += 1;
         s->pending.push_back(f);
+        s->arrivals.fetch_add(1, std::memory_order_release);
         if (frame_id) *frame_id = f->id;
     }
     s->cv.notify_one();
