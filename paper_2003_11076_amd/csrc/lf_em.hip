@@ -300,19 +300,24 @@ EmArgs make_em_args(const lf_params *p, const Geometry &g, float lambda) {
 }
 
 // Row tiles (grid (ceil(W/tile), H)), or with a dynamic-only work list one
-// wave per item (grid d.max_items; blocks past the list's length exit).
+// wave per item (grid d.max_items rounded up to a multiple of 8; blocks past
+// the list's length exit).
 hipError_t launch_em(const lf_params *p, const Geometry &g, EmArgs a, int tile, size_t lds, hipStream_t s,
                      const DynPlan *d) {
     EmKernel kern = pick_em(p, g);
     a.tile = tile;
     dim3 block(tile), grid((p->W + tile - 1) / tile, p->H);
+    a.n_blocks = grid.x * grid.y;
     if (a.items) {
+        // one wave per item; the objective has a slot per possible item, and
+        // the grid is rounded up to a multiple of 8 (the items are dealt to
+        // the XCDs in groups)
         a.seg_w = d->span;
         block = dim3(64);
-        grid = dim3(d->max_items);
+        grid = dim3((d->max_items + 7) & ~7);
+        a.n_blocks = d->max_items;
         lds = d->lds;
     }
-    a.n_blocks = grid.x * grid.y;
     hipLaunchKernelGGL(kern, grid, block, lds, s, a);
     return hipGetLastError();
 }

@@ -1081,14 +1081,19 @@ __device__ __forceinline__ void em_entry(const EmArgs &a) {
         // dynamic reference pixels (rho_ref < tau) of a row from its first
         // column on, within seg_w columns of it, one per lane; the tile
         // spans the first to the last of them
-        block_id = blockIdx.x;
-        if (block_id >= *a.n_items) {
-            // past the list: this block's objective partials are zero
-            if (threadIdx.x == 0)
-                for (int it = 0; it < a.n_iters; ++it)
-                    if (a.want_obj || it == a.n_iters - 1) a.obj[(size_t)it * a.n_blocks + block_id] = 0.0;
-            return;
+        // Blocks go to the XCDs round robin (block b to XCD b % 8): the
+        // list's items (in row order) are dealt so that consecutive ones,
+        // which stage overlapping windows of a row, run on one XCD and share
+        // its L2 (the grid is a multiple of 8 and at least the list's bound).
+        const int lin = blockIdx.x, n_items = *a.n_items;
+        if (lin >= n_items && lin < a.n_blocks && threadIdx.x == 0) {
+            // the objective partials past the list are zero
+            for (int it = 0; it < a.n_iters; ++it)
+                if (a.want_obj || it == a.n_iters - 1) a.obj[(size_t)it * a.n_blocks + lin] = 0.0;
         }
+        const int per = (n_items + 7) >> 3;
+        block_id = (lin & 7) * per + (lin >> 3);
+        if ((lin >> 3) >= per || block_id >= n_items) return;
         const int4 item = a.items[block_id];
         y = item.x;
         const int first = item.y, take = max(min(item.z, 64), 1), lane = threadIdx.x;
